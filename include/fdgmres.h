@@ -1,0 +1,170 @@
+/*
+ * fdgmres.h -- C ABI of the MI355X (gfx950) FD-preconditioned flexible GMRES library.
+ *
+ * Problem (M. Tani, arXiv 1705.04384): the nonsymmetric system A u = f of eq. 3.1
+ * from B-spline collocation of the Poisson problem (eq. 2.1 with K = I, Sec. 2.2),
+ * solved by GMRES (Sec. 3) preconditioned with P, the same discretization on the
+ * unit domain: P is the Kronecker sum of eq. 2.7 (d = 2) or eq. 2.9 (d = 3), and
+ * P s = b (eq. 4.1) is solved exactly by the nonsymmetric fast diagonalization of
+ * eq. 4.7 / 4.9 from the pencil factors of eq. 4.6.
+ *
+ * Conventions used by every entry point:
+ *  - Unknowns are numbered with i_1 fastest (Sec. 2.1, after eq. 2.3): a vector of
+ *    length N = n_1 n_2 (n_3) is the row-major array X[i_d]...[i_2][i_1].
+ *    Direction index l is 0-based here: l = 0 is i_1.
+ *  - Dense matrices are row-major: F[i*n + j] = (F)_{ij}.
+ *  - Every function returns an int status (fdg_status); nothing else crosses the ABI
+ *    as an error.  A negative value is an error and leaves outputs unspecified.
+ *    fdg_last_error() gives a message for the most recent error in the calling thread.
+ *  - "host" pointers are ordinary CPU memory, read during the call and never kept.
+ *    "device" pointers are HIP device memory (e.g. a torch tensor's data_ptr()),
+ *    owned by the caller; calls on a context are ordered on the context's HIP stream
+ *    and device inputs must not alias device outputs.
+ *  - A context is not thread-safe; use one context per thread/stream.
+ */
+#ifndef FDGMRES_H
+#define FDGMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FDG_OK = 0,
+  FDG_NOT_CONVERGED = 1,  /* solve ran out of iterations; x holds the last iterate        */
+  FDG_EINVAL = -1,        /* bad argument (size, pointer, malformed CSR, non-finite data)   */
+  FDG_ENOMEM = -2,        /* device allocation failed                                      */
+  FDG_EHIP = -3,          /* a HIP runtime call failed                                     */
+  FDG_ECOMPLEX = -4,      /* pencil eigenvalues not real and positive (Remark 1 violated)  */
+  FDG_ENOTREADY = -5,     /* factors or operator missing for the requested call            */
+  FDG_ENOCONV = -6        /* host eigen-iteration did not converge                         */
+} fdg_status;
+
+typedef enum {
+  FDG_PREC_FP64 = 0,      /* P^{-1} in FP64 (exact up to rounding)                          */
+  FDG_PREC_FP32 = 1,      /* factors and mode products in FP32                              */
+  FDG_PREC_BF16 = 2       /* BF16 factors and inputs, FP32 accumulation and intermediates   */
+} fdg_prec;
+
+enum {
+  FDG_SOLVE_USE_X0 = 1,       /* start from the x passed in instead of 0                     */
+  FDG_SOLVE_FIXED_ITERS = 2   /* run exactly maxit inner iterations, ignore rtol in a cycle  */
+};
+
+typedef struct {
+  int iterations;        /* inner (Arnoldi) iterations performed                           */
+  int restarts;          /* completed cycles                                               */
+  int converged;         /* 1 iff ||b - A x|| <= rtol ||b||                                 */
+  int breakdown;         /* 1 if the last cycle ended on h_{j+1,j} <= 1e-14 ||A z_j||       */
+  double rel_res_est;    /* |g_{j+1}| / ||b|| after the last iteration                      */
+  double rel_res_true;   /* ||b - A x||_2 / ||b||_2, recomputed in FP64 at the end          */
+  double ms_total;       /* wall time of the call, host clock                               */
+} fdg_info;
+
+/* ------------------------------------------------------------------------------------
+ * Host-only setup.  These touch no GPU and may be called without one.
+ * ---------------------------------------------------------------------------------- */
+
+/* Univariate collocation factors of eq. 2.8 for degree p >= 1 and n >= max(p-1, 1)
+ * interior unknowns: open uniform knot vector with E = n + 2 - p spans (Sec. 2.1),
+ * Greville points of the interior functions (eq. 2.4).
+ *   M[i*n+j]  = B_j(tau_i),  K[i*n+j] = -B_j''(tau_i),  D1[i*n+j] = B_j'(tau_i)  (host, n*n)
+ *   tau[i]    = tau_i                                                             (host, n)
+ * Any output pointer may be NULL.  Errors: FDG_EINVAL for bad p, n. */
+int fdg_colloc_factors(int p, int n, double *M, double *K, double *D1, double *tau);
+
+/* Nonsymmetric FD factors of one pencil (eq. 4.6 and the definition of V after it):
+ * K U = M U diag(lambda), V = (M U)^{-T}.  Eigenvalues ascending, columns of U of unit
+ * 2-norm.  K, M: host n*n input; U, V: host n*n output; lambda: host n output.
+ * cond_u (may be NULL) receives the 1-norm condition number of U.
+ * Errors: FDG_EINVAL (bad n, singular M or M U), FDG_ECOMPLEX (an eigenvalue with a
+ * relative imaginary part above 1e-10 or a non-positive real part), FDG_ENOCONV. */
+int fdg_factor_pencil(int n, const double *K, const double *M,
+                      double *U, double *V, double *lambda, double *cond_u);
+
+/* Collocation matrix of -Laplace on the deformed cube F([0,1]^3) with
+ * F_a(xi) = xi_a + amp sin(2 pi xi_{a+1}) sin(2 pi xi_{a+2}) (cyclic a), degree p,
+ * n unknowns per direction, in CSR (rows = collocation points, i_1 fastest).
+ * The general-geometry matrix of Sec. 2.2 is built from the chain rule
+ *   -Lap u = -sum_kl C_kl d_k d_l u^ - sum_k g_k d_k u^,  C = J^{-1}J^{-T},
+ *   g = -J^{-1} sum_lm (d_l d_m F) C_lm.
+ * band = 0 stores the true pattern (B-splines whose support holds the point);
+ * band = 1 stores every column with |j_l - i_l| <= p in each direction (explicit zeros
+ * included: the (2p+1)^3 stencil).
+ * Call with rowptr/col/val NULL to get *nnz; then pass arrays of n^3+1, *nnz, *nnz. */
+int fdg_deformed_csr(int p, int n, double amp, int band, int64_t *nnz,
+                     int64_t *rowptr, int32_t *col, double *val);
+
+/* f = d pi^2 prod_l sin(pi tau_{i_l}) on the unit domain (u = prod sin(pi x_l)),
+ * i_1 fastest.  tau: host n; f: host n^d. */
+int fdg_manufactured_rhs(int d, int n, const double *tau, double *f);
+
+/* ------------------------------------------------------------------------------------
+ * Device context.
+ * ---------------------------------------------------------------------------------- */
+typedef struct fdg_ctx fdg_ctx;
+
+/* d in {2, 3}; n[l] the unknowns in direction l (all equal, 1 <= n <= 1024);
+ * batch >= 1 independent same-shape problems stored back to back (vector length
+ * batch * N); hip_stream a hipStream_t (NULL = default stream) on which all work of
+ * the context is ordered.  Uses the current HIP device. */
+int fdg_create(fdg_ctx **ctx, int d, const int32_t *n, int batch, void *hip_stream);
+int fdg_destroy(fdg_ctx *ctx);
+
+/* Preconditioner factors of direction l (eq. 4.6): U, V host n*n row-major, lambda host
+ * n, all real.  Copied to the device (FP64, plus FP32/BF16 copies, rounded to nearest
+ * even).  Errors: FDG_EINVAL (bad l, non-finite), FDG_ECOMPLEX (some sum of eigenvalues
+ * over the directions could be <= 0 -- checked once all directions are set). */
+int fdg_set_prec_factors(fdg_ctx *ctx, int l, const double *U, const double *V,
+                         const double *lambda);
+
+/* Arithmetic of the P^{-1} mode products (default FDG_PREC_FP64). */
+int fdg_set_precision(fdg_ctx *ctx, int prec);
+
+/* Operator A = unit-domain Kronecker sum (eq. 2.7 / 2.9) with factors M_l, K_l of
+ * direction l: host n*n row-major, banded (stored by their row bands). */
+int fdg_set_operator_kron(fdg_ctx *ctx, int l, const double *M, const double *K);
+
+/* Operator A as a host CSR matrix of N rows (the same for every batch entry):
+ * rowptr[N+1] (int64, rowptr[0] = 0, non-decreasing), col[nnz] (int32 in [0, N)),
+ * val[nnz] (finite).  Copied to the device as a slot-major ELL matrix. */
+int fdg_set_operator_csr(fdg_ctx *ctx, int64_t nrows, int64_t nnz, const int64_t *rowptr,
+                         const int32_t *col, const double *val);
+
+/* s = P^{-1} b (eq. 4.7 / 4.9) for every batch entry.  b, s: device, batch*N FP64. */
+int fdg_apply_prec(fdg_ctx *ctx, const double *b, double *s);
+
+/* y = A x for every batch entry.  x, y: device, batch*N FP64. */
+int fdg_matvec(fdg_ctx *ctx, const double *x, double *y);
+
+/* Right-preconditioned flexible GMRES(restart) for A x = b, batch must be 1.
+ * b, x: device, N FP64.  x0 = 0 unless flags has FDG_SOLVE_USE_X0.  Each cycle runs
+ * classical Gram-Schmidt with one reorthogonalisation, Givens rotations in FP64 on the
+ * host, x += Z y at its end and a true FP64 residual; converged iff
+ * ||b - A x|| <= rtol ||b||.  With FDG_SOLVE_FIXED_ITERS exactly maxit iterations run.
+ * Blocks until done.  Returns FDG_OK, FDG_NOT_CONVERGED, or an error.
+ * info may be NULL. */
+int fdg_solve(fdg_ctx *ctx, const double *b, double *x, double rtol, int restart,
+              int maxit, int flags, fdg_info *info);
+
+/* Device bytes a context of this shape needs for a solve with the given restart
+ * (factors, operator excluded for CSR, Krylov bases, scratch). */
+size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart);
+
+/* Per-kernel timing with HIP events recorded on the context stream around every launch
+ * of the named kernel class while enabled.  kernel: 0 = FD mode-product passes,
+ * 1 = operator matvec, 2 = Krylov vector kernels.  fdg_timer_read returns the number of
+ * timed launches and their summed duration in milliseconds, and resets the timer. */
+int fdg_timer_enable(fdg_ctx *ctx, int kernel, int enable);
+int fdg_timer_read(fdg_ctx *ctx, int kernel, int64_t *launches, double *total_ms);
+
+const char *fdg_status_str(int status);
+const char *fdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDGMRES_H */

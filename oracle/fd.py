@@ -35,9 +35,52 @@ def factor_pencil(K, M):
     order = np.argsort(lam, kind="stable")
     lam = lam[order]
     U = U[:, order]
+    U = _cluster_eigenvectors(K, M, lam, U)
     U = U / np.linalg.norm(U, axis=0)
     V = np.linalg.inv(M @ U).T
     return U, V, lam
+
+
+def _cluster_eigenvectors(K, M, lam, U, rel=1e-8):
+    """Eigenvectors for clusters of (numerically) equal eigenvalues.
+
+    Remark 1 notes an outlier eigenvalue of algebraic multiplicity two and assumes the
+    pencil is diagonalizable; the two outlier modes live at opposite ends of the
+    interval and their eigenvalues agree to rounding once n is moderate, where the
+    QZ eigenvector step may return one vector twice.  For each cluster of eigenvalues
+    within rel * max|lam| of each other, the columns are replaced by an orthonormal
+    basis of the cluster's invariant subspace of M^{-1} K (ordered real Schur form),
+    combined by the eigenvectors of the cluster's Schur block when that block is not a
+    multiple of the identity.  A cluster whose block is far from diagonalizable is
+    rejected."""
+    tol = rel * np.max(np.abs(lam))
+    n = len(lam)
+    i = 0
+    A = None
+    while i < n:
+        j = i + 1
+        while j < n and lam[j] - lam[j - 1] <= tol:
+            j += 1
+        k = j - i
+        if k > 1:
+            if A is None:
+                A = np.linalg.solve(M, K)
+            lo, hi = lam[i] - tol, lam[j - 1] + tol
+            T, Z, sdim = sla.schur(A, output="real", sort=lambda re, im: (re >= lo) & (re <= hi))
+            if sdim != k:
+                raise ComplexPencilError("eigenvalue cluster not separable")
+            T11 = T[:k, :k]
+            off = np.abs(np.triu(T11, 1)).max()
+            if off <= 1e-10 * np.abs(lam[i]):
+                W = np.eye(k)
+            else:
+                w, W = np.linalg.eig(T11)
+                if np.max(np.abs(w.imag)) > 0 or np.linalg.cond(W) > 1e8:
+                    raise ComplexPencilError("eigenvalue cluster is not diagonalizable")
+                W = W[:, np.argsort(w.real)].real
+            U[:, i:j] = Z[:, :k] @ W
+        i = j
+    return U
 
 
 def mode_product(X, A, l):

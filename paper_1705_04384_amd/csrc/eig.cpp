@@ -1,0 +1,412 @@
+// Host FP64 factorisation of one univariate pencil for the nonsymmetric FD method.
+//
+// eq. 4.6: M^{-1} K U = U D with D real (Remark 1), then V = (M U)^{-T} (the definition
+// right after eq. 4.6), so that M = V^{-T} U^{-1} and K = V^{-T} D U^{-1}.
+//
+// Method (no LAPACK in the image): A = M^{-1} K by LU with partial pivoting, Householder
+// reduction to upper Hessenberg form, Francis implicit double-shift QR iterations to
+// a real Schur form T = Z^T A Z (accumulating Z), 2x2 blocks with real eigenvalues split
+// by a rotation; eigenvectors of the triangular T by back-substitution; U = Z Y.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+
+namespace fdg {
+namespace {
+
+struct Mat {
+  int n;
+  std::vector<double> a;
+  explicit Mat(int n_) : n(n_), a((size_t)n_ * n_, 0.0) {}
+  double &operator()(int i, int j) { return a[(size_t)i * n + j]; }
+  double operator()(int i, int j) const { return a[(size_t)i * n + j]; }
+};
+
+// LU with partial pivoting in place; piv[i] = row swapped with i.  Returns false if singular.
+bool lu_factor(Mat &A, std::vector<int> &piv) {
+  const int n = A.n;
+  piv.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::fabs(A(k, k));
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A(i, k)) > best) { best = std::fabs(A(i, k)); p = i; }
+    piv[k] = p;
+    if (best == 0.0 || !std::isfinite(best)) return false;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(A(k, j), A(p, j));
+    const double inv = 1.0 / A(k, k);
+    for (int i = k + 1; i < n; ++i) {
+      const double l = A(i, k) * inv;
+      A(i, k) = l;
+      if (l != 0.0)
+        for (int j = k + 1; j < n; ++j) A(i, j) -= l * A(k, j);
+    }
+  }
+  return true;
+}
+
+// Solves LU X = B in place for B (n x nrhs, row-major).
+void lu_solve(const Mat &LU, const std::vector<int> &piv, std::vector<double> &B, int nrhs) {
+  const int n = LU.n;
+  for (int k = 0; k < n; ++k)
+    if (piv[k] != k)
+      for (int c = 0; c < nrhs; ++c) std::swap(B[(size_t)k * nrhs + c], B[(size_t)piv[k] * nrhs + c]);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < i; ++k) {
+      const double l = LU(i, k);
+      if (l != 0.0)
+        for (int c = 0; c < nrhs; ++c) B[(size_t)i * nrhs + c] -= l * B[(size_t)k * nrhs + c];
+    }
+  for (int i = n - 1; i >= 0; --i) {
+    for (int k = i + 1; k < n; ++k) {
+      const double u = LU(i, k);
+      if (u != 0.0)
+        for (int c = 0; c < nrhs; ++c) B[(size_t)i * nrhs + c] -= u * B[(size_t)k * nrhs + c];
+    }
+    const double inv = 1.0 / LU(i, i);
+    for (int c = 0; c < nrhs; ++c) B[(size_t)i * nrhs + c] *= inv;
+  }
+}
+
+// Householder reduction to upper Hessenberg form, H = Z^T A Z, Z accumulated.
+void hessenberg(Mat &H, Mat &Z) {
+  const int n = H.n;
+  std::vector<double> v(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    double alpha = 0.0;
+    for (int i = k + 1; i < n; ++i) alpha += H(i, k) * H(i, k);
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    if (H(k + 1, k) > 0) alpha = -alpha;
+    // v = x - alpha e1 on rows k+1..n-1
+    for (int i = 0; i < n; ++i) v[i] = 0.0;
+    v[k + 1] = H(k + 1, k) - alpha;
+    for (int i = k + 2; i < n; ++i) v[i] = H(i, k);
+    double vv = 0.0;
+    for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    // left: H = (I - beta v v^T) H on rows k+1.., columns k..
+    for (int j = k; j < n; ++j) {
+      double s = 0.0;
+      for (int i = k + 1; i < n; ++i) s += v[i] * H(i, j);
+      s *= beta;
+      for (int i = k + 1; i < n; ++i) H(i, j) -= s * v[i];
+    }
+    // right: H = H (I - beta v v^T) on all rows, columns k+1..
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += H(i, j) * v[j];
+      s *= beta;
+      for (int j = k + 1; j < n; ++j) H(i, j) -= s * v[j];
+    }
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += Z(i, j) * v[j];
+      s *= beta;
+      for (int j = k + 1; j < n; ++j) Z(i, j) -= s * v[j];
+    }
+    H(k + 1, k) = alpha;
+    for (int i = k + 2; i < n; ++i) H(i, k) = 0.0;
+  }
+}
+
+// Applies the reflector I - beta v v^T (v of length m at rows/cols r0..r0+m-1) to H
+// from both sides within the given ranges, and to Z from the right.
+void apply_reflector(Mat &H, Mat &Z, int r0, int m, const double *v, double beta, int col_lo,
+                     int row_hi) {
+  const int n = H.n;
+  for (int j = col_lo; j < n; ++j) {
+    double s = 0.0;
+    for (int t = 0; t < m; ++t) s += v[t] * H(r0 + t, j);
+    s *= beta;
+    for (int t = 0; t < m; ++t) H(r0 + t, j) -= s * v[t];
+  }
+  for (int i = 0; i <= row_hi; ++i) {
+    double s = 0.0;
+    for (int t = 0; t < m; ++t) s += H(i, r0 + t) * v[t];
+    s *= beta;
+    for (int t = 0; t < m; ++t) H(i, r0 + t) -= s * v[t];
+  }
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int t = 0; t < m; ++t) s += Z(i, r0 + t) * v[t];
+    s *= beta;
+    for (int t = 0; t < m; ++t) Z(i, r0 + t) -= s * v[t];
+  }
+}
+
+// Reflector mapping x (length m) to a multiple of e1: returns beta, fills v.
+double make_reflector(const double *x, int m, double *v) {
+  double nrm = 0.0;
+  for (int t = 0; t < m; ++t) nrm += x[t] * x[t];
+  nrm = std::sqrt(nrm);
+  if (nrm == 0.0) {
+    for (int t = 0; t < m; ++t) v[t] = 0.0;
+    return 0.0;
+  }
+  const double alpha = x[0] > 0 ? -nrm : nrm;
+  v[0] = x[0] - alpha;
+  for (int t = 1; t < m; ++t) v[t] = x[t];
+  double vv = 0.0;
+  for (int t = 0; t < m; ++t) vv += v[t] * v[t];
+  return vv == 0.0 ? 0.0 : 2.0 / vv;
+}
+
+// Rotates the 2x2 diagonal block at (p, p+1), whose eigenvalues are real, to upper
+// triangular form.  Returns false if the block's eigenvalues are genuinely complex.
+bool split_block(Mat &H, Mat &Z, int p, double *ev0, double *ev1) {
+  const int n = H.n, q = p + 1;
+  const double a = H(p, p), b = H(p, q), c = H(q, p), d = H(q, q);
+  const double half = 0.5 * (a - d);
+  double disc = half * half + b * c;
+  const double scale = std::fabs(a) + std::fabs(d) + std::fabs(b) + std::fabs(c);
+  if (disc < 0.0) {
+    if (std::sqrt(-disc) > 1e-10 * scale) return false;
+    disc = 0.0;
+  }
+  const double r = std::sqrt(disc);
+  const double mid = 0.5 * (a + d);
+  // eigenvalue of larger distance from d first, computed without cancellation
+  const double lam = half >= 0 ? mid + r : mid - r;
+  // eigenvector (b, lam - a) or (lam - d, c), whichever is larger
+  double x0 = b, x1 = lam - a;
+  const double y0 = lam - d, y1 = c;
+  if (std::hypot(y0, y1) > std::hypot(x0, x1)) { x0 = y0; x1 = y1; }
+  const double nv = std::hypot(x0, x1);
+  double cs = 1.0, sn = 0.0;
+  if (nv > 0.0) { cs = x0 / nv; sn = x1 / nv; }
+  // Q2 = [[cs, -sn], [sn, cs]];  H <- Q2^T H Q2 on rows/cols p, q
+  for (int j = p; j < n; ++j) {
+    const double h0 = H(p, j), h1 = H(q, j);
+    H(p, j) = cs * h0 + sn * h1;
+    H(q, j) = -sn * h0 + cs * h1;
+  }
+  for (int i = 0; i <= q; ++i) {
+    const double h0 = H(i, p), h1 = H(i, q);
+    H(i, p) = cs * h0 + sn * h1;
+    H(i, q) = -sn * h0 + cs * h1;
+  }
+  for (int i = 0; i < n; ++i) {
+    const double z0 = Z(i, p), z1 = Z(i, q);
+    Z(i, p) = cs * z0 + sn * z1;
+    Z(i, q) = -sn * z0 + cs * z1;
+  }
+  H(q, p) = 0.0;
+  *ev0 = H(p, p);
+  *ev1 = H(q, q);
+  return true;
+}
+
+// Francis double-shift QR on the Hessenberg H to upper-triangular form (real spectrum).
+int schur_real(Mat &H, Mat &Z, std::vector<double> &ev) {
+  const int n = H.n;
+  const double eps = 2.220446049250313e-16;
+  double anorm = 0.0;
+  for (double x : H.a) anorm = std::max(anorm, std::fabs(x));
+  if (anorm == 0.0) anorm = 1.0;
+  ev.assign(n, 0.0);
+  int hi = n - 1;
+  int iter = 0, total = 0;
+  const int max_total = 60 * std::max(n, 10);
+  double v[3];
+  while (hi >= 0) {
+    int l = hi;
+    for (; l > 0; --l) {
+      double s = std::fabs(H(l - 1, l - 1)) + std::fabs(H(l, l));
+      if (s == 0.0) s = anorm;
+      if (std::fabs(H(l, l - 1)) <= eps * s) {
+        H(l, l - 1) = 0.0;
+        break;
+      }
+    }
+    if (l == hi) {
+      ev[hi] = H(hi, hi);
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (l == hi - 1) {
+      double e0, e1;
+      if (!split_block(H, Z, hi - 1, &e0, &e1))
+        return set_error(FDG_ECOMPLEX, "factor_pencil: complex eigenvalue pair");
+      ev[hi - 1] = e0;
+      ev[hi] = e1;
+      hi -= 2;
+      iter = 0;
+      continue;
+    }
+    if (++total > max_total) return set_error(FDG_ENOCONV, "factor_pencil: QR iteration did not converge");
+    ++iter;
+    double s, t;
+    if (iter % 11 == 10) {  // exceptional shift against stagnation
+      const double w = std::fabs(H(hi, hi - 1)) + std::fabs(H(hi - 1, hi - 2));
+      s = 1.5 * w + H(hi, hi);
+      t = w * w;
+    } else {
+      s = H(hi - 1, hi - 1) + H(hi, hi);
+      t = H(hi - 1, hi - 1) * H(hi, hi) - H(hi - 1, hi) * H(hi, hi - 1);
+    }
+    double x = H(l, l) * H(l, l) + H(l, l + 1) * H(l + 1, l) - s * H(l, l) + t;
+    double y = H(l + 1, l) * (H(l, l) + H(l + 1, l + 1) - s);
+    double z = H(l + 1, l) * H(l + 2, l + 1);
+    for (int k = l; k <= hi - 2; ++k) {
+      const double xv[3] = {x, y, z};
+      const double beta = make_reflector(xv, 3, v);
+      if (beta != 0.0) {
+        apply_reflector(H, Z, k, 3, v, beta, std::max(l, k - 1), std::min(k + 3, hi));
+        if (k > l) {
+          H(k + 1, k - 1) = 0.0;
+          H(k + 2, k - 1) = 0.0;
+        }
+      }
+      x = H(k + 1, k);
+      y = H(k + 2, k);
+      if (k < hi - 2) z = H(k + 3, k);
+    }
+    const double xv[2] = {x, y};
+    const double beta = make_reflector(xv, 2, v);
+    if (beta != 0.0) {
+      apply_reflector(H, Z, hi - 1, 2, v, beta, std::max(l, hi - 2), hi);
+      if (hi - 2 >= l) H(hi, hi - 2) = 0.0;
+    }
+  }
+  return FDG_OK;
+}
+
+}  // namespace
+}  // namespace fdg
+
+using namespace fdg;
+
+extern "C" int fdg_factor_pencil(int n, const double *K, const double *M, double *U, double *V,
+                                 double *lambda, double *cond_u) {
+  clear_error();
+  if (n < 1 || n > 4096 || !K || !M || !U || !V || !lambda)
+    return set_error(FDG_EINVAL, "factor_pencil: bad arguments (n=%d)", n);
+  const size_t nn = (size_t)n * n;
+  for (size_t i = 0; i < nn; ++i)
+    if (!std::isfinite(K[i]) || !std::isfinite(M[i]))
+      return set_error(FDG_EINVAL, "factor_pencil: non-finite input");
+  // A = M^{-1} K
+  Mat LU(n);
+  std::memcpy(LU.a.data(), M, nn * sizeof(double));
+  std::vector<int> piv;
+  if (!lu_factor(LU, piv)) return set_error(FDG_EINVAL, "factor_pencil: M is singular");
+  std::vector<double> A(K, K + nn);
+  lu_solve(LU, piv, A, n);
+  Mat H(n), Z(n);
+  H.a = A;
+  for (int i = 0; i < n; ++i) Z(i, i) = 1.0;
+  hessenberg(H, Z);
+  std::vector<double> ev;
+  int st = schur_real(H, Z, ev);
+  if (st != FDG_OK) return st;
+  double emax = 0.0;
+  for (double e : ev) emax = std::max(emax, std::fabs(e));
+  for (double e : ev)
+    if (!(e > 0.0)) return set_error(FDG_ECOMPLEX, "factor_pencil: non-positive eigenvalue %g", e);
+  // eigenvectors of the upper-triangular T = H by back-substitution
+  const double ulp = 2.220446049250313e-16;
+  Mat Y(n);
+  for (int k = n - 1; k >= 0; --k) {
+    const double lk = H(k, k);
+    const double smin = std::max(ulp * std::fabs(lk), 1e-300);
+    Y(k, k) = 1.0;
+    for (int i = k - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int j = i + 1; j <= k; ++j) s += H(i, j) * Y(j, k);
+      double den = H(i, i) - lk;
+      double y;
+      if (std::fabs(den) < smin) {
+        // equal eigenvalues (the double outlier of Remark 1): when the coupling is at
+        // rounding level the Schur vector itself is an eigenvector of the cluster;
+        // otherwise perturb the divisor as for nearby eigenvalues.
+        double ymax = 0.0;
+        for (int j = i + 1; j <= k; ++j) ymax = std::max(ymax, std::fabs(Y(j, k)));
+        if (std::fabs(s) <= 1e-10 * std::fabs(lk) * ymax) {
+          y = 0.0;
+        } else {
+          den = den >= 0 ? smin : -smin;
+          y = -s / den;
+        }
+      } else {
+        y = -s / den;
+      }
+      Y(i, k) = y;
+      if (std::fabs(y) > 1e150) {  // rescale the partial vector
+        for (int j = i; j <= k; ++j) Y(j, k) *= 1e-150;
+      }
+    }
+  }
+  // U = Z Y, unit columns, eigenvalues ascending
+  Mat Uz(n);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      double s = 0.0;
+      for (int j = 0; j <= k; ++j) s += Z(i, j) * Y(j, k);
+      Uz(i, k) = s;
+    }
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ev[a] < ev[b]; });
+  for (int c = 0; c < n; ++c) {
+    const int k = order[c];
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) nrm += Uz(i, k) * Uz(i, k);
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return set_error(FDG_ENOCONV, "factor_pencil: degenerate eigenvector");
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + c] = Uz(i, k) / nrm;
+    lambda[c] = ev[k];
+  }
+  // V = (M U)^{-T}
+  Mat MU(n);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double m = M[(size_t)i * n + j];
+        if (m != 0.0) s += m * U[(size_t)j * n + k];
+      }
+      MU(i, k) = s;
+    }
+  std::vector<int> piv2;
+  if (!lu_factor(MU, piv2)) return set_error(FDG_EINVAL, "factor_pencil: M U is singular");
+  std::vector<double> inv(nn, 0.0);
+  for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+  lu_solve(MU, piv2, inv, n);  // inv = (M U)^{-1}
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) V[(size_t)i * n + k] = inv[(size_t)k * n + i];
+  if (cond_u) {
+    Mat LUu(n);
+    std::memcpy(LUu.a.data(), U, nn * sizeof(double));
+    std::vector<int> p3;
+    double c1 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += std::fabs(U[(size_t)i * n + k]);
+      c1 = std::max(c1, s);
+    }
+    if (!lu_factor(LUu, p3)) {
+      *cond_u = INFINITY;
+    } else {
+      std::vector<double> ui(nn, 0.0);
+      for (int i = 0; i < n; ++i) ui[(size_t)i * n + i] = 1.0;
+      lu_solve(LUu, p3, ui, n);
+      double c2 = 0.0;
+      for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += std::fabs(ui[(size_t)i * n + k]);
+        c2 = std::max(c2, s);
+      }
+      *cond_u = c1 * c2;
+    }
+  }
+  (void)emax;
+  return FDG_OK;
+}

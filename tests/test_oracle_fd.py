@@ -63,7 +63,7 @@ def test_kronecker_identity(d, p, n):
     assert np.linalg.norm(P @ s - v) <= 1e-12 * np.linalg.norm(v)
 
 
-@pytest.mark.parametrize("p,n", [(2, 16), (3, 33), (4, 64), (5, 40), (6, 48)])
+@pytest.mark.parametrize("p,n", [(2, 16), (3, 33), (4, 64), (5, 40), (6, 48), (3, 96), (4, 128), (6, 192)])
 def test_remark1_real_positive_wellconditioned(p, n):
     M, K, _, _ = colloc.colloc_factors(p, n)
     U, V, lam = fd.factor_pencil(K, M)
@@ -80,6 +80,18 @@ def test_low_eigenvalues_approach_dirichlet_laplacian():
     _, _, lam = fd.factor_pencil(K, M)
     for k in range(1, 4):
         assert abs(lam[k - 1] - (k * np.pi) ** 2) <= 1e-6 * (k * np.pi) ** 2
+
+
+@pytest.mark.parametrize("p,n", [(3, 96), (4, 128)])
+def test_double_outlier_kronecker_identity(p, n):
+    """Where the two outlier eigenvalues coincide to rounding, P^{-1} is still exact (2D)."""
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    U, V, lam = fd.factor_pencil(K, M)
+    assert lam[-1] - lam[-2] <= 1e-12 * lam[-1]
+    P = colloc.unit_operator([M] * 2, [K] * 2)
+    v = np.random.default_rng(3).standard_normal(n * n)
+    s = fd.fd_apply([U] * 2, [V] * 2, [lam] * 2, v)
+    assert np.linalg.norm(P @ s - v) <= 1e-12 * np.linalg.norm(v)
 
 
 def test_outlier_eigenvalue_pair():
