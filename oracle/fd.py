@@ -41,7 +41,7 @@ def factor_pencil(K, M):
     return U, V, lam
 
 
-def _cluster_eigenvectors(K, M, lam, U, rel=1e-8):
+def _cluster_eigenvectors(K, M, lam, U, rel=1e-10):
     """Eigenvectors for clusters of (numerically) equal eigenvalues.
 
     Remark 1 notes an outlier eigenvalue of algebraic multiplicity two and assumes the
@@ -50,8 +50,9 @@ def _cluster_eigenvectors(K, M, lam, U, rel=1e-8):
     QZ eigenvector step may return one vector twice.  For each cluster of eigenvalues
     within rel * max|lam| of each other, the columns are replaced by an orthonormal
     basis of the cluster's invariant subspace of M^{-1} K (ordered real Schur form),
-    combined by the eigenvectors of the cluster's Schur block when that block is not a
-    multiple of the identity.  A cluster whose block is far from diagonalizable is
+    combined by the eigenvectors of the cluster's Schur block unless that block is a
+    multiple of the identity to rounding.  Pairs that are merely close (the gap well
+    above rounding) keep their QZ eigenvectors, which are accurate there.  A cluster whose block is far from diagonalizable is
     rejected."""
     tol = rel * np.max(np.abs(lam))
     n = len(lam)
@@ -70,8 +71,8 @@ def _cluster_eigenvectors(K, M, lam, U, rel=1e-8):
             if sdim != k:
                 raise ComplexPencilError("eigenvalue cluster not separable")
             T11 = T[:k, :k]
-            off = np.abs(np.triu(T11, 1)).max()
-            if off <= 1e-10 * np.abs(lam[i]):
+            spread = np.abs(T11 - np.mean(np.diag(T11)) * np.eye(k)).max()
+            if spread <= 1e-12 * np.abs(lam[i]):        # a scalar block to rounding
                 W = np.eye(k)
             else:
                 w, W = np.linalg.eig(T11)

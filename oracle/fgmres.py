@@ -10,7 +10,9 @@ Readings fixed here:
 * Givens rotations r = hypot(a, b), c = a / r, s = b / r on the Hessenberg
   columns, residual estimate |g_{j+1}|;
 * a cycle stops when |g_{j+1}| <= rtol ||b||, on lucky breakdown
-  (h_{j+1,j} <= 1e-14 ||A z_j||), at the restart length, or at maxit;
+  (h_{j+1,j} <= 1e-14 ||A z_j||, with ||A z_j|| taken as the 2-norm of the
+  Hessenberg column, equal to it because the basis is orthonormal), at the
+  restart length, or at maxit;
 * at the end of a cycle x += Z y (back-substitution) and the true residual
   ||b - A x|| decides convergence; otherwise the next cycle restarts from x.
 """
@@ -62,7 +64,6 @@ def fgmres(matvec, prec, b, rtol=1e-8, restart=30, maxit=1000, x0=None, iters=No
         for j in range(m):
             Z[j] = prec(V[j])
             w = matvec(Z[j])
-            wnorm0 = np.linalg.norm(w)
             h1 = V[:j + 1] @ w
             w = w - V[:j + 1].T @ h1
             h2 = V[:j + 1] @ w
@@ -70,6 +71,7 @@ def fgmres(matvec, prec, b, rtol=1e-8, restart=30, maxit=1000, x0=None, iters=No
             H[:j + 1, j] = h1 + h2
             hn = np.linalg.norm(w)
             H[j + 1, j] = hn
+            wnorm0 = np.linalg.norm(H[:j + 2, j])    # = ||A z_j|| (V orthonormal)
             for i in range(j):                      # previous rotations
                 a, c = H[i, j], H[i + 1, j]
                 H[i, j] = cs[i] * a + sn[i] * c

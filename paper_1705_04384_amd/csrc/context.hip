@@ -1,0 +1,700 @@
+// Device context of the C ABI: factor and operator upload, the preconditioner apply
+// (eq. 4.7 / 4.9), the operator matvec, and the flexible GMRES driver (Sec. 3) whose
+// Givens least-squares update runs in FP64 on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "modeprod.h"
+
+using namespace fdg;
+
+namespace {
+
+constexpr int kTimerClasses = 3;
+
+struct TimerState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;     // free events
+  std::vector<hipEvent_t> pending;  // start, stop, start, stop, ...
+};
+
+}  // namespace
+
+struct fdg_ctx {
+  int d = 0, n = 0, batch = 1, device = 0;
+  int64_t N = 0;
+  hipStream_t stream = nullptr;
+  int prec = FDG_PREC_FP64;
+  // preconditioner factors, zero-padded ldw x ldw
+  int ldw = 0;
+  bool have_factor[3] = {false, false, false};
+  double *Wv[3] = {nullptr, nullptr, nullptr};  // V_l^T: Y = W X applies V_l^T along mode l
+  double *Wu[3] = {nullptr, nullptr, nullptr};  // U_l
+  double *lam[3] = {nullptr, nullptr, nullptr};
+  float *Wv32[3] = {nullptr, nullptr, nullptr}, *Wu32[3] = {nullptr, nullptr, nullptr};
+  uint16_t *Wv16[3] = {nullptr, nullptr, nullptr}, *Wu16[3] = {nullptr, nullptr, nullptr};
+  float *lam32[3] = {nullptr, nullptr, nullptr};
+  double lam_min[3] = {0, 0, 0};
+  // operator
+  int op_kind = 0;  // 0 none, 1 Kronecker bands, 2 ELL
+  bool have_op[3] = {false, false, false};
+  double *bandM[3] = {nullptr, nullptr, nullptr}, *bandK[3] = {nullptr, nullptr, nullptr};
+  int32_t *bandlo[3] = {nullptr, nullptr, nullptr};
+  int bandw[3] = {0, 0, 0};
+  int32_t *ell_col = nullptr;
+  double *ell_val = nullptr;
+  int ell_width = 0;
+  // workspace
+  double *t1 = nullptr, *t2 = nullptr;
+  void *t32a = nullptr, *t32b = nullptr;
+  int restart_alloc = 0;
+  double *Vb = nullptr, *Zb = nullptr, *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *Hcol = nullptr,
+         *ydev = nullptr;
+  double *hpin = nullptr;  // pinned host staging
+  TimerState timers[kTimerClasses];
+};
+
+namespace {
+
+int hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return FDG_OK;
+  if (e == hipErrorOutOfMemory) return set_error(FDG_ENOMEM, "%s: out of device memory", what);
+  return set_error(FDG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                  \
+  do {                                                \
+    int _st = hip_check((call), #call);               \
+    if (_st != FDG_OK) return _st;                    \
+  } while (0)
+
+template <typename T>
+int dalloc(T **p, size_t count) {
+  if (*p) return FDG_OK;
+  return hip_check(hipMalloc((void **)p, count * sizeof(T) + 256), "hipMalloc");
+}
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+// Brackets one launch of timer class c with events when that timer is on.
+struct TimedLaunch {
+  fdg_ctx *ctx;
+  int c;
+  hipEvent_t stop = nullptr;
+  TimedLaunch(fdg_ctx *x, int cls) : ctx(x), c(cls) {
+    TimerState &t = ctx->timers[c];
+    if (!t.on) return;
+    hipEvent_t a, b;
+    if (t.pool.size() >= 2) {
+      a = t.pool.back(); t.pool.pop_back();
+      b = t.pool.back(); t.pool.pop_back();
+    } else {
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    }
+    (void)hipEventRecord(a, ctx->stream);
+    t.pending.push_back(a);
+    stop = b;
+  }
+  ~TimedLaunch() {
+    if (!stop) return;
+    (void)hipEventRecord(stop, ctx->stream);
+    ctx->timers[c].pending.push_back(stop);
+  }
+};
+
+bool finite_all(const double *a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+uint16_t to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan kept
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+int ensure_workspace(fdg_ctx *c) {
+  const size_t tot = (size_t)c->N * c->batch;
+  int st;
+  if ((st = dalloc(&c->t1, tot)) != FDG_OK) return st;
+  if ((st = dalloc(&c->t2, tot)) != FDG_OK) return st;
+  return FDG_OK;
+}
+
+int ensure_lowp_workspace(fdg_ctx *c) {
+  const size_t tot = (size_t)c->N * c->batch;
+  int st;
+  if ((st = dalloc((float **)&c->t32a, tot)) != FDG_OK) return st;
+  if ((st = dalloc((float **)&c->t32b, tot)) != FDG_OK) return st;
+  return FDG_OK;
+}
+
+int check_ready_prec(fdg_ctx *c) {
+  for (int l = 0; l < c->d; ++l)
+    if (!c->have_factor[l]) return set_error(FDG_ENOTREADY, "preconditioner factors of direction %d not set", l);
+  return FDG_OK;
+}
+
+int check_ready_op(fdg_ctx *c) {
+  if (c->op_kind == 1) {
+    for (int l = 0; l < c->d; ++l)
+      if (!c->have_op[l]) return set_error(FDG_ENOTREADY, "operator factors of direction %d not set", l);
+    return FDG_OK;
+  }
+  if (c->op_kind == 2) return FDG_OK;
+  return set_error(FDG_ENOTREADY, "operator not set");
+}
+
+int do_apply(fdg_ctx *c, const double *b, double *s) {
+  int st = ensure_workspace(c);
+  if (st != FDG_OK) return st;
+  if (c->prec != FDG_PREC_FP64) {
+    if ((st = ensure_lowp_workspace(c)) != FDG_OK) return st;
+    TimedLaunch tl(c, 0);
+    return fd_apply_lowp(c->stream, c->prec, c->d, c->n, c->batch, b, s, c->t32a, c->t32b,
+                         c->prec == FDG_PREC_FP32 ? (const void *const *)c->Wv32 : (const void *const *)c->Wv16,
+                         c->prec == FDG_PREC_FP32 ? (const void *const *)c->Wu32 : (const void *const *)c->Wu16,
+                         c->lam32, c->ldw);
+  }
+  const int n = c->n;
+  const int64_t B = c->batch;
+  const int64_t n2 = (int64_t)n * n;
+  auto mode = [&](const double *X, double *Y, const double *W, int l) {
+    TimedLaunch tl(c, 0);
+    if (l == 0) {
+      const int64_t rows = B * (c->d == 3 ? n2 : n);
+      launch_modeprod_f64(c->stream, X, Y, W, c->ldw, n, rows, 0, 1, n, 1);
+    } else if (l == 1) {
+      const int64_t outer = B * (c->d == 3 ? n : 1);
+      launch_modeprod_f64(c->stream, X, Y, W, c->ldw, n, n, n2, n, 1, outer);
+    } else {
+      launch_modeprod_f64(c->stream, X, Y, W, c->ldw, n, n2, n2 * n, n2, 1, B);
+    }
+  };
+  if (c->d == 3) {
+    mode(b, c->t1, c->Wv[0], 0);
+    mode(c->t1, c->t2, c->Wv[1], 1);
+    mode(c->t2, c->t1, c->Wv[2], 2);
+    {
+      TimedLaunch tl(c, 0);
+      launch_divide_f64(c->stream, c->t1, 3, n, B, c->lam[0], c->lam[1], c->lam[2]);
+    }
+    mode(c->t1, c->t2, c->Wu[0], 0);
+    mode(c->t2, c->t1, c->Wu[1], 1);
+    mode(c->t1, s, c->Wu[2], 2);
+  } else {
+    mode(b, c->t1, c->Wv[0], 0);
+    mode(c->t1, c->t2, c->Wv[1], 1);
+    {
+      TimedLaunch tl(c, 0);
+      launch_divide_f64(c->stream, c->t2, 2, n, B, c->lam[0], c->lam[1], nullptr);
+    }
+    mode(c->t2, c->t1, c->Wu[0], 0);
+    mode(c->t1, s, c->Wu[1], 1);
+  }
+  return hip_check(hipGetLastError(), "apply_prec launch");
+}
+
+int do_matvec(fdg_ctx *c, const double *x, double *y) {
+  TimedLaunch tl(c, 1);
+  if (c->op_kind == 1) {
+    KronBands bd;
+    for (int l = 0; l < 3; ++l) {
+      const int q = l < c->d ? l : 0;
+      bd.M[l] = c->bandM[q];
+      bd.K[l] = c->bandK[q];
+      bd.lo[l] = c->bandlo[q];
+      bd.w[l] = c->bandw[q];
+    }
+    launch_kron_matvec_f64(c->stream, x, y, c->d, c->n, c->batch, bd);
+  } else {
+    launch_ell_matvec_f64(c->stream, x, y, c->N, c->N, c->ell_width, c->ell_col, c->ell_val, c->batch);
+  }
+  return hip_check(hipGetLastError(), "matvec launch");
+}
+
+int ensure_krylov(fdg_ctx *c, int m) {
+  if (c->restart_alloc >= m) return FDG_OK;
+  dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol); dfree(c->ydev);
+  if (c->hpin) { (void)hipHostFree(c->hpin); c->hpin = nullptr; }
+  c->restart_alloc = 0;
+  const size_t NB = (size_t)c->N * c->batch;
+  const int G = reduction_blocks(c->N);
+  int st;
+  if ((st = dalloc(&c->Vb, NB * (m + 1))) != FDG_OK) return st;
+  if ((st = dalloc(&c->Zb, NB * m)) != FDG_OK) return st;
+  if ((st = dalloc(&c->P1, (size_t)G * (m + 1) * c->batch)) != FDG_OK) return st;
+  if ((st = dalloc(&c->P2, (size_t)G * (m + 1) * c->batch)) != FDG_OK) return st;
+  if ((st = dalloc(&c->P3, (size_t)G * c->batch)) != FDG_OK) return st;
+  if ((st = dalloc(&c->Hcol, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
+  if ((st = dalloc(&c->ydev, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
+  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * (size_t)(2 * m + 8) * c->batch, hipHostMallocDefault));
+  c->restart_alloc = m;
+  return FDG_OK;
+}
+
+int read_scalars(fdg_ctx *c, const double *dev, int count) {
+  HIPCHK(hipMemcpyAsync(c->hpin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return FDG_OK;
+}
+
+// ||v|| of a device vector (batch entry 0) into c->hpin[0].
+int device_norm(fdg_ctx *c, const double *v) {
+  const int G = reduction_blocks(c->N);
+  {
+    TimedLaunch tl(c, 2);
+    launch_dots(c->stream, v, 0, 1, v, c->N, 1, G, c->P3);
+  }
+  {
+    TimedLaunch tl(c, 2);
+    launch_finalize_norm(c->stream, c->P3, G, 1, c->Hcol);
+  }
+  return read_scalars(c, c->Hcol, 1);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------
+extern "C" int fdg_create(fdg_ctx **out, int d, const int32_t *n, int batch, void *hip_stream) {
+  clear_error();
+  if (!out || !n) return set_error(FDG_EINVAL, "create: NULL argument");
+  *out = nullptr;
+  if (d != 2 && d != 3) return set_error(FDG_EINVAL, "create: d must be 2 or 3 (got %d)", d);
+  for (int l = 0; l < d; ++l)
+    if (n[l] != n[0]) return set_error(FDG_EINVAL, "create: all directions must have the same n");
+  if (n[0] < 1 || n[0] > 1024) return set_error(FDG_EINVAL, "create: n must be in [1, 1024] (got %d)", n[0]);
+  if (batch < 1) return set_error(FDG_EINVAL, "create: batch must be >= 1");
+  const int64_t N = ipow(n[0], d);
+  if (N * (int64_t)batch > ((int64_t)1 << 40)) return set_error(FDG_EINVAL, "create: problem too large");
+  int dev = 0;
+  int st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (st != FDG_OK) return st;
+  fdg_ctx *c = new fdg_ctx();
+  c->d = d;
+  c->n = n[0];
+  c->N = N;
+  c->batch = batch;
+  c->device = dev;
+  c->stream = (hipStream_t)hip_stream;
+  c->ldw = ((n[0] + 63) / 64) * 64;
+  *out = c;
+  return FDG_OK;
+}
+
+extern "C" int fdg_destroy(fdg_ctx *c) {
+  clear_error();
+  if (!c) return FDG_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (int l = 0; l < 3; ++l) {
+    dfree(c->Wv[l]); dfree(c->Wu[l]); dfree(c->lam[l]);
+    dfree(c->Wv32[l]); dfree(c->Wu32[l]); dfree(c->Wv16[l]); dfree(c->Wu16[l]); dfree(c->lam32[l]);
+    dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandlo[l]);
+  }
+  dfree(c->ell_col); dfree(c->ell_val);
+  dfree(c->t1); dfree(c->t2);
+  if (c->t32a) (void)hipFree(c->t32a);
+  if (c->t32b) (void)hipFree(c->t32b);
+  dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol); dfree(c->ydev);
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  for (auto &t : c->timers) {
+    for (auto e : t.pool) (void)hipEventDestroy(e);
+    for (auto e : t.pending) (void)hipEventDestroy(e);
+  }
+  delete c;
+  return FDG_OK;
+}
+
+extern "C" int fdg_set_prec_factors(fdg_ctx *c, int l, const double *U, const double *V, const double *lambda) {
+  clear_error();
+  if (!c || !U || !V || !lambda) return set_error(FDG_EINVAL, "set_prec_factors: NULL argument");
+  if (l < 0 || l >= c->d) return set_error(FDG_EINVAL, "set_prec_factors: bad direction %d", l);
+  const int n = c->n, ld = c->ldw;
+  if (!finite_all(U, (size_t)n * n) || !finite_all(V, (size_t)n * n) || !finite_all(lambda, n))
+    return set_error(FDG_EINVAL, "set_prec_factors: non-finite factor");
+  double lmin = lambda[0];
+  for (int i = 1; i < n; ++i) lmin = std::min(lmin, lambda[i]);
+  std::vector<double> wv((size_t)ld * ld, 0.0), wu((size_t)ld * ld, 0.0), lm(ld, 1.0);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j) {
+      wv[(size_t)k * ld + j] = V[(size_t)j * n + k];
+      wu[(size_t)k * ld + j] = U[(size_t)k * n + j];
+    }
+  for (int i = 0; i < n; ++i) lm[i] = lambda[i];
+  int st;
+  if ((st = dalloc(&c->Wv[l], wv.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->Wu[l], wu.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->lam[l], lm.size())) != FDG_OK) return st;
+  HIPCHK(hipMemcpy(c->Wv[l], wv.data(), wv.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->Wu[l], wu.data(), wu.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->lam[l], lm.data(), lm.size() * 8, hipMemcpyHostToDevice));
+  // reduced-precision copies (rounded once, to nearest even)
+  std::vector<float> fv(wv.size()), fu(wu.size()), fl(lm.size());
+  std::vector<uint16_t> bv(wv.size()), bu(wu.size());
+  for (size_t i = 0; i < wv.size(); ++i) {
+    fv[i] = (float)wv[i];
+    fu[i] = (float)wu[i];
+    bv[i] = to_bf16_rne((float)wv[i]);
+    bu[i] = to_bf16_rne((float)wu[i]);
+  }
+  for (size_t i = 0; i < lm.size(); ++i) fl[i] = (float)lm[i];
+  if ((st = dalloc(&c->Wv32[l], fv.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->Wu32[l], fu.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->Wv16[l], bv.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->Wu16[l], bu.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->lam32[l], fl.size())) != FDG_OK) return st;
+  HIPCHK(hipMemcpy(c->Wv32[l], fv.data(), fv.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->Wu32[l], fu.data(), fu.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->Wv16[l], bv.data(), bv.size() * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->Wu16[l], bu.data(), bu.size() * 2, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->lam32[l], fl.data(), fl.size() * 4, hipMemcpyHostToDevice));
+  c->have_factor[l] = true;
+  c->lam_min[l] = lmin;
+  bool all = true;
+  double sum = 0.0;
+  for (int q = 0; q < c->d; ++q) {
+    all = all && c->have_factor[q];
+    sum += c->lam_min[q];
+  }
+  if (all && !(sum > 0.0)) {
+    c->have_factor[l] = false;
+    return set_error(FDG_ECOMPLEX, "set_prec_factors: eigenvalue sums can be <= 0");
+  }
+  return FDG_OK;
+}
+
+extern "C" int fdg_set_precision(fdg_ctx *c, int prec) {
+  clear_error();
+  if (!c) return set_error(FDG_EINVAL, "set_precision: NULL context");
+  if (prec != FDG_PREC_FP64 && prec != FDG_PREC_FP32 && prec != FDG_PREC_BF16)
+    return set_error(FDG_EINVAL, "set_precision: unknown precision %d", prec);
+  c->prec = prec;
+  return FDG_OK;
+}
+
+extern "C" int fdg_set_operator_kron(fdg_ctx *c, int l, const double *M, const double *K) {
+  clear_error();
+  if (!c || !M || !K) return set_error(FDG_EINVAL, "set_operator_kron: NULL argument");
+  if (l < 0 || l >= c->d) return set_error(FDG_EINVAL, "set_operator_kron: bad direction %d", l);
+  if (c->op_kind == 2) return set_error(FDG_EINVAL, "set_operator_kron: context already has a CSR operator");
+  const int n = c->n;
+  if (!finite_all(M, (size_t)n * n) || !finite_all(K, (size_t)n * n))
+    return set_error(FDG_EINVAL, "set_operator_kron: non-finite factor");
+  std::vector<int> lo(n), hi(n);
+  int w = 1;
+  for (int i = 0; i < n; ++i) {
+    int a = n, b = -1;
+    for (int j = 0; j < n; ++j)
+      if (M[(size_t)i * n + j] != 0.0 || K[(size_t)i * n + j] != 0.0) { a = std::min(a, j); b = std::max(b, j); }
+    if (b < 0) { a = 0; b = 0; }
+    lo[i] = a;
+    hi[i] = b;
+    w = std::max(w, b - a + 1);
+  }
+  std::vector<double> bm((size_t)n * w, 0.0), bk((size_t)n * w, 0.0);
+  std::vector<int32_t> blo(n);
+  for (int i = 0; i < n; ++i) {
+    const int s = std::min(lo[i], n - w);  // window [s, s+w) covers [lo, hi] and stays inside
+    blo[i] = s;
+    for (int t = 0; t < w; ++t) {
+      bm[(size_t)i * w + t] = M[(size_t)i * n + s + t];
+      bk[(size_t)i * w + t] = K[(size_t)i * n + s + t];
+    }
+  }
+  dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandlo[l]);
+  int st;
+  if ((st = dalloc(&c->bandM[l], bm.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->bandK[l], bk.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->bandlo[l], blo.size())) != FDG_OK) return st;
+  HIPCHK(hipMemcpy(c->bandM[l], bm.data(), bm.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->bandK[l], bk.data(), bk.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->bandlo[l], blo.data(), blo.size() * 4, hipMemcpyHostToDevice));
+  c->bandw[l] = w;
+  c->have_op[l] = true;
+  c->op_kind = 1;
+  return FDG_OK;
+}
+
+extern "C" int fdg_set_operator_csr(fdg_ctx *c, int64_t nrows, int64_t nnz, const int64_t *rowptr,
+                                    const int32_t *col, const double *val) {
+  clear_error();
+  if (!c || !rowptr || (nnz > 0 && (!col || !val))) return set_error(FDG_EINVAL, "set_operator_csr: NULL argument");
+  if (c->op_kind == 1) return set_error(FDG_EINVAL, "set_operator_csr: context already has a Kronecker operator");
+  if (nrows != c->N) return set_error(FDG_EINVAL, "set_operator_csr: nrows %lld != N %lld", (long long)nrows, (long long)c->N);
+  if (rowptr[0] != 0 || rowptr[nrows] != nnz) return set_error(FDG_EINVAL, "set_operator_csr: rowptr ends do not match nnz");
+  int width = 0;
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t len = rowptr[r + 1] - rowptr[r];
+    if (len < 0) return set_error(FDG_EINVAL, "set_operator_csr: rowptr decreases at row %lld", (long long)r);
+    if (len > 4096) return set_error(FDG_EINVAL, "set_operator_csr: row %lld longer than 4096", (long long)r);
+    width = std::max(width, (int)len);
+  }
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (col[e] < 0 || col[e] >= nrows) return set_error(FDG_EINVAL, "set_operator_csr: column out of range at %lld", (long long)e);
+    if (!std::isfinite(val[e])) return set_error(FDG_EINVAL, "set_operator_csr: non-finite value at %lld", (long long)e);
+  }
+  if (width == 0) width = 1;
+  const size_t cnt = (size_t)width * nrows;
+  std::vector<int32_t> ec(cnt);
+  std::vector<double> ev(cnt, 0.0);
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t b = rowptr[r], len = rowptr[r + 1] - b;
+    for (int t = 0; t < width; ++t) {
+      const size_t e = (size_t)t * nrows + r;
+      if (t < len) {
+        ec[e] = col[b + t];
+        ev[e] = val[b + t];
+      } else {
+        ec[e] = (int32_t)r;  // padding: a valid column with a zero coefficient
+      }
+    }
+  }
+  dfree(c->ell_col); dfree(c->ell_val);
+  int st;
+  if ((st = dalloc(&c->ell_col, cnt)) != FDG_OK) return st;
+  if ((st = dalloc(&c->ell_val, cnt)) != FDG_OK) return st;
+  HIPCHK(hipMemcpy(c->ell_col, ec.data(), cnt * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->ell_val, ev.data(), cnt * 8, hipMemcpyHostToDevice));
+  c->ell_width = width;
+  c->op_kind = 2;
+  return FDG_OK;
+}
+
+extern "C" int fdg_apply_prec(fdg_ctx *c, const double *b, double *s) {
+  clear_error();
+  if (!c || !b || !s) return set_error(FDG_EINVAL, "apply_prec: NULL argument");
+  if (b == s) return set_error(FDG_EINVAL, "apply_prec: input and output alias");
+  int st = check_ready_prec(c);
+  if (st != FDG_OK) return st;
+  return do_apply(c, b, s);
+}
+
+extern "C" int fdg_matvec(fdg_ctx *c, const double *x, double *y) {
+  clear_error();
+  if (!c || !x || !y) return set_error(FDG_EINVAL, "matvec: NULL argument");
+  if (x == y) return set_error(FDG_EINVAL, "matvec: input and output alias");
+  int st = check_ready_op(c);
+  if (st != FDG_OK) return st;
+  return do_matvec(c, x, y);
+}
+
+extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, int restart, int maxit, int flags,
+                         fdg_info *info) {
+  clear_error();
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!c || !b || !x) return set_error(FDG_EINVAL, "solve: NULL argument");
+  if (b == x) return set_error(FDG_EINVAL, "solve: b and x alias");
+  if (c->batch != 1) return set_error(FDG_EINVAL, "solve: context batch must be 1");
+  if (!(rtol >= 0.0) || restart < 1 || restart > 255 || maxit < 0)
+    return set_error(FDG_EINVAL, "solve: bad rtol/restart/maxit");
+  int st;
+  if ((st = check_ready_prec(c)) != FDG_OK) return st;
+  if ((st = check_ready_op(c)) != FDG_OK) return st;
+  if ((st = ensure_workspace(c)) != FDG_OK) return st;
+  const int m = restart;
+  if ((st = ensure_krylov(c, m)) != FDG_OK) return st;
+  const int64_t N = c->N;
+  const int G = reduction_blocks(N);
+  const bool fixed = (flags & FDG_SOLVE_FIXED_ITERS) != 0;
+  const bool use_x0 = (flags & FDG_SOLVE_USE_X0) != 0;
+  const int limit = maxit;
+  double *V = c->Vb, *Z = c->Zb;
+  auto Vq = [&](int q) { return V + (size_t)q * N; };
+  auto Zq = [&](int q) { return Z + (size_t)q * N; };
+
+  if ((st = device_norm(c, b)) != FDG_OK) return st;
+  const double bnorm = c->hpin[0];
+  fdg_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  if (!use_x0) HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
+  if (bnorm == 0.0) {
+    if (!use_x0) HIPCHK(hipStreamSynchronize(c->stream));
+    inf.converged = 1;
+    inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return FDG_OK;
+  }
+  const double target = rtol * bnorm;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+  int total = 0, restarts = 0;
+  bool x_nonzero = use_x0;
+  double last_est = 1.0;
+  bool breakdown = false;
+  while (true) {
+    double beta;
+    if (x_nonzero) {
+      if ((st = do_matvec(c, x, c->t1)) != FDG_OK) return st;
+      {
+        TimedLaunch tl(c, 2);
+        launch_residual(c->stream, b, c->t1, Vq(0), N, 1, G, c->P3);
+      }
+      {
+        TimedLaunch tl(c, 2);
+        launch_finalize_norm(c->stream, c->P3, G, 1, c->Hcol);
+      }
+      if ((st = read_scalars(c, c->Hcol, 1)) != FDG_OK) return st;
+      beta = c->hpin[0];
+    } else {
+      HIPCHK(hipMemcpyAsync(Vq(0), b, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
+      {
+        TimedLaunch tl(c, 2);
+        launch_finalize_norm(c->stream, c->P3, G, 1, c->Hcol);  // ||b|| partials are still in P3
+      }
+      beta = bnorm;
+    }
+    inf.rel_res_true = beta / bnorm;
+    if ((!fixed && beta <= target) || total >= limit) {
+      inf.converged = beta <= target;
+      break;
+    }
+    {
+      TimedLaunch tl(c, 2);
+      launch_scale(c->stream, Vq(0), Vq(0), c->Hcol, 0, N, 1);
+    }
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    breakdown = false;
+    for (int j = 0; j < m; ++j) {
+      if ((st = do_apply(c, Vq(j), Zq(j))) != FDG_OK) return st;
+      if ((st = do_matvec(c, Zq(j), Vq(j + 1))) != FDG_OK) return st;
+      double *w = Vq(j + 1);
+      const int nv = j + 1;
+      {
+        TimedLaunch tl(c, 2);
+        launch_dots(c->stream, V, N, nv, w, N, 1, G, c->P1);
+      }
+      {
+        TimedLaunch tl(c, 2);
+        launch_update(c->stream, V, N, nv, c->P1, G, w, N, 1, nullptr);
+      }
+      {
+        TimedLaunch tl(c, 2);
+        launch_dots(c->stream, V, N, nv, w, N, 1, G, c->P2);
+      }
+      {
+        TimedLaunch tl(c, 2);
+        launch_update(c->stream, V, N, nv, c->P2, G, w, N, 1, c->P3);
+      }
+      {
+        TimedLaunch tl(c, 2);
+        launch_finalize_h(c->stream, c->P1, c->P2, c->P3, G, nv, 1, c->Hcol);
+      }
+      {
+        TimedLaunch tl(c, 2);
+        launch_scale(c->stream, w, w, c->Hcol + nv, 0, N, 1);
+      }
+      HIPCHK(hipGetLastError());
+      if ((st = read_scalars(c, c->Hcol, nv + 1)) != FDG_OK) return st;
+      for (int q = 0; q <= nv; ++q) Hij(q, j) = c->hpin[q];
+      double wn0 = 0.0;
+      for (int q = 0; q <= nv; ++q) wn0 += Hij(q, j) * Hij(q, j);
+      wn0 = std::sqrt(wn0);
+      const double hn = Hij(j + 1, j);
+      for (int i = 0; i < j; ++i) {
+        const double a = Hij(i, j), bb = Hij(i + 1, j);
+        Hij(i, j) = cs[i] * a + sn[i] * bb;
+        Hij(i + 1, j) = -sn[i] * a + cs[i] * bb;
+      }
+      {
+        const double a = Hij(j, j), bb = Hij(j + 1, j);
+        if (bb == 0.0) {
+          cs[j] = 1.0; sn[j] = 0.0;
+        } else {
+          const double r = std::hypot(a, bb);
+          cs[j] = a / r; sn[j] = bb / r;
+          Hij(j, j) = r;
+        }
+        Hij(j + 1, j) = 0.0;
+      }
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      k = j + 1;
+      last_est = std::fabs(g[j + 1]) / bnorm;
+      breakdown = hn <= 1e-14 * wn0;
+      if (total >= limit || breakdown) break;
+      if (!fixed && std::fabs(g[j + 1]) <= target) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int q = i + 1; q < k; ++q) s -= Hij(i, q) * y[q];
+      y[i] = s / Hij(i, i);
+    }
+    std::memcpy(c->hpin + m + 4, y.data(), sizeof(double) * k);
+    HIPCHK(hipMemcpyAsync(c->ydev, c->hpin + m + 4, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+    {
+      TimedLaunch tl(c, 2);
+      launch_lincomb(c->stream, x, Z, N, k, c->ydev, 0, N, 1);
+    }
+    x_nonzero = true;
+    ++restarts;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  inf.iterations = total;
+  inf.restarts = restarts;
+  inf.breakdown = breakdown ? 1 : 0;
+  inf.rel_res_est = last_est;
+  inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return inf.converged ? FDG_OK : FDG_NOT_CONVERGED;
+}
+
+extern "C" size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart) {
+  if ((d != 2 && d != 3) || n < 1 || batch < 1 || restart < 0) return 0;
+  const size_t N = (size_t)ipow(n, d) * batch;
+  const size_t ld = ((size_t)(n + 63) / 64) * 64;
+  size_t bytes = 2 * N * 8;                       // apply ping-pong buffers
+  if (prec != FDG_PREC_FP64) bytes += 2 * N * 4;  // low-precision intermediates
+  bytes += (size_t)(2 * restart + 1) * N * 8;     // Krylov bases V (m+1) and Z (m)
+  bytes += (size_t)d * (2 * ld * ld * (8 + 4 + 2) + ld * 12);  // factors in three precisions
+  bytes += (size_t)reduction_blocks((int64_t)ipow(n, d)) * (2 * restart + 3) * 8 * batch + 4096;
+  return bytes;
+}
+
+extern "C" int fdg_timer_enable(fdg_ctx *c, int kernel, int enable) {
+  clear_error();
+  if (!c || kernel < 0 || kernel >= kTimerClasses) return set_error(FDG_EINVAL, "timer_enable: bad argument");
+  c->timers[kernel].on = enable != 0;
+  return FDG_OK;
+}
+
+extern "C" int fdg_timer_read(fdg_ctx *c, int kernel, int64_t *launches, double *total_ms) {
+  clear_error();
+  if (!c || kernel < 0 || kernel >= kTimerClasses || !launches || !total_ms)
+    return set_error(FDG_EINVAL, "timer_read: bad argument");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  TimerState &t = c->timers[kernel];
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (size_t i = 0; i + 1 < t.pending.size(); i += 2) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t.pending[i], t.pending[i + 1]));
+    sum += ms;
+    ++cnt;
+  }
+  for (auto e : t.pending) t.pool.push_back(e);
+  t.pending.clear();
+  *launches = cnt;
+  *total_ms = sum;
+  return FDG_OK;
+}

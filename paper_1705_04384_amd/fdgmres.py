@@ -1,0 +1,242 @@
+"""Python binding of libfdgmres.so: argument marshalling only.
+
+Every computation runs in the library (host setup in C++, the solve in HIP kernels);
+torch tensors provide device memory and the HIP stream.  The names follow the C ABI in
+include/fdgmres.h.  The library must have been built (``build.build()``); importing
+this module without it raises, there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdgmres.so")
+
+FDG_OK = 0
+FDG_NOT_CONVERGED = 1
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+SOLVE_USE_X0 = 1
+SOLVE_FIXED_ITERS = 2
+TIMER_APPLY, TIMER_MATVEC, TIMER_KRYLOV = 0, 1, 2
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class FdgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class fdg_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("breakdown", ctypes.c_int), ("rel_res_est", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+_lib = None
+
+EXPORTS = [
+    "fdg_colloc_factors", "fdg_factor_pencil", "fdg_deformed_csr", "fdg_manufactured_rhs",
+    "fdg_create", "fdg_destroy", "fdg_set_prec_factors", "fdg_set_precision",
+    "fdg_set_operator_kron", "fdg_set_operator_csr", "fdg_apply_prec", "fdg_matvec", "fdg_solve",
+    "fdg_footprint_bytes", "fdg_timer_enable", "fdg_timer_read", "fdg_status_str", "fdg_last_error",
+]
+
+
+def lib():
+    """Loads the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not built: run paper_1705_04384_amd/build.py (no fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.fdg_colloc_factors.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.fdg_factor_pencil.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.fdg_deformed_csr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, _i64p, _i64p,
+                                   _i32p, _dp]
+    L.fdg_manufactured_rhs.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+    L.fdg_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_void_p]
+    L.fdg_destroy.argtypes = [ctypes.c_void_p]
+    L.fdg_set_prec_factors.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
+    L.fdg_set_precision.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.fdg_set_operator_kron.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
+    L.fdg_set_operator_csr.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _dp]
+    L.fdg_apply_prec.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.fdg_matvec.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.fdg_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                            ctypes.c_int, ctypes.c_int, ctypes.POINTER(fdg_info)]
+    L.fdg_footprint_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.fdg_footprint_bytes.restype = ctypes.c_size_t
+    L.fdg_timer_enable.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    L.fdg_timer_read.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, _dp]
+    L.fdg_status_str.argtypes = [ctypes.c_int]
+    L.fdg_status_str.restype = ctypes.c_char_p
+    L.fdg_last_error.argtypes = []
+    L.fdg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st, allow=(FDG_OK,)):
+    if st in allow:
+        return st
+    L = lib()
+    raise FdgError(st, f"{L.fdg_status_str(st).decode()}: {L.fdg_last_error().decode()}")
+
+
+def _ptr(a, typ=_dp):
+    return a.ctypes.data_as(typ)
+
+
+# ---- host setup -------------------------------------------------------------------------
+
+def colloc_factors(p, n):
+    """(M, K, D1, tau) of eq. 2.8 on the uniform open knot vector, Greville points (eq. 2.4)."""
+    M = np.zeros((n, n)); K = np.zeros((n, n)); D1 = np.zeros((n, n)); tau = np.zeros(n)
+    _check(lib().fdg_colloc_factors(p, n, _ptr(M), _ptr(K), _ptr(D1), _ptr(tau)))
+    return M, K, D1, tau
+
+
+def factor_pencil(K, M):
+    """(U, V, lam, cond1(U)) with K U = M U diag(lam), V = (M U)^{-T} (eq. 4.6)."""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    n = K.shape[0]
+    U = np.zeros((n, n)); V = np.zeros((n, n)); lam = np.zeros(n); c = ctypes.c_double()
+    _check(lib().fdg_factor_pencil(n, _ptr(K), _ptr(M), _ptr(U), _ptr(V), _ptr(lam), ctypes.byref(c)))
+    return U, V, lam, c.value
+
+
+def deformed_csr(p, n, amp=0.1, band=False):
+    """CSR (rowptr, col, val) of the collocation matrix on the deformed cube."""
+    L = lib()
+    nnz = ctypes.c_int64()
+    _check(L.fdg_deformed_csr(p, n, amp, int(band), ctypes.byref(nnz), None, None, None))
+    rowptr = np.zeros(n ** 3 + 1, dtype=np.int64)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value, dtype=np.float64)
+    _check(L.fdg_deformed_csr(p, n, amp, int(band), ctypes.byref(nnz), _ptr(rowptr, _i64p), _ptr(col, _i32p),
+                              _ptr(val)))
+    return rowptr, col, val
+
+
+def manufactured_rhs(d, n, tau):
+    f = np.zeros(n ** d)
+    _check(lib().fdg_manufactured_rhs(d, n, _ptr(np.ascontiguousarray(tau, dtype=np.float64)), _ptr(f)))
+    return f
+
+
+def footprint_bytes(d, n, batch=1, prec=PREC_FP64, restart=30):
+    return int(lib().fdg_footprint_bytes(d, n, batch, prec, restart))
+
+
+# ---- device context -------------------------------------------------------------------------
+
+def _dev_ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One problem shape (d, n, batch) on one HIP stream."""
+
+    def __init__(self, d, n, batch=1, stream=None):
+        import torch
+        self.d, self.n, self.batch = d, n, batch
+        self.N = n ** d
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        dims = (ctypes.c_int32 * 3)(n, n, n)
+        _check(lib().fdg_create(ctypes.byref(h), d, dims, batch, ctypes.c_void_p(stream.cuda_stream)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().fdg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_prec_factors(self, l, U, V, lam):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        _check(lib().fdg_set_prec_factors(self._h, l, _ptr(U), _ptr(V), _ptr(lam)))
+
+    def set_precision(self, prec):
+        _check(lib().fdg_set_precision(self._h, prec))
+
+    def set_operator_kron(self, l, M, K):
+        M = np.ascontiguousarray(M, dtype=np.float64)
+        K = np.ascontiguousarray(K, dtype=np.float64)
+        _check(lib().fdg_set_operator_kron(self._h, l, _ptr(M), _ptr(K)))
+
+    def set_operator_csr(self, rowptr, col, val):
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        _check(lib().fdg_set_operator_csr(self._h, len(rowptr) - 1, len(col), _ptr(rowptr, _i64p),
+                                          _ptr(col, _i32p), _ptr(val)))
+
+    def apply_prec(self, b, s):
+        _check(lib().fdg_apply_prec(self._h, _dev_ptr(b), _dev_ptr(s)))
+
+    def matvec(self, x, y):
+        _check(lib().fdg_matvec(self._h, _dev_ptr(x), _dev_ptr(y)))
+
+    def solve(self, b, x, rtol=1e-8, restart=30, maxit=1000, flags=0):
+        info = fdg_info()
+        st = lib().fdg_solve(self._h, _dev_ptr(b), _dev_ptr(x), rtol, restart, maxit, flags, ctypes.byref(info))
+        _check(st, allow=(FDG_OK, FDG_NOT_CONVERGED))
+        return {k: getattr(info, k) for k, _ in fdg_info._fields_}
+
+    def timer_enable(self, kernel, on=True):
+        _check(lib().fdg_timer_enable(self._h, kernel, int(on)))
+
+    def timer_read(self, kernel):
+        cnt = ctypes.c_int64(); ms = ctypes.c_double()
+        _check(lib().fdg_timer_read(self._h, kernel, ctypes.byref(cnt), ctypes.byref(ms)))
+        return cnt.value, ms.value
+
+
+def unit_problem(d, p, n, batch=1, stream=None, prec=PREC_FP64):
+    """Context for the unit-domain collocation problem: operator (eq. 2.7 / 2.9) and its FD
+    preconditioner, all factors built by the library's host setup."""
+    M, K, D1, tau = colloc_factors(p, n)
+    U, V, lam, _ = factor_pencil(K, M)
+    ctx = Context(d, n, batch=batch, stream=stream)
+    for l in range(d):
+        ctx.set_prec_factors(l, U, V, lam)
+        ctx.set_operator_kron(l, M, K)
+    ctx.set_precision(prec)
+    ctx.tau = tau
+    return ctx
+
+
+def deformed_problem(p, n, amp=0.1, band=False, stream=None, prec=PREC_FP64):
+    """Context for the deformed-cube collocation problem (CSR operator) preconditioned by the
+    unit-cube FD solve."""
+    M, K, D1, tau = colloc_factors(p, n)
+    U, V, lam, _ = factor_pencil(K, M)
+    ctx = Context(3, n, stream=stream)
+    for l in range(3):
+        ctx.set_prec_factors(l, U, V, lam)
+    rowptr, col, val = deformed_csr(p, n, amp, band)
+    ctx.set_operator_csr(rowptr, col, val)
+    ctx.set_precision(prec)
+    ctx.tau = tau
+    ctx.nnz = len(col)
+    return ctx

@@ -1,0 +1,117 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol include/fdgmres.h
+declares, and its host-side setup (collocation factors, pencil factorisation,
+deformed-cube CSR, manufactured right-hand side) agrees with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import colloc, fd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdgmres.h")
+
+fdg = pytest.importorskip("paper_1705_04384_amd.fdgmres")
+
+
+def _lib():
+    try:
+        return fdg.lib()
+    except RuntimeError as e:
+        pytest.fail(str(e))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib()
+    text = open(HEADER).read()
+    names = sorted(set(re.findall(r"\b(fdg_[a-z0-9_]+)\s*\(", text)))
+    assert len(names) >= 15
+    missing = [nm for nm in names if not hasattr(L, nm)]
+    assert not missing, missing
+    assert set(fdg.EXPORTS) <= set(names)
+
+
+@pytest.mark.parametrize("p,n", [(2, 16), (3, 33), (4, 128), (5, 21), (6, 192), (3, 96)])
+def test_colloc_factors_match_oracle(p, n):
+    _lib()
+    M, K, D1, tau = fdg.colloc_factors(p, n)
+    Mo, Ko, D1o, tauo = colloc.colloc_factors(p, n)
+    assert np.array_equal(tau, tauo)
+    E = n + 2 - p
+    assert np.abs(M - Mo).max() <= 1e-14
+    assert np.abs(D1 - D1o).max() <= 1e-13 * E
+    assert np.abs(K - Ko).max() <= 1e-12 * E * E
+    # identical sparsity (exact Greville points on knots for odd p)
+    assert np.array_equal(M != 0, Mo != 0)
+
+
+@pytest.mark.parametrize("p,n", [(3, 33), (4, 128), (6, 192), (2, 64), (3, 96), (5, 47)])
+def test_factor_pencil_gives_exact_inverse(p, n):
+    _lib()
+    M, K, _, _ = fdg.colloc_factors(p, n)
+    U, V, lam, cond = fdg.factor_pencil(K, M)
+    Uo, Vo, lamo = fd.factor_pencil(K, M)
+    assert np.all(np.diff(lam) >= 0)
+    assert np.abs(lam - lamo).max() <= 1e-12 * lamo.max()
+    assert cond < 1e4
+    b = np.random.default_rng(n).standard_normal(n * n)
+    s = fd.fd_apply([U] * 2, [V] * 2, [lam] * 2, b)
+    so = fd.fd_apply([Uo] * 2, [Vo] * 2, [lamo] * 2, b)
+    assert np.linalg.norm(s - so) <= 1e-11 * np.linalg.norm(so)
+
+
+def test_factor_pencil_rejects_complex_spectrum():
+    L = _lib()
+    rng = np.random.default_rng(0)
+    K = rng.standard_normal((10, 10))
+    M = np.eye(10)
+    with pytest.raises(fdg.FdgError) as ei:
+        fdg.factor_pencil(K, M)
+    assert ei.value.status == -4
+
+
+def test_bad_arguments_are_errors():
+    _lib()
+    with pytest.raises(fdg.FdgError) as ei:
+        fdg.colloc_factors(0, 10)
+    assert ei.value.status == -1
+    with pytest.raises(fdg.FdgError):
+        fdg.colloc_factors(5, 2)
+
+
+@pytest.mark.parametrize("p,n", [(3, 7), (2, 6), (4, 6)])
+def test_deformed_csr_matches_oracle(p, n):
+    _lib()
+    rowptr, col, val = fdg.deformed_csr(p, n, 0.1, band=False)
+    A = sp.csr_matrix((val, col, rowptr), shape=(n ** 3, n ** 3))
+    Ao = colloc.deformed_operator(p, n, 0.1)
+    assert abs(A - Ao).max() <= 1e-11 * abs(Ao).max()
+    assert np.all(np.diff(rowptr) <= (p + 1) ** 3)
+
+
+def test_deformed_csr_band_variant_has_full_stencil():
+    _lib()
+    p, n = 3, 9
+    rowptr, col, val = fdg.deformed_csr(p, n, 0.1, band=True)
+    nnz = np.diff(rowptr)
+    assert nnz.max() == (2 * p + 1) ** 3
+    A = sp.csr_matrix((val, col, rowptr), shape=(n ** 3, n ** 3))
+    Ao = colloc.deformed_operator(p, n, 0.1)
+    assert abs(A - Ao).max() <= 1e-11 * abs(Ao).max()
+
+
+def test_manufactured_rhs_matches_oracle():
+    _lib()
+    for d, p, n in [(2, 3, 33), (3, 4, 20)]:
+        _, _, _, tau = fdg.colloc_factors(p, n)
+        f = fdg.manufactured_rhs(d, n, tau)
+        assert np.allclose(f, colloc.manufactured_rhs(p, n, d), rtol=1e-14, atol=1e-13)
+
+
+def test_footprint_grows_with_restart():
+    _lib()
+    a = fdg.footprint_bytes(3, 128, 1, 0, 30)
+    b = fdg.footprint_bytes(3, 128, 1, 0, 50)
+    assert b > a > 61 * 8 * 128 ** 3

@@ -63,7 +63,7 @@ def test_kronecker_identity(d, p, n):
     assert np.linalg.norm(P @ s - v) <= 1e-12 * np.linalg.norm(v)
 
 
-@pytest.mark.parametrize("p,n", [(2, 16), (3, 33), (4, 64), (5, 40), (6, 48), (3, 96), (4, 128), (6, 192)])
+@pytest.mark.parametrize("p,n", [(2, 16), (3, 33), (4, 64), (5, 40), (6, 48), (3, 96), (4, 128), (6, 192), (5, 47), (6, 47)])
 def test_remark1_real_positive_wellconditioned(p, n):
     M, K, _, _ = colloc.colloc_factors(p, n)
     U, V, lam = fd.factor_pencil(K, M)
