@@ -1,0 +1,157 @@
+"""Benchmark: FD-preconditioned flexible GMRES on one MI355X.
+
+Workload (one step): the 3D Poisson collocation system on the unit cube, degree p = 4,
+n = 128 unknowns per direction (N = 2,097,152), FP64, solved to rtol 1e-8 by FGMRES(30)
+from x0 = 0 for two right-hand sides: the manufactured f = 3 pi^2 prod sin(pi tau_l) and
+a seeded N(0, 1) vector.  The operator is applied as the Kronecker sum of eq. 2.9, the
+preconditioner by the FD solve of eq. 4.9.  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+Extra fields: the P^{-1} apply rate (algorithmic 12 n^4 flops per apply), the roofline
+of the dominant kernel (the FP64 MFMA mode product, 2 n^4 flops per launch) from HIP
+events recorded around every launch in the timed region, and the oracle (CPU, FP64)
+timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-solves", type=int, default=4)
+    return ap.parse_args()
+
+
+def cpu_baseline(p, n, f, noise, count):
+    """The oracle (FP64, numpy/scipy) solving the same problem; setup excluded."""
+    import numpy as np
+    from oracle import colloc, fd, fgmres
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    U, V, lam = fd.factor_pencil(K, M)
+    mv = lambda v: colloc.unit_matvec([M] * 3, [K] * 3, v)
+    pr = lambda v: fd.fd_apply([U] * 3, [V] * 3, [lam] * 3, v)
+    rhs = [f, noise]
+    t0 = time.perf_counter()
+    its = []
+    for k in range(count):
+        _, info = fgmres.fgmres(mv, pr, rhs[k % 2], rtol=1e-8, restart=30)
+        its.append(info["iterations"])
+    dt = time.perf_counter() - t0
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((d.get("num_threads") or 0) for d in threadpool_info()) or None
+    except Exception:
+        pass
+    return dict(value=count / dt, unit="solves/s", cores=threads or os.cpu_count(), kind="oracle",
+                sample=f"{count} oracle FGMRES(30) solves of the same 128^3 p=4 problem "
+                       f"(alternating the two right-hand sides), {dt:.1f} s, iterations {its}")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1705_04384_amd import fdgmres, inputs
+
+    torch.cuda.set_device(0)
+    d, p, n = 3, args.p, args.n
+    N = n ** d
+    ctx = fdgmres.unit_problem(d, p, n)
+    f = fdgmres.manufactured_rhs(d, n, ctx.tau)
+    noise = inputs.rhs_normal(inputs.SEED_NOISE_128, N)
+    B = [torch.from_numpy(f).cuda(), torch.from_numpy(noise).cuda()]
+    X = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(2)]
+
+    def step():
+        infos = []
+        for k in range(2):
+            infos.append(ctx.solve(B[k], X[k], rtol=1e-8, restart=30, maxit=1000))
+        return infos
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timer_read(fdgmres.TIMER_APPLY)
+    ctx.timer_enable(fdgmres.TIMER_APPLY, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.timer_enable(fdgmres.TIMER_APPLY, False)
+    launches, kms = ctx.timer_read(fdgmres.TIMER_APPLY)
+    for info in infos:
+        assert info["converged"] and info["rel_res_true"] <= 1e-8, info
+
+    # P^{-1} apply alone
+    s = torch.empty(N, dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        ctx.apply_prec(B[1], s)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.apply_reps):
+        ctx.apply_prec(B[1], s)
+    torch.cuda.synchronize()
+    t_apply = (time.perf_counter() - ta) / args.apply_reps
+    apply_flops = 4 * d * n ** (d + 1)
+
+    mode_flops = 2 * n ** (d + 1)
+    avg_s = kms / 1e3 / max(launches, 1)
+    achieved = mode_flops / avg_s / 1e12
+    solves = 2 * args.steps
+    out = {
+        "metric": "GMRES solves/sec to rtol 1e-8",
+        "value": solves / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D Poisson B-spline collocation, unit cube, p={p}, n={n} (N={N}), "
+                               f"Greville points, manufactured + N(0,1) RHS, FGMRES(30) to rtol 1e-8, "
+                               f"Kronecker operator, FD preconditioner, all FP64",
+                   "solves_per_step": 2},
+        "iterations": [i["iterations"] for i in infos],
+        "rel_res_true": [i["rel_res_true"] for i in infos],
+        "apply_prec": {"ms": t_apply * 1e3, "tflops": apply_flops / t_apply / 1e12,
+                       "frac_fp64_mfma": apply_flops / t_apply / 1e12 / PEAK_FP64_TFLOPS},
+        "roofline": {"kernel": "k_modeprod_f64 (FD mode product, FP64 MFMA)", "bound": "mfma",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "launches": launches, "avg_launch_us": avg_s * 1e6,
+                     "flops_per_launch": mode_flops},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, n, f, noise, args.cpu_solves)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

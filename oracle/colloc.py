@@ -59,6 +59,23 @@ def unit_operator(Ms, Ks):
     return A.tocsr()
 
 
+def unit_matvec(Ms, Ks, x):
+    """y = P x for the unit-domain operator of eq. 2.7 / 2.9 without forming P: each
+    Kronecker term is applied as one mode product per direction (dense factors)."""
+    d = len(Ms)
+    shape = [Ms[l].shape[0] for l in reversed(range(d))]
+    X = np.asarray(x, dtype=np.float64).reshape(shape)
+    Y = np.zeros_like(X)
+    for l in range(d):
+        T = X
+        for q in range(d):
+            F = Ks[q] if q == l else Ms[q]
+            axis = d - 1 - q
+            T = np.moveaxis(np.tensordot(F, T, axes=([1], [axis])), 0, axis)
+        Y = Y + T
+    return Y.ravel()
+
+
 def tensor_grid(vals_by_dir):
     """Tensor of shape (n_d, ..., n_1) holding the listed per-direction 1D arrays,
     returned as a list of d arrays (coordinate l+1 broadcast over the grid); flattening

@@ -191,20 +191,14 @@ int do_apply(fdg_ctx *c, const double *b, double *s) {
     mode(b, c->t1, c->Wv[0], 0);
     mode(c->t1, c->t2, c->Wv[1], 1);
     mode(c->t2, c->t1, c->Wv[2], 2);
-    {
-      TimedLaunch tl(c, 0);
-      launch_divide_f64(c->stream, c->t1, 3, n, B, c->lam[0], c->lam[1], c->lam[2]);
-    }
+    launch_divide_f64(c->stream, c->t1, 3, n, B, c->lam[0], c->lam[1], c->lam[2]);
     mode(c->t1, c->t2, c->Wu[0], 0);
     mode(c->t2, c->t1, c->Wu[1], 1);
     mode(c->t1, s, c->Wu[2], 2);
   } else {
     mode(b, c->t1, c->Wv[0], 0);
     mode(c->t1, c->t2, c->Wv[1], 1);
-    {
-      TimedLaunch tl(c, 0);
-      launch_divide_f64(c->stream, c->t2, 2, n, B, c->lam[0], c->lam[1], nullptr);
-    }
+    launch_divide_f64(c->stream, c->t2, 2, n, B, c->lam[0], c->lam[1], nullptr);
     mode(c->t2, c->t1, c->Wu[0], 0);
     mode(c->t1, s, c->Wu[1], 1);
   }

@@ -35,7 +35,8 @@ static inline unsigned grid1(int64_t work, int per_block) {
 // Mode product, FP64 MFMA.  One workgroup (4 waves) computes a 64 (k) x 64 (c) output
 // tile; wave w owns a 32 x 32 quarter = 2 x 2 MFMA tiles of 16 x 16.
 // v_mfma_f64_16x16x4_f64 operand layout (lane l, li = l % 16, lg = l / 16):
-//   A[m = li][k = lg],  B[k = lg][n = li],  D[m = 4*lg + r][n = li] in register r.
+//   A[m = li][k = lg],  B[k = lg][n = li],  D[m = lg + 4*r][n = li] in register r
+// (the FP32 16x16x4 form instead returns D[m = 4*lg + r][n = li]).
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_modeprod_f64(const double *__restrict__ X,
                                                          double *__restrict__ Y,
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_modeprod_f64(const double *__restric
       const int64_t c = c0 + 16 * tj + li;
       if (c >= ncols) continue;
       for (int r = 0; r < 4; ++r) {
-        const int k = k0 + 16 * ti + 4 * lg + r;
+        const int k = k0 + 16 * ti + lg + 4 * r;
         if (k < n) Yo[k * sJ + c * sC] = acc[ti][tj][r];
       }
     }

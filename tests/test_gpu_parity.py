@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: the FD apply is exact up to rounding on both sides, so FP64 results agree
+to ~1e-13 relative (checked at 1e-11: the two sides use independently computed
+eigenvector bases, whose conditioning scales the rounding).  Solves are compared
+after the same number of FGMRES iterations at <= 1e-8 relative solution error.
+"""
+import numpy as np
+import pytest
+
+from oracle import colloc, fd, fgmres
+from paper_1705_04384_amd import inputs
+from tests.gpu_helpers import oracle_unit, relerr, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _fdg():
+    torch_cuda()
+    from paper_1705_04384_amd import fdgmres
+    fdgmres.lib()
+    return fdgmres
+
+
+@pytest.mark.parametrize("d,p,n,batch", [
+    (2, 3, 33, 1), (3, 4, 16, 1), (3, 3, 33, 2), (2, 5, 47, 3), (3, 6, 20, 1),
+    (2, 2, 64, 1), (3, 2, 17, 1), (2, 4, 130, 2), (3, 4, 70, 1),
+])
+def test_apply_prec_fp64(d, p, n, batch):
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.unit_problem(d, p, n, batch=batch)
+    N = n ** d
+    b = np.concatenate([inputs.rhs_normal(100 + k, N) for k in range(batch)])
+    s = torch.empty(batch * N, dtype=torch.float64, device="cuda")
+    ctx.apply_prec(to_dev(b), s)
+    torch.cuda.synchronize()
+    got = s.cpu().numpy()
+    _, prec = oracle_unit(p, n, d)
+    for k in range(batch):
+        ref = prec(b[k * N:(k + 1) * N])
+        assert relerr(got[k * N:(k + 1) * N], ref) <= 1e-11, (d, p, n, k)
+    ctx.close()
+
+
+@pytest.mark.parametrize("d,p,n,batch", [(2, 3, 33, 1), (3, 4, 16, 2), (3, 6, 21, 1), (2, 5, 40, 1)])
+def test_kron_matvec(d, p, n, batch):
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.unit_problem(d, p, n, batch=batch)
+    N = n ** d
+    x = np.concatenate([inputs.rhs_normal(200 + k, N) for k in range(batch)])
+    y = torch.empty(batch * N, dtype=torch.float64, device="cuda")
+    ctx.matvec(to_dev(x), y)
+    torch.cuda.synchronize()
+    P, _ = oracle_unit(p, n, d)
+    got = y.cpu().numpy()
+    for k in range(batch):
+        assert relerr(got[k * N:(k + 1) * N], P @ x[k * N:(k + 1) * N]) <= 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("p,n,band", [(3, 12, False), (4, 9, False), (3, 8, True)])
+def test_csr_matvec_deformed(p, n, band):
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.deformed_problem(p, n, 0.1, band=band)
+    x = inputs.rhs_uniform(3, n ** 3)
+    y = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    ctx.matvec(to_dev(x), y)
+    torch.cuda.synchronize()
+    A = colloc.deformed_operator(p, n, 0.1)
+    assert relerr(y.cpu().numpy(), A @ x) <= 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("d,p,n", [(2, 3, 33), (3, 4, 24), (3, 6, 18)])
+def test_solve_unit_domain_one_iteration(d, p, n):
+    """A = P on the unit domain: one FGMRES iteration reaches rounding level."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.unit_problem(d, p, n)
+    f = fdg.manufactured_rhs(d, n, ctx.tau)
+    assert np.allclose(f, colloc.manufactured_rhs(p, n, d), rtol=1e-14, atol=1e-12)
+    x = torch.empty(n ** d, dtype=torch.float64, device="cuda")
+    info = ctx.solve(to_dev(f), x, rtol=1e-8, restart=30)
+    P, prec = oracle_unit(p, n, d)
+    xo, io = fgmres.fgmres(lambda v: P @ v, prec, f, rtol=1e-8, restart=30)
+    assert info["converged"] and info["iterations"] == io["iterations"] == 1
+    assert info["rel_res_true"] <= 1e-12
+    assert relerr(x.cpu().numpy(), xo) <= 1e-8
+    ctx.close()
+
+
+@pytest.mark.parametrize("p,n,restart", [(3, 12, 30), (3, 10, 6), (2, 9, 30), (4, 8, 30)])
+def test_solve_deformed_matches_oracle(p, n, restart):
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.deformed_problem(p, n, 0.1)
+    b = inputs.rhs_uniform(inputs.SEED_DEFORMED_96, n ** 3)
+    A = colloc.deformed_operator(p, n, 0.1)
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    U, V, lam = fd.factor_pencil(K, M)
+    prec = lambda v: fd.fd_apply([U] * 3, [V] * 3, [lam] * 3, v)
+    xo, io = fgmres.fgmres(lambda v: A @ v, prec, b, rtol=1e-8, restart=restart)
+    # free-running: same stopping iteration
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.solve(to_dev(b), x, rtol=1e-8, restart=restart)
+    assert info["converged"] and io["converged"]
+    assert info["iterations"] == io["iterations"], (info, io["iterations"])
+    assert info["restarts"] == io["restarts"]
+    # fixed count: identical iteration, solutions agree
+    xf = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    k = io["iterations"]
+    info_f = ctx.solve(to_dev(b), xf, rtol=1e-8, restart=restart, maxit=k, flags=fdg.SOLVE_FIXED_ITERS)
+    assert info_f["iterations"] == k
+    assert relerr(xf.cpu().numpy(), xo) <= 1e-8
+    assert abs(info_f["rel_res_true"] - io["rel_res"]) <= 1e-9
+    ctx.close()
+
+
+def test_solve_use_x0_and_zero_rhs():
+    fdg = _fdg()
+    torch = torch_cuda()
+    p, n = 3, 10
+    ctx = fdg.deformed_problem(p, n, 0.1)
+    b = inputs.rhs_uniform(9, n ** 3)
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.solve(to_dev(b), x, rtol=1e-10)
+    assert info["converged"]
+    # restarting from the converged solution needs no iteration
+    info2 = ctx.solve(to_dev(b), x, rtol=1e-8, flags=fdg.SOLVE_USE_X0)
+    assert info2["iterations"] == 0 and info2["converged"]
+    z = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+    info3 = ctx.solve(z, x, rtol=1e-8)
+    assert info3["converged"] and info3["iterations"] == 0
+    assert float(x.abs().max()) == 0.0
+    ctx.close()
+
+
+def test_not_converged_status():
+    fdg = _fdg()
+    torch = torch_cuda()
+    p, n = 3, 10
+    ctx = fdg.deformed_problem(p, n, 0.1)
+    b = inputs.rhs_uniform(9, n ** 3)
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.solve(to_dev(b), x, rtol=1e-12, restart=5, maxit=3)
+    assert not info["converged"] and info["iterations"] == 3
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,bound", [(1, 2e-5), (2, 5e-2)])
+def test_low_precision_apply_contraction(prec, bound):
+    """P P~^{-1} b ~ b with the FP32 / BF16 preconditioner (one-apply contraction)."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    d, p, n = 3, 4, 40
+    ctx = fdg.unit_problem(d, p, n, prec=prec)
+    b = inputs.rhs_normal(5, n ** d)
+    s = torch.empty(n ** d, dtype=torch.float64, device="cuda")
+    ctx.apply_prec(to_dev(b), s)
+    torch.cuda.synchronize()
+    P, prec64 = oracle_unit(p, n, d)
+    sg = s.cpu().numpy()
+    contraction = relerr(P @ sg, b)
+    assert contraction <= bound, contraction
+    assert relerr(sg, prec64(b)) <= 50 * bound
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_mixed_precision_solve_reaches_fp64_accuracy(prec):
+    fdg = _fdg()
+    torch = torch_cuda()
+    d, p, n = 3, 6, 24
+    ctx = fdg.unit_problem(d, p, n, prec=prec)
+    b = inputs.rhs_normal(inputs.SEED_SWEEP_192, n ** d)
+    x = torch.empty(n ** d, dtype=torch.float64, device="cuda")
+    info = ctx.solve(to_dev(b), x, rtol=1e-10, restart=50)
+    _, prec64 = oracle_unit(p, n, d)
+    xref = prec64(b)
+    assert info["converged"]
+    assert info["iterations"] <= (3 if prec == 1 else 8)
+    assert relerr(x.cpu().numpy(), xref) <= 1e-8
+    ctx.close()
+
+
+def test_errors_through_the_abi():
+    fdg = _fdg()
+    torch = torch_cuda()
+    with pytest.raises(fdg.FdgError):
+        fdg.Context(4, 10)
+    ctx = fdg.Context(3, 8)
+    v = torch.zeros(512, dtype=torch.float64, device="cuda")
+    w = torch.zeros(512, dtype=torch.float64, device="cuda")
+    with pytest.raises(fdg.FdgError) as ei:
+        ctx.apply_prec(v, w)            # no factors yet
+    assert ei.value.status == -5
+    with pytest.raises(fdg.FdgError) as ei:
+        ctx.set_operator_csr(np.array([0, 2, 1] + [1] * 510, dtype=np.int64), np.zeros(1, np.int32), np.zeros(1))
+    assert ei.value.status == -1
+    rowptr = np.arange(513, dtype=np.int64)
+    with pytest.raises(fdg.FdgError):
+        ctx.set_operator_csr(rowptr, np.full(512, 600, np.int32), np.ones(512))   # column out of range
+    with pytest.raises(fdg.FdgError):
+        ctx.set_precision(7)
+    ctx.close()

@@ -158,3 +158,11 @@ def test_deformed_manufactured_order():
         hs.append(1.0 / bspline.n_spans(p, n))
     order = np.log(errs[-2] / errs[-1]) / np.log(hs[-2] / hs[-1])
     assert order >= p - 1 - 0.1, (errs, order)
+
+
+@pytest.mark.parametrize("d,p,n", [(2, 3, 11), (3, 4, 9), (3, 2, 7)])
+def test_unit_matvec_equals_sparse_operator(d, p, n):
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    x = np.random.default_rng(1).standard_normal(n ** d)
+    P = colloc.unit_operator([M] * d, [K] * d)
+    assert np.allclose(colloc.unit_matvec([M] * d, [K] * d, x), P @ x, rtol=1e-13, atol=1e-13 * abs(P @ x).max())
