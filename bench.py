@@ -90,8 +90,9 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.timer_read(fdgmres.TIMER_APPLY)
-    ctx.timer_enable(fdgmres.TIMER_APPLY, True)
+    for t in (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE):
+        ctx.timer_read(t)
+        ctx.timer_enable(t, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
@@ -99,8 +100,10 @@ def main():
         infos = step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ctx.timer_enable(fdgmres.TIMER_APPLY, False)
+    for t in (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE):
+        ctx.timer_enable(t, False)
     launches, kms = ctx.timer_read(fdgmres.TIMER_APPLY)
+    f_launches, f_kms = ctx.timer_read(fdgmres.TIMER_FIBRE)
     for info in infos:
         assert info["converged"] and info["rel_res_true"] <= 1e-8, info
 
@@ -116,9 +119,10 @@ def main():
     t_apply = (time.perf_counter() - ta) / args.apply_reps
     apply_flops = 4 * d * n ** (d + 1)
 
-    mode_flops = 2 * n ** (d + 1)
+    pass_flops = 4 * n ** (d + 1)      # one fused pass = two mode products of 2 n^4 flops
     avg_s = kms / 1e3 / max(launches, 1)
-    achieved = mode_flops / avg_s / 1e12
+    achieved = pass_flops / avg_s / 1e12
+    f_avg_s = f_kms / 1e3 / max(f_launches, 1)
     solves = 2 * args.steps
     out = {
         "metric": "GMRES solves/sec to rtol 1e-8",
@@ -141,11 +145,14 @@ def main():
         "rel_res_true": [i["rel_res_true"] for i in infos],
         "apply_prec": {"ms": t_apply * 1e3, "tflops": apply_flops / t_apply / 1e12,
                        "frac_fp64_mfma": apply_flops / t_apply / 1e12 / PEAK_FP64_TFLOPS},
-        "roofline": {"kernel": "k_modeprod_f64 (FD mode product, FP64 MFMA)", "bound": "mfma",
+        "roofline": {"kernel": "k_slab (FD modes 1+2, FP64 MFMA)", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "launches": launches, "avg_launch_us": avg_s * 1e6,
-                     "flops_per_launch": mode_flops},
+                     "flops_per_launch": pass_flops},
+        "fibre_pass": {"kernel": "k_fibre (FD mode 3 + divide + mode 3, FP64 MFMA)", "launches": f_launches,
+                       "avg_launch_us": f_avg_s * 1e6,
+                       "tflops": pass_flops / f_avg_s / 1e12 if f_launches else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, n, f, noise, args.cpu_solves)

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.h"
+#include "fd_apply.h"
 #include "kernels.h"
 #include "modeprod.h"
 
@@ -17,7 +18,7 @@ using namespace fdg;
 
 namespace {
 
-constexpr int kTimerClasses = 3;
+constexpr int kTimerClasses = 4;
 
 struct TimerState {
   bool on = false;
@@ -56,7 +57,7 @@ struct fdg_ctx {
   void *t32a = nullptr, *t32b = nullptr;
   int restart_alloc = 0;
   double *Vb = nullptr, *Zb = nullptr, *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *Hcol = nullptr,
-         *ydev = nullptr;
+         *ydev = nullptr, *hbuf = nullptr;
   double *hpin = nullptr;  // pinned host staging
   TimerState timers[kTimerClasses];
 };
@@ -175,6 +176,32 @@ int do_apply(fdg_ctx *c, const double *b, double *s) {
   const int n = c->n;
   const int64_t B = c->batch;
   const int64_t n2 = (int64_t)n * n;
+  if (fd_fused_supported(n)) {
+    if (c->d == 3) {
+      {
+        TimedLaunch tl(c, 0);
+        launch_slab_f64(c->stream, b, c->t1, c->Wv[0], c->Wv[1], c->ldw, n, B * n, false, nullptr, nullptr);
+      }
+      {
+        TimedLaunch tl(c, 3);
+        launch_fibre_f64(c->stream, c->t1, c->t2, c->Wv[2], c->Wu[2], c->ldw, n, B, c->lam[0], c->lam[1], c->lam[2]);
+      }
+      {
+        TimedLaunch tl(c, 0);
+        launch_slab_f64(c->stream, c->t2, s, c->Wu[0], c->Wu[1], c->ldw, n, B * n, false, nullptr, nullptr);
+      }
+    } else {
+      {
+        TimedLaunch tl(c, 0);
+        launch_slab_f64(c->stream, b, c->t1, c->Wv[0], c->Wv[1], c->ldw, n, B, true, c->lam[0], c->lam[1]);
+      }
+      {
+        TimedLaunch tl(c, 0);
+        launch_slab_f64(c->stream, c->t1, s, c->Wu[0], c->Wu[1], c->ldw, n, B, false, nullptr, nullptr);
+      }
+    }
+    return hip_check(hipGetLastError(), "apply_prec launch");
+  }
   auto mode = [&](const double *X, double *Y, const double *W, int l) {
     TimedLaunch tl(c, 0);
     if (l == 0) {
@@ -226,6 +253,7 @@ int do_matvec(fdg_ctx *c, const double *x, double *y) {
 int ensure_krylov(fdg_ctx *c, int m) {
   if (c->restart_alloc >= m) return FDG_OK;
   dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol); dfree(c->ydev);
+  dfree(c->hbuf);
   if (c->hpin) { (void)hipHostFree(c->hpin); c->hpin = nullptr; }
   c->restart_alloc = 0;
   const size_t NB = (size_t)c->N * c->batch;
@@ -238,6 +266,7 @@ int ensure_krylov(fdg_ctx *c, int m) {
   if ((st = dalloc(&c->P3, (size_t)G * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->Hcol, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->ydev, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
+  if ((st = dalloc(&c->hbuf, (size_t)2 * (m + 2) * c->batch)) != FDG_OK) return st;
   HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * (size_t)(2 * m + 8) * c->batch, hipHostMallocDefault));
   c->restart_alloc = m;
   return FDG_OK;
@@ -258,7 +287,7 @@ int device_norm(fdg_ctx *c, const double *v) {
   }
   {
     TimedLaunch tl(c, 2);
-    launch_finalize_norm(c->stream, c->P3, G, 1, c->Hcol);
+    launch_reduce(c->stream, c->P3, G, 1, 1, c->Hcol, 1, true, nullptr, 0, nullptr, 0);
   }
   return read_scalars(c, c->Hcol, 1);
 }
@@ -308,6 +337,7 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
   if (c->t32a) (void)hipFree(c->t32a);
   if (c->t32b) (void)hipFree(c->t32b);
   dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol); dfree(c->ydev);
+  dfree(c->hbuf);
   if (c->hpin) (void)hipHostFree(c->hpin);
   for (auto &t : c->timers) {
     for (auto e : t.pool) (void)hipEventDestroy(e);
@@ -403,6 +433,10 @@ extern "C" int fdg_set_operator_kron(fdg_ctx *c, int l, const double *M, const d
     hi[i] = b;
     w = std::max(w, b - a + 1);
   }
+  for (int i = 1; i < n; ++i)
+    if (lo[i] < lo[i - 1])
+      return set_error(FDG_EINVAL, "set_operator_kron: band starts must not decrease (row %d)", i);
+  if (w > kron_window_max()) return set_error(FDG_EINVAL, "set_operator_kron: band wider than %d", kron_window_max());
   std::vector<double> bm((size_t)n * w, 0.0), bk((size_t)n * w, 0.0);
   std::vector<int32_t> blo(n);
   for (int i = 0; i < n; ++i) {
@@ -543,16 +577,13 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       }
       {
         TimedLaunch tl(c, 2);
-        launch_finalize_norm(c->stream, c->P3, G, 1, c->Hcol);
+        launch_reduce(c->stream, c->P3, G, 1, 1, c->Hcol, 1, true, nullptr, 0, nullptr, 0);
       }
       if ((st = read_scalars(c, c->Hcol, 1)) != FDG_OK) return st;
       beta = c->hpin[0];
     } else {
+      // r = b; Hcol[0] still holds ||b|| from the norm above
       HIPCHK(hipMemcpyAsync(Vq(0), b, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
-      {
-        TimedLaunch tl(c, 2);
-        launch_finalize_norm(c->stream, c->P3, G, 1, c->Hcol);  // ||b|| partials are still in P3
-      }
       beta = bnorm;
     }
     inf.rel_res_true = beta / bnorm;
@@ -573,25 +604,34 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       if ((st = do_matvec(c, Zq(j), Vq(j + 1))) != FDG_OK) return st;
       double *w = Vq(j + 1);
       const int nv = j + 1;
-      {
+      double *h1 = c->hbuf, *h2 = c->hbuf + (m + 2);
+      {  // classical Gram-Schmidt, first pass: h1 = V^T w, w -= V h1
         TimedLaunch tl(c, 2);
         launch_dots(c->stream, V, N, nv, w, N, 1, G, c->P1);
       }
       {
         TimedLaunch tl(c, 2);
-        launch_update(c->stream, V, N, nv, c->P1, G, w, N, 1, nullptr);
+        launch_reduce(c->stream, c->P1, G, nv, 1, h1, 0, false, nullptr, 0, nullptr, 0);
       }
       {
+        TimedLaunch tl(c, 2);
+        launch_update(c->stream, V, N, nv, h1, 0, w, N, 1, G, nullptr);
+      }
+      {  // reorthogonalisation: h2 = V^T w, w -= V h2; Hessenberg column h1 + h2
         TimedLaunch tl(c, 2);
         launch_dots(c->stream, V, N, nv, w, N, 1, G, c->P2);
       }
       {
         TimedLaunch tl(c, 2);
-        launch_update(c->stream, V, N, nv, c->P2, G, w, N, 1, c->P3);
+        launch_reduce(c->stream, c->P2, G, nv, 1, h2, 0, false, h1, 0, c->Hcol, 0);
       }
       {
         TimedLaunch tl(c, 2);
-        launch_finalize_h(c->stream, c->P1, c->P2, c->P3, G, nv, 1, c->Hcol);
+        launch_update(c->stream, V, N, nv, h2, 0, w, N, 1, G, c->P3);
+      }
+      {  // h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}
+        TimedLaunch tl(c, 2);
+        launch_reduce(c->stream, c->P3, G, 1, 1, c->Hcol + nv, 0, true, nullptr, 0, nullptr, 0);
       }
       {
         TimedLaunch tl(c, 2);

@@ -1,0 +1,326 @@
+// Fused FP64 fast-diagonalization solve (eq. 4.9 in 3D, eq. 4.7 in 2D) on MFMA.
+//
+// The tensor X[b][i3][i2][i1] (i1 fastest) is processed in three passes:
+//   pass A ("slab"):  per i3-slab, Y = W2 . X_slab . W1^T  -- modes 1 and 2 with V_1^T, V_2^T
+//   pass B ("fibre"): per block of (i2, i1) columns, T = W3a . X_cols, T /= Lambda,
+//                     S = W3b . T                        -- mode 3 with V_3^T, divide, U_3
+//   pass C ("slab"):  modes 1 and 2 with U_1, U_2
+// In 2D pass A also applies the divide by lambda_2[k2] + lambda_1[k1] and pass B is absent.
+// Each pass reads and writes the tensor once; the intermediate of the two chained
+// contractions lives in LDS.
+//
+// v_mfma_f64_16x16x4_f64 lane layout (li = lane % 16, lg = lane / 16):
+//   A[m = li][k = lg], B[k = lg][n = li], D[m = lg + 4 r][n = li] in register r.
+// The contraction index is permuted so that each lane reads four consecutive elements:
+// over the four MFMAs t = 0..3 of a 16-wide k-block starting at j0, lane group lg
+// supplies contraction index j0 + 4 lg + t to both operands.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fd_apply.h"
+
+namespace fdg {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kBlock = 256;  // 4 waves
+constexpr int kNT = 2;       // 16-column MFMA tiles per wave
+constexpr int kNB = 16 * kNT;  // columns per workgroup
+
+__device__ inline dbl4 mfma(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Four consecutive doubles p[0..3], zero where the index j + t >= jmax or !ok.
+template <bool VEC>
+__device__ inline void load4(const double *p, int j, int jmax, bool ok, double (&v)[4]) {
+  if (VEC && ok && j + 3 < jmax) {
+    const dbl4 x = *reinterpret_cast<const dbl4 *>(p);
+    v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = (ok && j + t < jmax) ? p[t] : 0.0;
+  }
+}
+
+__device__ inline void load4_pad(const double *p, double (&v)[4]) {  // always in bounds, 32-B aligned
+  const dbl4 x = *reinterpret_cast<const dbl4 *>(p);
+  v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+}
+
+// ------------------------------------------------------------------------------------
+// Pass A / C.  Workgroup = (slab s, column block cb); wave w owns rows
+// [w*MT*16, (w+1)*MT*16) of both contractions and all kNB columns.
+//   GEMM1: Y1[i2][c] = sum_i1 X[s][i2][i1] W1[c][i1]      (A = X rows, B = W1 rows)
+//   GEMM2: Y2[k2][c] = sum_i2 W2[k2][i2] Y1[i2][c]        (A = W2 rows, B = Y1 from LDS)
+//   2D divide: Y2[k2][c] /= lam2[k2] + lam1[c].
+// ------------------------------------------------------------------------------------
+template <int MT, bool VEC, bool DIV>
+__global__ __launch_bounds__(kBlock) void k_slab(const double *__restrict__ X, double *__restrict__ Y,
+                                                 const double *__restrict__ W1, const double *__restrict__ W2,
+                                                 int ldw, int n, int64_t nslab, int ncb, int xcd_remap,
+                                                 const double *__restrict__ lam1, const double *__restrict__ lam2) {
+  constexpr int MPAD = 4 * MT * 16;
+  constexpr int LDP = MPAD + 2;
+  __shared__ double y1t[kNB * LDP];  // Y1 transposed: y1t[c][i2]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  int64_t s;
+  int cb;
+  {
+    const int64_t bid = blockIdx.x;
+    if (xcd_remap) {  // the ncb workgroups of one slab share an XCD (and its L2)
+      const int64_t xcd = bid & 7, local = bid >> 3;
+      s = (local / ncb) * 8 + xcd;
+      cb = (int)(local % ncb);
+    } else {
+      s = bid / ncb;
+      cb = (int)(bid % ncb);
+    }
+  }
+  if (s >= nslab) return;
+  const int64_t n2 = (int64_t)n * n;
+  const double *Xs = X + s * n2;
+  double *Ys = Y + s * n2;
+  const int c0 = cb * kNB;
+  const int m0 = wave * MT * 16;
+  const int kpad = (n + 15) & ~15;
+
+  // ---- GEMM1 ----
+  dbl4 acc[MT][kNT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < kpad; j0 += 16) {
+    const int j = j0 + 4 * lg;
+    double av[MT][4], bv[kNT][4];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      const int row = m0 + 16 * a + li;
+      load4<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, av[a]);
+    }
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) load4_pad(W1 + (size_t)(c0 + 16 * b + li) * ldw + j, bv[b]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(av[a][t], bv[b][t], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y1t[(16 * b + li) * LDP + m0 + 16 * a + lg + 4 * r] = acc[a][b][r];
+  __syncthreads();
+
+  // ---- GEMM2 ----
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < kpad; j0 += 16) {
+    const int j = j0 + 4 * lg;
+    double av[MT][4], bv[kNT][4];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + j, av[a]);
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) {
+      const double *p = y1t + (16 * b + li) * LDP + j;
+      bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(av[a][t], bv[b][t], acc[a][b]);
+  }
+#pragma unroll
+  for (int b = 0; b < kNT; ++b) {
+    const int c = c0 + 16 * b + li;
+    if (c >= n) continue;
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k2 = m0 + 16 * a + lg + 4 * r;
+        if (k2 < n) {
+          double v = acc[a][b][r];
+          if (DIV) v = v / (lam2[k2] + lam1[c]);
+          Ys[(int64_t)k2 * n + c] = v;
+        }
+      }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Pass B.  Workgroup = (batch entry b, block of kNB columns c of the n x n^2 matrix
+// X[b][i3][c]).  The column block is staged in LDS transposed (xt[c][i3]); then
+//   GEMM1: T[k3][c] = sum_i3 Wa[k3][i3] X[i3][c];   T /= lam3[k3] + lam2[i2] + lam1[i1]
+//   GEMM2: S[k3][c] = sum_k Wb[k3][k] T[k][c]        (T back in LDS, transposed)
+// ------------------------------------------------------------------------------------
+template <int MT>
+__global__ __launch_bounds__(kBlock) void k_fibre(const double *__restrict__ X, double *__restrict__ Y,
+                                                  const double *__restrict__ Wa, const double *__restrict__ Wb,
+                                                  int ldw, int n, int ncb, const double *__restrict__ lam1,
+                                                  const double *__restrict__ lam2, const double *__restrict__ lam3) {
+  constexpr int MPAD = 4 * MT * 16;
+  constexpr int LDP = MPAD + 2;
+  __shared__ double xt[kNB * LDP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t bidx = blockIdx.x / ncb;
+  const int cb = (int)(blockIdx.x % ncb);
+  const int64_t n2 = (int64_t)n * n;
+  const double *Xb = X + bidx * n2 * n;
+  double *Yb = Y + bidx * n2 * n;
+  const int64_t c0 = (int64_t)cb * kNB;
+  const int m0 = wave * MT * 16;
+  const int kpad = (n + 15) & ~15;
+  // stage X[i3][c0 .. c0+kNB) -> xt[c][i3], zero beyond n or n^2
+  for (int e = threadIdx.x; e < kpad * kNB; e += kBlock) {
+    const int i3 = e / kNB, c = e % kNB;
+    const int64_t cg = c0 + c;
+    xt[c * LDP + i3] = (i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0;
+  }
+  __syncthreads();
+  dbl4 acc[MT][kNT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < kpad; j0 += 16) {
+    const int j = j0 + 4 * lg;
+    double av[MT][4], bv[kNT][4];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) load4_pad(Wa + (size_t)(m0 + 16 * a + li) * ldw + j, av[a]);
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) {
+      const double *p = xt + (16 * b + li) * LDP + j;
+      bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(av[a][t], bv[b][t], acc[a][b]);
+  }
+  __syncthreads();  // every wave has finished reading xt
+#pragma unroll
+  for (int b = 0; b < kNT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    const bool cok = cg < n2;
+    const int i2 = cok ? (int)(cg / n) : 0, i1 = cok ? (int)(cg % n) : 0;
+    const double l12 = lam2[i2] + lam1[i1];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k3 = m0 + 16 * a + lg + 4 * r;
+        // rows k3 >= n are zero (zero-padded Wa); lam3 is padded with 1
+        xt[(16 * b + li) * LDP + k3] = acc[a][b][r] / (lam3[k3] + l12);
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < kpad; j0 += 16) {
+    const int j = j0 + 4 * lg;
+    double av[MT][4], bv[kNT][4];
+#pragma unroll
+    for (int a = 0; a < MT; ++a) load4_pad(Wb + (size_t)(m0 + 16 * a + li) * ldw + j, av[a]);
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) {
+      const double *p = xt + (16 * b + li) * LDP + j;
+      bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(av[a][t], bv[b][t], acc[a][b]);
+  }
+#pragma unroll
+  for (int b = 0; b < kNT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    if (cg >= n2) continue;
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k3 = m0 + 16 * a + lg + 4 * r;
+        if (k3 < n) Yb[(int64_t)k3 * n2 + cg] = acc[a][b][r];
+      }
+  }
+}
+
+template <int MT>
+void slab_launch(hipStream_t s, const double *X, double *Y, const double *W1, const double *W2, int ldw, int n,
+                 int64_t nslab, bool div, const double *lam1, const double *lam2) {
+  const int ncb = (n + kNB - 1) / kNB;
+  const int64_t nwg = nslab * ncb;
+  const int remap = (nslab % 8 == 0) ? 1 : 0;
+  const bool vec = (n % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 31) == 0);
+  const dim3 grid((unsigned)nwg), blk(kBlock);
+  if (div) {
+    if (vec)
+      hipLaunchKernelGGL((k_slab<MT, true, true>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1, lam2);
+    else
+      hipLaunchKernelGGL((k_slab<MT, false, true>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1, lam2);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((k_slab<MT, true, false>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1, lam2);
+    else
+      hipLaunchKernelGGL((k_slab<MT, false, false>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1, lam2);
+  }
+}
+
+template <int MT>
+void fibre_launch(hipStream_t s, const double *X, double *Y, const double *Wa, const double *Wb, int ldw, int n,
+                  int64_t batch, const double *lam1, const double *lam2, const double *lam3) {
+  const int64_t n2 = (int64_t)n * n;
+  const int ncb = (int)((n2 + kNB - 1) / kNB);
+  const dim3 grid((unsigned)(batch * ncb)), blk(kBlock);
+  hipLaunchKernelGGL((k_fibre<MT>), grid, blk, 0, s, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
+}
+
+}  // namespace
+
+bool fd_fused_supported(int n) { return n >= 1 && n <= 256; }
+
+void launch_slab_f64(hipStream_t s, const double *X, double *Y, const double *W1, const double *W2, int ldw, int n,
+                     int64_t nslab, bool divide, const double *lam1, const double *lam2) {
+  if (n <= 64)
+    slab_launch<1>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);
+  else if (n <= 128)
+    slab_launch<2>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);
+  else if (n <= 192)
+    slab_launch<3>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);
+  else
+    slab_launch<4>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);
+}
+
+void launch_fibre_f64(hipStream_t s, const double *X, double *Y, const double *Wa, const double *Wb, int ldw, int n,
+                      int64_t batch, const double *lam1, const double *lam2, const double *lam3) {
+  if (n <= 64)
+    fibre_launch<1>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);
+  else if (n <= 128)
+    fibre_launch<2>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);
+  else if (n <= 192)
+    fibre_launch<3>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);
+  else
+    fibre_launch<4>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);
+}
+
+}  // namespace fdg

@@ -32,8 +32,10 @@ struct KronBands {
   const int32_t *lo[3];
   int w[3];
 };
+// Requires non-decreasing band starts lo[] and w <= kron_window_max().
 void launch_kron_matvec_f64(hipStream_t s, const double *x, double *y, int d, int n, int64_t nbatch,
                             const KronBands &bands);
+int kron_window_max();
 
 // Slot-major ELL: entry (row, slot) at col[slot*ld + row], val[slot*ld + row].
 void launch_ell_matvec_f64(hipStream_t s, const double *x, double *y, int64_t nrows, int64_t ld,
@@ -44,15 +46,13 @@ void launch_ell_matvec_f64(hipStream_t s, const double *x, double *y, int64_t nr
 // Partial sums of batch entry b, block g, component q at P[(b*G + g)*nv + q].
 void launch_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *w, int64_t N,
                  int64_t nbatch, int G, double *P);
-// w -= sum_q V_q h_q with h_q = sum_g Pin[..] (fixed order); with Pnorm != NULL also
-// the partial sums of |w|^2 (one component).
-void launch_update(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G,
-                   double *w, int64_t N, int64_t nbatch, double *Pnorm);
-// Hcol[b*(nv+1) + q] = sum_g P1 + sum_g P2 (q < nv);  Hcol[b*(nv+1) + nv] = sqrt(sum_g P3).
-void launch_finalize_h(hipStream_t s, const double *P1, const double *P2, const double *P3, int G,
-                       int nv, int64_t nbatch, double *Hcol);
-// out[b] = sqrt(sum_g P[b*G + g]).
-void launch_finalize_norm(hipStream_t s, const double *P, int G, int64_t nbatch, double *out);
+// out[b*ostride + q] = sum_g P (sqrt of it if do_sqrt), q < ncomp; with add != NULL also
+// out2[b*o2stride + q] = sum + add[b*astride + q].
+void launch_reduce(hipStream_t s, const double *P, int G, int ncomp, int64_t nbatch, double *out,
+                   int ostride, bool do_sqrt, const double *add, int astride, double *out2, int o2stride);
+// w -= sum_q V_q h[b*hstride + q]; with Pnorm != NULL also the partial sums of |w|^2.
+void launch_update(hipStream_t s, const double *V, int64_t ldv, int nv, const double *h, int hstride,
+                   double *w, int64_t N, int64_t nbatch, int G, double *Pnorm);
 // v = w / nrm[b*nstride] (0 where nrm is 0).
 void launch_scale(hipStream_t s, const double *w, double *v, const double *nrm, int nstride,
                   int64_t N, int64_t nbatch);

@@ -1,0 +1,232 @@
+// Operator matvecs: the unit-domain collocation matrix of eq. 2.9 / 2.7 applied from its
+// banded univariate factors, and a slot-major ELL matvec for an assembled matrix.
+//
+// Unit domain, 3D: y = (K3 x M2 x M1 + M3 x K2 x M1 + M3 x M2 x K1) x, sum-factorised.
+// One thread owns an output column (i2, i1) and sweeps a chunk of i3.  For every plane
+// j3 it needs, it forms the direction-1 band sums sM = M1 x, sK = K1 x on the rows
+// j2 of the i2 band and then the direction-2 sums
+//     a(j3)  = sum_j2 M2 sM,      c(j3) = sum_j2 (K2 sM + M2 sK);
+// the output is y(i3) = sum_j3 K3 a(j3) + M3 c(j3).  Band starts are non-decreasing in
+// the row index, so the planes j3 a chunk needs form a sliding window kept in registers:
+// each output row costs one new plane (2 w1 w2 + 3 w2 FMAs) plus 2 w3 FMAs.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace fdg {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kChunk = 16;  // output rows of the sweep direction per thread
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <int WMAX>
+__global__ __launch_bounds__(kBlock) void k_kron3_window(const double *__restrict__ x, double *__restrict__ y,
+                                                         int n, KronBands bd) {
+  const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // i2 * n + i1
+  const int64_t n2 = (int64_t)n * n;
+  if (col >= n2) return;
+  const int s = blockIdx.y * kChunk;
+  const int e = s + kChunk < n ? s + kChunk : n;
+  const int64_t b = blockIdx.z;
+  const int i1 = (int)(col % n), i2 = (int)(col / n);
+  const double *xb = x + b * n2 * n;
+  double *yb = y + b * n2 * n;
+  const int w1 = bd.w[0], w2 = bd.w[1], w3 = bd.w[2];
+  double m1[WMAX], k1[WMAX], m2[WMAX], k2[WMAX];
+#pragma unroll
+  for (int t = 0; t < WMAX; ++t) {
+    m1[t] = t < w1 ? bd.M[0][(size_t)i1 * w1 + t] : 0.0;
+    k1[t] = t < w1 ? bd.K[0][(size_t)i1 * w1 + t] : 0.0;
+    m2[t] = t < w2 ? bd.M[1][(size_t)i2 * w2 + t] : 0.0;
+    k2[t] = t < w2 ? bd.K[1][(size_t)i2 * w2 + t] : 0.0;
+  }
+  const int lo1 = bd.lo[0][i1], lo2 = bd.lo[1][i2];
+  auto plane = [&](int j3, double &a, double &c) {
+    a = 0.0;
+    c = 0.0;
+    const double *xp = xb + (int64_t)j3 * n2 + (int64_t)lo2 * n + lo1;
+#pragma unroll
+    for (int t2 = 0; t2 < WMAX; ++t2) {
+      if (t2 < w2) {
+        const double *xr = xp + (int64_t)t2 * n;
+        double sm = 0.0, sk = 0.0;
+#pragma unroll
+        for (int t1 = 0; t1 < WMAX; ++t1) {
+          if (t1 < w1) {
+            const double v = xr[t1];
+            sm = fma(m1[t1], v, sm);
+            sk = fma(k1[t1], v, sk);
+          }
+        }
+        a = fma(m2[t2], sm, a);
+        c = fma(k2[t2], sm, c);
+        c = fma(m2[t2], sk, c);
+      }
+    }
+  };
+  // window: slots WMAX-w3 .. WMAX-1 hold planes base .. base+w3-1
+  double A[WMAX], C[WMAX];
+  int base = bd.lo[2][s];
+#pragma unroll
+  for (int u = 0; u < WMAX; ++u) {
+    const int t = u - (WMAX - w3);
+    if (t >= 0) {
+      plane(base + t, A[u], C[u]);
+    } else {
+      A[u] = 0.0;
+      C[u] = 0.0;
+    }
+  }
+  for (int i3 = s; i3 < e; ++i3) {
+    const int target = bd.lo[2][i3];
+    while (base < target) {
+#pragma unroll
+      for (int u = 0; u < WMAX - 1; ++u) {
+        A[u] = A[u + 1];
+        C[u] = C[u + 1];
+      }
+      plane(base + w3, A[WMAX - 1], C[WMAX - 1]);
+      ++base;
+    }
+    const double *m3 = bd.M[2] + (size_t)i3 * w3;
+    const double *k3 = bd.K[2] + (size_t)i3 * w3;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < WMAX; ++u) {
+      const int t = u - (WMAX - w3);
+      if (t >= 0) {
+        acc = fma(k3[t], A[u], acc);
+        acc = fma(m3[t], C[u], acc);
+      }
+    }
+    yb[(int64_t)i3 * n2 + col] = acc;
+  }
+}
+
+// 2D: one thread owns column i1 and sweeps a chunk of i2; window of direction-1 band sums.
+template <int WMAX>
+__global__ __launch_bounds__(kBlock) void k_kron2_window(const double *__restrict__ x, double *__restrict__ y,
+                                                         int n, KronBands bd) {
+  const int i1 = blockIdx.x * kBlock + threadIdx.x;
+  if (i1 >= n) return;
+  const int s = blockIdx.y * kChunk;
+  const int e = s + kChunk < n ? s + kChunk : n;
+  const int64_t b = blockIdx.z;
+  const int64_t N = (int64_t)n * n;
+  const double *xb = x + b * N;
+  double *yb = y + b * N;
+  const int w1 = bd.w[0], w2 = bd.w[1];
+  double m1[WMAX], k1[WMAX];
+#pragma unroll
+  for (int t = 0; t < WMAX; ++t) {
+    m1[t] = t < w1 ? bd.M[0][(size_t)i1 * w1 + t] : 0.0;
+    k1[t] = t < w1 ? bd.K[0][(size_t)i1 * w1 + t] : 0.0;
+  }
+  const int lo1 = bd.lo[0][i1];
+  auto row = [&](int j2, double &sm, double &sk) {
+    sm = 0.0;
+    sk = 0.0;
+    const double *xr = xb + (int64_t)j2 * n + lo1;
+#pragma unroll
+    for (int t1 = 0; t1 < WMAX; ++t1)
+      if (t1 < w1) {
+        const double v = xr[t1];
+        sm = fma(m1[t1], v, sm);
+        sk = fma(k1[t1], v, sk);
+      }
+  };
+  double SM[WMAX], SK[WMAX];
+  int base = bd.lo[1][s];
+#pragma unroll
+  for (int u = 0; u < WMAX; ++u) {
+    const int t = u - (WMAX - w2);
+    if (t >= 0) {
+      row(base + t, SM[u], SK[u]);
+    } else {
+      SM[u] = 0.0;
+      SK[u] = 0.0;
+    }
+  }
+  for (int i2 = s; i2 < e; ++i2) {
+    const int target = bd.lo[1][i2];
+    while (base < target) {
+#pragma unroll
+      for (int u = 0; u < WMAX - 1; ++u) {
+        SM[u] = SM[u + 1];
+        SK[u] = SK[u + 1];
+      }
+      row(base + w2, SM[WMAX - 1], SK[WMAX - 1]);
+      ++base;
+    }
+    const double *m2 = bd.M[1] + (size_t)i2 * w2;
+    const double *k2 = bd.K[1] + (size_t)i2 * w2;
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < WMAX; ++u) {
+      const int t = u - (WMAX - w2);
+      if (t >= 0) {
+        acc = fma(k2[t], SM[u], acc);
+        acc = fma(m2[t], SK[u], acc);
+      }
+    }
+    yb[(int64_t)i2 * n + i1] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ell_f64(const double *__restrict__ x, double *__restrict__ y,
+                                                    int64_t nrows, int64_t ld, int width,
+                                                    const int32_t *__restrict__ col,
+                                                    const double *__restrict__ val, int64_t total) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t b = idx / nrows, row = idx - b * nrows;
+  const double *xb = x + b * nrows;
+  double acc = 0.0;
+  for (int t = 0; t < width; ++t) {
+    const int64_t e = (int64_t)t * ld + row;
+    acc = fma(val[e], xb[col[e]], acc);
+  }
+  y[idx] = acc;
+}
+
+}  // namespace
+
+int kron_window_max() { return 16; }
+
+void launch_kron_matvec_f64(hipStream_t s, const double *x, double *y, int d, int n, int64_t nbatch,
+                            const KronBands &bd) {
+  int w = 0;
+  for (int l = 0; l < d; ++l) w = bd.w[l] > w ? bd.w[l] : w;
+  const dim3 blk(kBlock);
+  if (d == 3) {
+    const dim3 grid(cdiv((int64_t)n * n, kBlock), cdiv(n, kChunk), (unsigned)nbatch);
+    if (w <= 4)
+      hipLaunchKernelGGL(k_kron3_window<4>, grid, blk, 0, s, x, y, n, bd);
+    else if (w <= 8)
+      hipLaunchKernelGGL(k_kron3_window<8>, grid, blk, 0, s, x, y, n, bd);
+    else
+      hipLaunchKernelGGL(k_kron3_window<16>, grid, blk, 0, s, x, y, n, bd);
+  } else {
+    const dim3 grid(cdiv(n, kBlock), cdiv(n, kChunk), (unsigned)nbatch);
+    if (w <= 4)
+      hipLaunchKernelGGL(k_kron2_window<4>, grid, blk, 0, s, x, y, n, bd);
+    else if (w <= 8)
+      hipLaunchKernelGGL(k_kron2_window<8>, grid, blk, 0, s, x, y, n, bd);
+    else
+      hipLaunchKernelGGL(k_kron2_window<16>, grid, blk, 0, s, x, y, n, bd);
+  }
+}
+
+void launch_ell_matvec_f64(hipStream_t s, const double *x, double *y, int64_t nrows, int64_t ld, int width,
+                           const int32_t *col, const double *val, int64_t nbatch) {
+  const int64_t total = nrows * nbatch;
+  hipLaunchKernelGGL(k_ell_f64, dim3(cdiv(total, kBlock)), dim3(kBlock), 0, s, x, y, nrows, ld, width, col, val,
+                     total);
+}
+
+}  // namespace fdg

@@ -25,6 +25,8 @@ def _fdg():
 @pytest.mark.parametrize("d,p,n,batch", [
     (2, 3, 33, 1), (3, 4, 16, 1), (3, 3, 33, 2), (2, 5, 47, 3), (3, 6, 20, 1),
     (2, 2, 64, 1), (3, 2, 17, 1), (2, 4, 130, 2), (3, 4, 70, 1),
+    (2, 2, 1, 2), (3, 3, 5, 1), (3, 3, 65, 1), (2, 4, 256, 2), (2, 3, 260, 1), (3, 5, 129, 1),
+    (3, 4, 128, 1),
 ])
 def test_apply_prec_fp64(d, p, n, batch):
     fdg = _fdg()
