@@ -43,8 +43,8 @@ def fgmres(matvec, prec, b, rtol=1e-8, restart=30, maxit=1000, x0=None, iters=No
     restarts = 0
     hist = []
     limit = maxit if iters is None else iters
-    if bnorm == 0.0:
-        return x, dict(iterations=0, restarts=0, history=[], rel_res=0.0, converged=True)
+    if bnorm == 0.0:                                # A nonsingular: A x = 0 has x = 0
+        return np.zeros(N), dict(iterations=0, restarts=0, history=[], rel_res=0.0, converged=True)
     while True:
         r = b - matvec(x) if np.any(x) else b.copy()
         beta = np.linalg.norm(r)

@@ -49,6 +49,8 @@ struct fdg_ctx {
   double *bandM[3] = {nullptr, nullptr, nullptr}, *bandK[3] = {nullptr, nullptr, nullptr};
   int32_t *bandlo[3] = {nullptr, nullptr, nullptr};
   int bandw[3] = {0, 0, 0};
+  int bandrows4[3] = {0, 0, 0}, bandrows16[3] = {0, 0, 0}, bandstep[3] = {0, 0, 0};
+  double *mv_a = nullptr, *mv_c = nullptr;  // two-pass Kronecker matvec intermediates
   int32_t *ell_col = nullptr;
   double *ell_val = nullptr;
   int ell_width = 0;
@@ -57,8 +59,10 @@ struct fdg_ctx {
   void *t32a = nullptr, *t32b = nullptr;
   int restart_alloc = 0;
   double *Vb = nullptr, *Zb = nullptr, *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *Hcol = nullptr,
-         *ydev = nullptr, *hbuf = nullptr;
-  double *hpin = nullptr;  // pinned host staging
+         *ydev = nullptr, *hbuf = nullptr, *scal = nullptr;
+  double *hpin = nullptr;      // pinned, device-mapped host memory for the scalars the host needs
+  double *hpin_dev = nullptr;  // its device address
+  unsigned *counters = nullptr;  // last-block counters of the reductions
   TimerState timers[kTimerClasses];
 };
 
@@ -243,7 +247,15 @@ int do_matvec(fdg_ctx *c, const double *x, double *y) {
       bd.lo[l] = c->bandlo[q];
       bd.w[l] = c->bandw[q];
     }
-    launch_kron_matvec_f64(c->stream, x, y, c->d, c->n, c->batch, bd);
+    bd.rows4 = c->bandrows4[c->d == 3 ? 1 : 0];
+    bd.rows16 = c->bandrows16[c->d == 3 ? 1 : 0];
+    bd.step3 = c->bandstep[c->d == 3 ? 2 : 0];
+    if (c->d == 3) {
+      int st = dalloc(&c->mv_a, (size_t)c->N * c->batch);
+      if (st == FDG_OK) st = dalloc(&c->mv_c, (size_t)c->N * c->batch);
+      if (st != FDG_OK) return st;
+    }
+    launch_kron_matvec_f64(c->stream, x, y, c->d, c->n, c->batch, bd, c->mv_a, c->mv_c);
   } else {
     launch_ell_matvec_f64(c->stream, x, y, c->N, c->N, c->ell_width, c->ell_col, c->ell_val, c->batch);
   }
@@ -253,8 +265,9 @@ int do_matvec(fdg_ctx *c, const double *x, double *y) {
 int ensure_krylov(fdg_ctx *c, int m) {
   if (c->restart_alloc >= m) return FDG_OK;
   dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol); dfree(c->ydev);
-  dfree(c->hbuf);
+  dfree(c->hbuf); dfree(c->scal);
   if (c->hpin) { (void)hipHostFree(c->hpin); c->hpin = nullptr; }
+  dfree(c->counters);
   c->restart_alloc = 0;
   const size_t NB = (size_t)c->N * c->batch;
   const int G = reduction_blocks(c->N);
@@ -267,30 +280,14 @@ int ensure_krylov(fdg_ctx *c, int m) {
   if ((st = dalloc(&c->Hcol, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->ydev, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->hbuf, (size_t)2 * (m + 2) * c->batch)) != FDG_OK) return st;
-  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * (size_t)(2 * m + 8) * c->batch, hipHostMallocDefault));
+  if ((st = dalloc(&c->scal, (size_t)4 * c->batch)) != FDG_OK) return st;
+  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * (size_t)(2 * m + 8) * c->batch, hipHostMallocMapped));
+  HIPCHK(hipHostGetDevicePointer((void **)&c->hpin_dev, c->hpin, 0));
+
   c->restart_alloc = m;
   return FDG_OK;
 }
 
-int read_scalars(fdg_ctx *c, const double *dev, int count) {
-  HIPCHK(hipMemcpyAsync(c->hpin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  return FDG_OK;
-}
-
-// ||v|| of a device vector (batch entry 0) into c->hpin[0].
-int device_norm(fdg_ctx *c, const double *v) {
-  const int G = reduction_blocks(c->N);
-  {
-    TimedLaunch tl(c, 2);
-    launch_dots(c->stream, v, 0, 1, v, c->N, 1, G, c->P3);
-  }
-  {
-    TimedLaunch tl(c, 2);
-    launch_reduce(c->stream, c->P3, G, 1, 1, c->Hcol, 1, true, nullptr, 0, nullptr, 0);
-  }
-  return read_scalars(c, c->Hcol, 1);
-}
 
 }  // namespace
 
@@ -333,12 +330,14 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
     dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandlo[l]);
   }
   dfree(c->ell_col); dfree(c->ell_val);
+  dfree(c->mv_a); dfree(c->mv_c);
   dfree(c->t1); dfree(c->t2);
   if (c->t32a) (void)hipFree(c->t32a);
   if (c->t32b) (void)hipFree(c->t32b);
   dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol); dfree(c->ydev);
-  dfree(c->hbuf);
+  dfree(c->hbuf); dfree(c->scal);
   if (c->hpin) (void)hipHostFree(c->hpin);
+  dfree(c->counters);
   for (auto &t : c->timers) {
     for (auto e : t.pool) (void)hipEventDestroy(e);
     for (auto e : t.pending) (void)hipEventDestroy(e);
@@ -456,6 +455,14 @@ extern "C" int fdg_set_operator_kron(fdg_ctx *c, int l, const double *M, const d
   HIPCHK(hipMemcpy(c->bandK[l], bk.data(), bk.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->bandlo[l], blo.data(), blo.size() * 4, hipMemcpyHostToDevice));
   c->bandw[l] = w;
+  int rows4 = 0;
+  for (int i = 0; i < n; ++i) rows4 = std::max(rows4, blo[std::min(i + 3, n - 1)] + w - blo[i]);
+  c->bandrows4[l] = rows4;
+  int rows16 = 0, step = 0;
+  for (int i = 0; i < n; i += 16) rows16 = std::max(rows16, blo[std::min(i + 15, n - 1)] + w - blo[i]);
+  for (int i = 0; i + 1 < n; ++i) step = std::max(step, blo[i + 1] - blo[i]);
+  c->bandrows16[l] = rows16;
+  c->bandstep[l] = step;
   c->have_op[l] = true;
   c->op_kind = 1;
   return FDG_OK;
@@ -542,34 +549,59 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   const int64_t N = c->N;
   const int G = reduction_blocks(N);
   const bool fixed = (flags & FDG_SOLVE_FIXED_ITERS) != 0;
-  const bool use_x0 = (flags & FDG_SOLVE_USE_X0) != 0;
   const int limit = maxit;
   double *V = c->Vb, *Z = c->Zb;
   auto Vq = [&](int q) { return V + (size_t)q * N; };
   auto Zq = [&](int q) { return Z + (size_t)q * N; };
+  double *bn_dev = c->scal, *beta_dev = c->scal + 1;
+  double *h1 = c->hbuf;
+  // host-mapped scalars: [0, m+2) Hessenberg column, m+2 ||b||, m+3 residual norm
+  volatile double *hcol_h = c->hpin, *bn_h = c->hpin + m + 2, *beta_h = c->hpin + m + 3;
+  double *hcol_d = c->hpin_dev, *bn_hd = c->hpin_dev + m + 2, *beta_hd = c->hpin_dev + m + 3;
 
-  if ((st = device_norm(c, b)) != FDG_OK) return st;
-  const double bnorm = c->hpin[0];
+  {  // partials of ||b||^2; reduced by the first scaling of b or read directly below
+    TimedLaunch tl(c, 2);
+    launch_dots(c->stream, b, 0, 1, b, N, 1, G, c->P3);
+  }
   fdg_info inf;
   std::memset(&inf, 0, sizeof(inf));
-  if (!use_x0) HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
-  if (bnorm == 0.0) {
-    if (!use_x0) HIPCHK(hipStreamSynchronize(c->stream));
-    inf.converged = 1;
+  double bnorm = -1.0, target = 0.0;
+  auto learn_bnorm = [&]() {  // ||b|| has arrived in host-mapped memory (after a sync)
+    bnorm = *bn_h;
+    target = rtol * bnorm;
+  };
+  auto finish = [&](bool converged) {
+    inf.converged = converged ? 1 : 0;
     inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
+    return converged ? FDG_OK : FDG_NOT_CONVERGED;
+  };
+  auto zero_x = [&]() -> int {
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return FDG_OK;
+  };
+  bool x_nonzero = (flags & FDG_SOLVE_USE_X0) != 0;
+  if (x_nonzero || limit == 0) {
+    TimedLaunch tl(c, 2);
+    launch_norm_reduce(c->stream, c->P3, G, 1, bn_dev, 0, bn_hd, 0);
   }
-  const double target = rtol * bnorm;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  if (!x_nonzero && limit == 0) {  // nothing to iterate: x = 0
+    HIPCHK(hipStreamSynchronize(c->stream));
+    learn_bnorm();
+    if ((st = zero_x()) != FDG_OK) return st;
+    inf.rel_res_true = bnorm > 0.0 ? 1.0 : 0.0;
+    return finish(bnorm == 0.0);
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+  Coeffs y;
   auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
   int total = 0, restarts = 0;
-  bool x_nonzero = use_x0;
-  double last_est = 1.0;
+  double last_est = 1.0, rbeta = 0.0;
   bool breakdown = false;
   while (true) {
-    double beta;
-    if (x_nonzero) {
+    double beta = 0.0;
+    if (x_nonzero) {  // r = b - A x, v0 = r / ||r||; ||r|| read on the host
       if ((st = do_matvec(c, x, c->t1)) != FDG_OK) return st;
       {
         TimedLaunch tl(c, 2);
@@ -577,26 +609,25 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       }
       {
         TimedLaunch tl(c, 2);
-        launch_reduce(c->stream, c->P3, G, 1, 1, c->Hcol, 1, true, nullptr, 0, nullptr, 0);
+        launch_scale_reduce(c->stream, Vq(0), Vq(0), c->P3, G, N, 1, beta_dev, 0, beta_hd, 0);
       }
-      if ((st = read_scalars(c, c->Hcol, 1)) != FDG_OK) return st;
-      beta = c->hpin[0];
-    } else {
-      // r = b; Hcol[0] still holds ||b|| from the norm above
-      HIPCHK(hipMemcpyAsync(Vq(0), b, sizeof(double) * N, hipMemcpyDeviceToDevice, c->stream));
-      beta = bnorm;
-    }
-    inf.rel_res_true = beta / bnorm;
-    if ((!fixed && beta <= target) || total >= limit) {
-      inf.converged = beta <= target;
-      break;
-    }
-    {
+      HIPCHK(hipStreamSynchronize(c->stream));
+      if (bnorm < 0.0) learn_bnorm();
+      beta = *beta_h;
+      if (bnorm == 0.0) {  // b = 0: the solution is x = 0 exactly
+        if ((st = zero_x()) != FDG_OK) return st;
+        inf.rel_res_true = 0.0;
+        return finish(true);
+      }
+      rbeta = beta;
+      inf.rel_res_true = beta / bnorm;
+      if ((!fixed && beta <= target) || total >= limit) break;
+    } else {  // x = 0: r = b, v0 = b / ||b|| (||b|| reaches the host with the first column)
       TimedLaunch tl(c, 2);
-      launch_scale(c->stream, Vq(0), Vq(0), c->Hcol, 0, N, 1);
+      launch_scale_reduce(c->stream, b, Vq(0), c->P3, G, N, 1, bn_dev, 0, bn_hd, 0);
     }
     std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
+    g[0] = beta;  // completed below when ||b|| arrives with the first column
     int k = 0;
     breakdown = false;
     for (int j = 0; j < m; ++j) {
@@ -604,42 +635,34 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       if ((st = do_matvec(c, Zq(j), Vq(j + 1))) != FDG_OK) return st;
       double *w = Vq(j + 1);
       const int nv = j + 1;
-      double *h1 = c->hbuf, *h2 = c->hbuf + (m + 2);
-      {  // classical Gram-Schmidt, first pass: h1 = V^T w, w -= V h1
+      {  // classical Gram-Schmidt: h1 = V^T w
         TimedLaunch tl(c, 2);
         launch_dots(c->stream, V, N, nv, w, N, 1, G, c->P1);
       }
-      {
+      {  // w -= V h1; h2 = V^T w (reorthogonalisation)
         TimedLaunch tl(c, 2);
-        launch_reduce(c->stream, c->P1, G, nv, 1, h1, 0, false, nullptr, 0, nullptr, 0);
+        launch_update_dots(c->stream, V, N, nv, c->P1, G, w, N, 1, c->P2, h1, 0);
       }
-      {
+      {  // w -= V h2; Hessenberg column h1 + h2 to the host; ||w||
         TimedLaunch tl(c, 2);
-        launch_update(c->stream, V, N, nv, h1, 0, w, N, 1, G, nullptr);
-      }
-      {  // reorthogonalisation: h2 = V^T w, w -= V h2; Hessenberg column h1 + h2
-        TimedLaunch tl(c, 2);
-        launch_dots(c->stream, V, N, nv, w, N, 1, G, c->P2);
-      }
-      {
-        TimedLaunch tl(c, 2);
-        launch_reduce(c->stream, c->P2, G, nv, 1, h2, 0, false, h1, 0, c->Hcol, 0);
-      }
-      {
-        TimedLaunch tl(c, 2);
-        launch_update(c->stream, V, N, nv, h2, 0, w, N, 1, G, c->P3);
+        launch_update_norm(c->stream, V, N, nv, c->P2, G, w, N, 1, c->P3, h1, c->Hcol, 0, hcol_d, 0);
       }
       {  // h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}
         TimedLaunch tl(c, 2);
-        launch_reduce(c->stream, c->P3, G, 1, 1, c->Hcol + nv, 0, true, nullptr, 0, nullptr, 0);
-      }
-      {
-        TimedLaunch tl(c, 2);
-        launch_scale(c->stream, w, w, c->Hcol + nv, 0, N, 1);
+        launch_scale_reduce(c->stream, w, w, c->P3, G, N, 1, c->Hcol + nv, 0, hcol_d + nv, 0);
       }
       HIPCHK(hipGetLastError());
-      if ((st = read_scalars(c, c->Hcol, nv + 1)) != FDG_OK) return st;
-      for (int q = 0; q <= nv; ++q) Hij(q, j) = c->hpin[q];
+      HIPCHK(hipStreamSynchronize(c->stream));
+      if (bnorm < 0.0) {
+        learn_bnorm();
+        g[0] = bnorm;
+        if (bnorm == 0.0) {  // b = 0: x = 0 exactly
+          if ((st = zero_x()) != FDG_OK) return st;
+          inf.rel_res_true = 0.0;
+          return finish(true);
+        }
+      }
+      for (int q = 0; q <= nv; ++q) Hij(q, j) = hcol_h[q];
       double wn0 = 0.0;
       for (int q = 0; q <= nv; ++q) wn0 += Hij(q, j) * Hij(q, j);
       wn0 = std::sqrt(wn0);
@@ -670,27 +693,37 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       if (!fixed && std::fabs(g[j + 1]) <= target) break;
     }
     for (int i = k - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int q = i + 1; q < k; ++q) s -= Hij(i, q) * y[q];
-      y[i] = s / Hij(i, i);
+      double sacc = g[i];
+      for (int q = i + 1; q < k; ++q) sacc -= Hij(i, q) * y.v[q];
+      y.v[i] = sacc / Hij(i, i);
     }
-    std::memcpy(c->hpin + m + 4, y.data(), sizeof(double) * k);
-    HIPCHK(hipMemcpyAsync(c->ydev, c->hpin + m + 4, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
     {
       TimedLaunch tl(c, 2);
-      launch_lincomb(c->stream, x, Z, N, k, c->ydev, 0, N, 1);
+      launch_lincomb(c->stream, x, Z, N, k, y, N, 1, !x_nonzero);
     }
     x_nonzero = true;
     ++restarts;
+    if (total >= limit) {  // final true residual
+      if ((st = do_matvec(c, x, c->t1)) != FDG_OK) return st;
+      {
+        TimedLaunch tl(c, 2);
+        launch_residual(c->stream, b, c->t1, Vq(0), N, 1, G, c->P3);
+      }
+      {
+        TimedLaunch tl(c, 2);
+        launch_norm_reduce(c->stream, c->P3, G, 1, beta_dev, 0, beta_hd, 0);
+      }
+      HIPCHK(hipStreamSynchronize(c->stream));
+      rbeta = *beta_h;
+      inf.rel_res_true = rbeta / bnorm;
+      break;
+    }
   }
-  HIPCHK(hipStreamSynchronize(c->stream));
   inf.iterations = total;
   inf.restarts = restarts;
   inf.breakdown = breakdown ? 1 : 0;
   inf.rel_res_est = last_est;
-  inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  if (info) *info = inf;
-  return inf.converged ? FDG_OK : FDG_NOT_CONVERGED;
+  return finish(rbeta <= target);
 }
 
 extern "C" size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart) {

@@ -26,9 +26,15 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int kBlock = 256;  // 4 waves
-constexpr int kNT = 2;       // 16-column MFMA tiles per wave
-constexpr int kNB = 16 * kNT;  // columns per workgroup
+#ifndef FDG_FD_NT
+#define FDG_FD_NT 2
+#endif
+#ifndef FDG_FD_LDS_PAD
+#define FDG_FD_LDS_PAD 2
+#endif
+constexpr int kNT = FDG_FD_NT;   // 16-column MFMA tiles per wave
+constexpr int kNB = 16 * kNT;    // columns per workgroup
+constexpr int kPad = FDG_FD_LDS_PAD;  // LDS row padding (doubles, even: rows stay 16-byte aligned)
 
 __device__ inline dbl4 mfma(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -51,21 +57,86 @@ __device__ inline void load4_pad(const double *p, double (&v)[4]) {  // always i
   v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
 }
 
+// Fragments of one 16-wide k-block: MT row tiles of A, kNT column tiles of B (4 contraction
+// indices each per lane).
+template <int MT>
+struct Frag {
+  double a[MT][4];
+  double b[kNT][4];
+};
+
+template <int MT>
+__device__ inline void mma_block(const Frag<MT> &f, dbl4 (&acc)[MT][kNT]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(f.a[a][t], f.b[b][t], acc[a][b]);
+}
+
+// acc = sum over k-blocks j0 = 0, 16, .., kpad-16 of load(j0); the next block's operands are
+// loaded before the current block's MFMAs are issued (two register buffers).
+template <int MT, typename Load>
+__device__ inline void gemm_pipelined(int kpad, Load load, dbl4 (&acc)[MT][kNT]) {
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  Frag<MT> f0, f1;
+  load(0, f0);
+  for (int j0 = 0; j0 < kpad; j0 += 32) {
+    const bool has1 = j0 + 16 < kpad;
+    if (has1) load(j0 + 16, f1);
+    mma_block<MT>(f0, acc);
+    if (has1) {
+      if (j0 + 32 < kpad) load(j0 + 32, f0);
+      mma_block<MT>(f1, acc);
+    }
+  }
+}
+
+// acc = sum over the KB k-blocks of (A fragments already in registers) x (B from load_b);
+// B fragments are double-buffered.  k-blocks at or beyond kpad are skipped.
+template <int MT, int KB, typename LoadB>
+__device__ inline void gemm_preloaded_a(int kpad, const double (&xa)[MT][KB][4], LoadB load_b,
+                                        dbl4 (&acc)[MT][kNT]) {
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (kb * 16 >= kpad) break;
+    double bv[kNT][4];
+    load_b(kb * 16, bv);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(xa[a][kb][t], bv[b][t], acc[a][b]);
+  }
+}
+
 // ------------------------------------------------------------------------------------
-// Pass A / C.  Workgroup = (slab s, column block cb); wave w owns rows
+// Pass A / C.  Workgroup = (slab s, column block cb) with WAVES waves; wave w owns rows
 // [w*MT*16, (w+1)*MT*16) of both contractions and all kNB columns.
-//   GEMM1: Y1[i2][c] = sum_i1 X[s][i2][i1] W1[c][i1]      (A = X rows, B = W1 rows)
-//   GEMM2: Y2[k2][c] = sum_i2 W2[k2][i2] Y1[i2][c]        (A = W2 rows, B = Y1 from LDS)
+//   GEMM1: Y1[i2][c] = sum_i1 X[s][i2][i1] W1[c][i1]   (A = X rows from HBM, B = W1 tile in LDS)
+//   GEMM2: Y2[k2][c] = sum_i2 W2[k2][i2] Y1[i2][c]     (A = W2 rows from L2, B = Y1 in LDS)
 //   2D divide: Y2[k2][c] /= lam2[k2] + lam1[c].
+// The LDS buffer holds the W1 column tile during GEMM1 and then Y1 (transposed).
 // ------------------------------------------------------------------------------------
-template <int MT, bool VEC, bool DIV>
-__global__ __launch_bounds__(kBlock) void k_slab(const double *__restrict__ X, double *__restrict__ Y,
-                                                 const double *__restrict__ W1, const double *__restrict__ W2,
-                                                 int ldw, int n, int64_t nslab, int ncb, int xcd_remap,
-                                                 const double *__restrict__ lam1, const double *__restrict__ lam2) {
-  constexpr int MPAD = 4 * MT * 16;
-  constexpr int LDP = MPAD + 2;
-  __shared__ double y1t[kNB * LDP];  // Y1 transposed: y1t[c][i2]
+template <int WAVES, int MT, bool VEC, bool DIV, bool PRE>
+__global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(const double *__restrict__ X, double *__restrict__ Y,
+                                                     const double *__restrict__ W1, const double *__restrict__ W2,
+                                                     int ldw, int n, int64_t nslab, int ncb, int xcd_remap,
+                                                     const double *__restrict__ lam1,
+                                                     const double *__restrict__ lam2) {
+  constexpr int MPAD = WAVES * MT * 16;
+  constexpr int LDP = MPAD + kPad;
+  constexpr int NTHR = 64 * WAVES;
+  __shared__ double buf[kNB * LDP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
   int64_t s;
@@ -89,59 +160,76 @@ __global__ __launch_bounds__(kBlock) void k_slab(const double *__restrict__ X, d
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
 
+  // with PRE, the wave's whole strip of X (its MT*16 rows, all columns) is loaded into
+  // registers first, so its HBM latency overlaps the W1 staging below
+  constexpr int KB = PRE ? MPAD / 16 : 1;
+  double xa[MT][KB][4];
+  if (PRE) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int j = kb * 16 + 4 * lg;
+#pragma unroll
+      for (int a = 0; a < MT; ++a) {
+        const int row = m0 + 16 * a + li;
+        load4<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, xa[a][kb]);
+      }
+    }
+  }
+  // stage W1[c0 .. c0+kNB)[0 .. kpad) (zero-padded rows and columns beyond n)
+  for (int e = threadIdx.x; e < kNB * (kpad / 2); e += NTHR) {
+    const int c = e / (kpad / 2), j = 2 * (e % (kpad / 2));
+    const double2 v = *reinterpret_cast<const double2 *>(W1 + (size_t)(c0 + c) * ldw + j);
+    buf[c * LDP + j] = v.x;
+    buf[c * LDP + j + 1] = v.y;
+  }
+  __syncthreads();
+
   // ---- GEMM1 ----
   dbl4 acc[MT][kNT];
+  if (PRE) {
+    gemm_preloaded_a<MT, KB>(kpad, xa, [&](int j0, double (&bv)[kNT][4]) {
+      const int j = j0 + 4 * lg;
 #pragma unroll
-  for (int a = 0; a < MT; ++a)
+      for (int b = 0; b < kNT; ++b) {
+        const double *p = buf + (16 * b + li) * LDP + j;
+        bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
+      }
+    }, acc);
+  } else {
+    gemm_pipelined<MT>(kpad, [&](int j0, Frag<MT> &f) {
+      const int j = j0 + 4 * lg;
 #pragma unroll
-    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int j0 = 0; j0 < kpad; j0 += 16) {
-    const int j = j0 + 4 * lg;
-    double av[MT][4], bv[kNT][4];
+      for (int a = 0; a < MT; ++a) {
+        const int row = m0 + 16 * a + li;
+        load4<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
+      }
 #pragma unroll
-    for (int a = 0; a < MT; ++a) {
-      const int row = m0 + 16 * a + li;
-      load4<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, av[a]);
-    }
-#pragma unroll
-    for (int b = 0; b < kNT; ++b) load4_pad(W1 + (size_t)(c0 + 16 * b + li) * ldw + j, bv[b]);
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int a = 0; a < MT; ++a)
-#pragma unroll
-        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(av[a][t], bv[b][t], acc[a][b]);
+      for (int b = 0; b < kNT; ++b) {
+        const double *p = buf + (16 * b + li) * LDP + j;
+        f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
+      }
+    }, acc);
   }
+  __syncthreads();  // all waves are done with the W1 tile
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
     for (int b = 0; b < kNT; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) y1t[(16 * b + li) * LDP + m0 + 16 * a + lg + 4 * r] = acc[a][b][r];
+      for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + lg + 4 * r] = acc[a][b][r];
   __syncthreads();
 
   // ---- GEMM2 ----
-#pragma unroll
-  for (int a = 0; a < MT; ++a)
-#pragma unroll
-    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int j0 = 0; j0 < kpad; j0 += 16) {
+  gemm_pipelined<MT>(kpad, [&](int j0, Frag<MT> &f) {
     const int j = j0 + 4 * lg;
-    double av[MT][4], bv[kNT][4];
 #pragma unroll
-    for (int a = 0; a < MT; ++a) load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + j, av[a]);
+    for (int a = 0; a < MT; ++a) load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + j, f.a[a]);
 #pragma unroll
     for (int b = 0; b < kNT; ++b) {
-      const double *p = y1t + (16 * b + li) * LDP + j;
-      bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
+      const double *p = buf + (16 * b + li) * LDP + j;
+      f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int a = 0; a < MT; ++a)
-#pragma unroll
-        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(av[a][t], bv[b][t], acc[a][b]);
-  }
+  }, acc);
 #pragma unroll
   for (int b = 0; b < kNT; ++b) {
     const int c = c0 + 16 * b + li;
@@ -166,13 +254,15 @@ __global__ __launch_bounds__(kBlock) void k_slab(const double *__restrict__ X, d
 //   GEMM1: T[k3][c] = sum_i3 Wa[k3][i3] X[i3][c];   T /= lam3[k3] + lam2[i2] + lam1[i1]
 //   GEMM2: S[k3][c] = sum_k Wb[k3][k] T[k][c]        (T back in LDS, transposed)
 // ------------------------------------------------------------------------------------
-template <int MT>
-__global__ __launch_bounds__(kBlock) void k_fibre(const double *__restrict__ X, double *__restrict__ Y,
-                                                  const double *__restrict__ Wa, const double *__restrict__ Wb,
-                                                  int ldw, int n, int ncb, const double *__restrict__ lam1,
-                                                  const double *__restrict__ lam2, const double *__restrict__ lam3) {
-  constexpr int MPAD = 4 * MT * 16;
-  constexpr int LDP = MPAD + 2;
+template <int WAVES, int MT>
+__global__ __launch_bounds__(64 * WAVES) void k_fibre(const double *__restrict__ X, double *__restrict__ Y,
+                                                      const double *__restrict__ Wa, const double *__restrict__ Wb,
+                                                      int ldw, int n, int ncb, const double *__restrict__ lam1,
+                                                      const double *__restrict__ lam2,
+                                                      const double *__restrict__ lam3) {
+  constexpr int MPAD = WAVES * MT * 16;
+  constexpr int LDP = MPAD + kPad;
+  constexpr int NTHR = 64 * WAVES;
   __shared__ double xt[kNB * LDP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -185,34 +275,26 @@ __global__ __launch_bounds__(kBlock) void k_fibre(const double *__restrict__ X, 
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
   // stage X[i3][c0 .. c0+kNB) -> xt[c][i3], zero beyond n or n^2
-  for (int e = threadIdx.x; e < kpad * kNB; e += kBlock) {
+  for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
     const int i3 = e / kNB, c = e % kNB;
     const int64_t cg = c0 + c;
     xt[c * LDP + i3] = (i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0;
   }
   __syncthreads();
   dbl4 acc[MT][kNT];
+  auto lds_gemm = [&](const double *W) {
+    gemm_pipelined<MT>(kpad, [&](int j0, Frag<MT> &f) {
+      const int j = j0 + 4 * lg;
 #pragma unroll
-  for (int a = 0; a < MT; ++a)
+      for (int a = 0; a < MT; ++a) load4_pad(W + (size_t)(m0 + 16 * a + li) * ldw + j, f.a[a]);
 #pragma unroll
-    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int j0 = 0; j0 < kpad; j0 += 16) {
-    const int j = j0 + 4 * lg;
-    double av[MT][4], bv[kNT][4];
-#pragma unroll
-    for (int a = 0; a < MT; ++a) load4_pad(Wa + (size_t)(m0 + 16 * a + li) * ldw + j, av[a]);
-#pragma unroll
-    for (int b = 0; b < kNT; ++b) {
-      const double *p = xt + (16 * b + li) * LDP + j;
-      bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int a = 0; a < MT; ++a)
-#pragma unroll
-        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(av[a][t], bv[b][t], acc[a][b]);
-  }
+      for (int b = 0; b < kNT; ++b) {
+        const double *p = xt + (16 * b + li) * LDP + j;
+        f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
+      }
+    }, acc);
+  };
+  lds_gemm(Wa);
   __syncthreads();  // every wave has finished reading xt
 #pragma unroll
   for (int b = 0; b < kNT; ++b) {
@@ -230,27 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_fibre(const double *__restrict__ X, 
       }
   }
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < MT; ++a)
-#pragma unroll
-    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int j0 = 0; j0 < kpad; j0 += 16) {
-    const int j = j0 + 4 * lg;
-    double av[MT][4], bv[kNT][4];
-#pragma unroll
-    for (int a = 0; a < MT; ++a) load4_pad(Wb + (size_t)(m0 + 16 * a + li) * ldw + j, av[a]);
-#pragma unroll
-    for (int b = 0; b < kNT; ++b) {
-      const double *p = xt + (16 * b + li) * LDP + j;
-      bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int a = 0; a < MT; ++a)
-#pragma unroll
-        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(av[a][t], bv[b][t], acc[a][b]);
-  }
+  lds_gemm(Wb);
 #pragma unroll
   for (int b = 0; b < kNT; ++b) {
     const int64_t cg = c0 + 16 * b + li;
@@ -265,62 +327,88 @@ __global__ __launch_bounds__(kBlock) void k_fibre(const double *__restrict__ X, 
   }
 }
 
-template <int MT>
+template <int WAVES, int MT>
 void slab_launch(hipStream_t s, const double *X, double *Y, const double *W1, const double *W2, int ldw, int n,
                  int64_t nslab, bool div, const double *lam1, const double *lam2) {
   const int ncb = (n + kNB - 1) / kNB;
   const int64_t nwg = nslab * ncb;
   const int remap = (nslab % 8 == 0) ? 1 : 0;
   const bool vec = (n % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 31) == 0);
-  const dim3 grid((unsigned)nwg), blk(kBlock);
+  const dim3 grid((unsigned)nwg), blk(64 * WAVES);
+  constexpr bool PRE = false;  // preloading the X strip measured slower at n = 128
   if (div) {
     if (vec)
-      hipLaunchKernelGGL((k_slab<MT, true, true>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1, lam2);
+      hipLaunchKernelGGL((k_slab<WAVES, MT, true, true, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb,
+                         remap, lam1, lam2);
     else
-      hipLaunchKernelGGL((k_slab<MT, false, true>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1, lam2);
+      hipLaunchKernelGGL((k_slab<WAVES, MT, false, true, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb,
+                         remap, lam1, lam2);
   } else {
     if (vec)
-      hipLaunchKernelGGL((k_slab<MT, true, false>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1, lam2);
+      hipLaunchKernelGGL((k_slab<WAVES, MT, true, false, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb,
+                         remap, lam1, lam2);
     else
-      hipLaunchKernelGGL((k_slab<MT, false, false>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1, lam2);
+      hipLaunchKernelGGL((k_slab<WAVES, MT, false, false, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb,
+                         remap, lam1, lam2);
   }
 }
 
-template <int MT>
+template <int WAVES, int MT>
 void fibre_launch(hipStream_t s, const double *X, double *Y, const double *Wa, const double *Wb, int ldw, int n,
                   int64_t batch, const double *lam1, const double *lam2, const double *lam3) {
   const int64_t n2 = (int64_t)n * n;
   const int ncb = (int)((n2 + kNB - 1) / kNB);
-  const dim3 grid((unsigned)(batch * ncb)), blk(kBlock);
-  hipLaunchKernelGGL((k_fibre<MT>), grid, blk, 0, s, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
+  const dim3 grid((unsigned)(batch * ncb)), blk(64 * WAVES);
+  hipLaunchKernelGGL((k_fibre<WAVES, MT>), grid, blk, 0, s, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
 }
 
 }  // namespace
 
 bool fd_fused_supported(int n) { return n >= 1 && n <= 256; }
 
+// Workgroup shape (waves, 16-row tiles per wave) for a given n: MPAD = 16 * waves * MT
+// covers roundup(n, 16) with little padding (MPAD <= ldw always holds).
+struct Shape {
+  int waves, mt;
+};
+
+static Shape pick_shape(int n) {
+#if defined(FDG_FD_FORCE_W) && defined(FDG_FD_FORCE_MT)
+  if (16 * FDG_FD_FORCE_W * FDG_FD_FORCE_MT >= ((n + 15) & ~15) &&
+      16 * FDG_FD_FORCE_W * FDG_FD_FORCE_MT <= ((n + 63) / 64) * 64)
+    return {FDG_FD_FORCE_W, FDG_FD_FORCE_MT};
+#endif
+  const int k = (n + 15) / 16;  // 16-row tiles needed
+  if (k <= 4) return {4, 1};
+  if (k <= 8) return {k, 1};    // 5..8 waves, one tile each
+  if (k <= 12) return {12, 1};  // measured: 12 x 1 beats 6 x 2 and 4 x 3 for n in 129..192
+  return {8, 2};
+}
+
+#define FDG_SHAPES(X) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(4, 2) X(6, 2) X(8, 2) X(4, 3) X(12, 1)
+
 void launch_slab_f64(hipStream_t s, const double *X, double *Y, const double *W1, const double *W2, int ldw, int n,
                      int64_t nslab, bool divide, const double *lam1, const double *lam2) {
-  if (n <= 64)
-    slab_launch<1>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);
-  else if (n <= 128)
-    slab_launch<2>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);
-  else if (n <= 192)
-    slab_launch<3>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);
-  else
-    slab_launch<4>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);
+  const Shape sh = pick_shape(n);
+#define FDG_CASE(W, M)                                                                  \
+  if (sh.waves == W && sh.mt == M) {                                                   \
+    slab_launch<W, M>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);            \
+    return;                                                                            \
+  }
+  FDG_SHAPES(FDG_CASE)
+#undef FDG_CASE
 }
 
 void launch_fibre_f64(hipStream_t s, const double *X, double *Y, const double *Wa, const double *Wb, int ldw, int n,
                       int64_t batch, const double *lam1, const double *lam2, const double *lam3) {
-  if (n <= 64)
-    fibre_launch<1>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);
-  else if (n <= 128)
-    fibre_launch<2>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);
-  else if (n <= 192)
-    fibre_launch<3>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);
-  else
-    fibre_launch<4>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);
+  const Shape sh = pick_shape(n);
+#define FDG_CASE(W, M)                                                                  \
+  if (sh.waves == W && sh.mt == M) {                                                   \
+    fibre_launch<W, M>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);             \
+    return;                                                                            \
+  }
+  FDG_SHAPES(FDG_CASE)
+#undef FDG_CASE
 }
 
 }  // namespace fdg

@@ -31,10 +31,14 @@ struct KronBands {
   const double *K[3];
   const int32_t *lo[3];
   int w[3];
+  int rows4;   // max over i of lo2[min(i+3, n-1)] + w2 - lo2[i]: rows j2 that 4 rows i2 need
+  int rows16;  // the same for 16 rows i2 (aligned tiles)
+  int step3;   // max over i of lo3[i+1] - lo3[i]
 };
-// Requires non-decreasing band starts lo[] and w <= kron_window_max().
+// Requires non-decreasing band starts lo[] and w <= kron_window_max().  tmp_a, tmp_c:
+// scratch of nbatch * n^3 doubles each for the two-pass 3D form (may be NULL: one pass).
 void launch_kron_matvec_f64(hipStream_t s, const double *x, double *y, int d, int n, int64_t nbatch,
-                            const KronBands &bands);
+                            const KronBands &bands, double *tmp_a, double *tmp_c);
 int kron_window_max();
 
 // Slot-major ELL: entry (row, slot) at col[slot*ld + row], val[slot*ld + row].
@@ -43,23 +47,36 @@ void launch_ell_matvec_f64(hipStream_t s, const double *x, double *y, int64_t nr
 
 // ---- Krylov vector kernels --------------------------------------------------------------
 // Vectors of a basis are stored q-major: element (q, b, i) at V[q*ldv + b*N + i].
-// Partial sums of batch entry b, block g, component q at P[(b*G + g)*nv + q].
+// Partial sums of batch entry b, block g, component q at P[(b*G + g)*nv + q]
+// (G = reduction_blocks(N) <= 256); the consuming kernel reduces them in a fixed order.
+// "host" pointers are device addresses of host-mapped pinned memory (may be NULL).
+
+// Coefficients passed by value (kernel argument), at most 256.
+struct Coeffs {
+  double v[256];
+};
+
+// P = partial sums of V_q . w, q < nv.
 void launch_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *w, int64_t N,
                  int64_t nbatch, int G, double *P);
-// out[b*ostride + q] = sum_g P (sqrt of it if do_sqrt), q < ncomp; with add != NULL also
-// out2[b*o2stride + q] = sum + add[b*astride + q].
-void launch_reduce(hipStream_t s, const double *P, int G, int ncomp, int64_t nbatch, double *out,
-                   int ostride, bool do_sqrt, const double *add, int astride, double *out2, int o2stride);
-// w -= sum_q V_q h[b*hstride + q]; with Pnorm != NULL also the partial sums of |w|^2.
-void launch_update(hipStream_t s, const double *V, int64_t ldv, int nv, const double *h, int hstride,
-                   double *w, int64_t N, int64_t nbatch, int G, double *Pnorm);
-// v = w / nrm[b*nstride] (0 where nrm is 0).
-void launch_scale(hipStream_t s, const double *w, double *v, const double *nrm, int nstride,
-                  int64_t N, int64_t nbatch);
-// x += sum_q Z_q y[b*ystride + q], q < k.
-void launch_lincomb(hipStream_t s, double *x, const double *Z, int64_t ldz, int k, const double *y,
-                    int ystride, int64_t N, int64_t nbatch);
-// r = b - Ax and partial sums of |r|^2.
+// h1 = sum(Pin) (block 0 stores it to hout[b*hstride + q]); w -= V h1; Pout = partials of V^T w.
+void launch_update_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G,
+                        double *w, int64_t N, int64_t nbatch, double *Pout, double *hout, int hstride);
+// h2 = sum(Pin); Hcol = h1 + h2 (and host copy); w -= V h2; Pnorm = partials of |w|^2.
+void launch_update_norm(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G,
+                        double *w, int64_t N, int64_t nbatch, double *Pnorm, const double *h1,
+                        double *Hcol, int hstride, double *host, int host_stride);
+// d = sqrt(sum(Pn)); v = w / d (0 if d = 0; v may equal w); d stored to out and host.
+void launch_scale_reduce(hipStream_t s, const double *w, double *v, const double *Pn, int G, int64_t N,
+                         int64_t nbatch, double *out, int ostride, double *host, int host_stride);
+// d = sqrt(sum(Pn)) stored to out and host.
+void launch_norm_reduce(hipStream_t s, const double *Pn, int G, int64_t nbatch, double *out, int ostride,
+                        double *host, int host_stride);
+// x = (overwrite ? 0 : x) + sum_q Z_q y[q], q < k <= 256 (the same coefficients for every
+// batch entry).
+void launch_lincomb(hipStream_t s, double *x, const double *Z, int64_t ldz, int k, const Coeffs &y,
+                    int64_t N, int64_t nbatch, bool overwrite);
+// r = b - Ax and the partials of |r|^2.
 void launch_residual(hipStream_t s, const double *b, const double *Ax, double *r, int64_t N,
                      int64_t nbatch, int G, double *P);
 

@@ -1,12 +1,16 @@
-// Krylov vector kernels of flexible GMRES: multi-dot products, Gram-Schmidt updates,
-// norms, scaling and the final linear combination x += Z y.
+// Krylov vector kernels of flexible GMRES: multi-dot products, classical Gram-Schmidt
+// with reorthogonalisation, norms, scaling and the linear combination x += Z y.
 //
-// Reductions are deterministic: block g of batch entry b sums the contiguous chunk
-// [g*chunk, min(N, (g+1)*chunk)) in a fixed order (thread-strided accumulation, an xor
-// butterfly inside each wave, then the waves in index order) and writes one partial
-// sum; a one-block reduce kernel then sums the G partials (lane t takes g = t, t+64, ...
-// in increasing order, then an xor butterfly, which leaves the same bits in every lane).
-// G depends on N only, so a solve gives the same bits alone or inside a batch.
+// Reductions are deterministic.  A producer kernel has G <= 256 blocks (G depends on N
+// only); block g sums the contiguous chunk [g*chunk, min(N, (g+1)*chunk)) in a fixed
+// order (strided accumulation per thread, an xor butterfly inside each wave, then the
+// waves in index order) and stores one partial sum per component.  The consumer kernel
+// reduces the G partials itself, again in a fixed order (lane t takes g = t, t + 64, ...,
+// then an xor butterfly, which leaves the same bits in every lane), so every block of
+// the consumer holds identical values; block 0 publishes them to device memory and to
+// host-mapped memory for the host's least-squares update.  Kernel boundaries order the
+// two steps; no device-wide fences or atomics are used.  A problem gives the same bits
+// alone or inside a batch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,11 +22,11 @@ namespace fdg {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr int kQB = 8;  // basis vectors per register batch
-
-inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+constexpr int kRed = 1024;  // threads of the reduction-producing kernels
+constexpr int kRedWaves = kRed / 64;
+constexpr int kBlock = 256;  // threads of the streaming kernels
+constexpr int kQB = 8;       // basis vectors per register batch
+constexpr int kMaxG = 256;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -30,192 +34,347 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Contiguous chunk of block g; chunks are multiples of 2 * kRed elements.
 __device__ inline void chunk_of(int64_t N, int G, int g, int64_t &beg, int64_t &end) {
-  const int64_t chunk = (N + G - 1) / G;
+  int64_t chunk = (N + G - 1) / G;
+  chunk = (chunk + 2 * kRed - 1) / (2 * kRed) * (2 * kRed);
   beg = (int64_t)g * chunk;
+  if (beg > N) beg = N;
   end = beg + chunk < N ? beg + chunk : N;
 }
 
-__global__ __launch_bounds__(kBlock) void k_dots(const double *__restrict__ V, int64_t ldv, int nv,
-                                                 const double *__restrict__ w, int64_t N, int G,
-                                                 double *__restrict__ P) {
-  __shared__ double red[kWaves][kQB];
-  const int g = blockIdx.x;
-  const int64_t b = blockIdx.y;
-  int64_t beg, end;
-  chunk_of(N, G, g, beg, end);
-  const double *wb = w + b * N;
-  const double *Vb = V + b * N;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q0 = 0; q0 < nv; q0 += kQB) {
-    double acc[kQB];
+// Fixed-order sum of the G <= 256 partials of component q, valid in every lane.
+__device__ inline double sum_partials(const double *P, int G, int ncomp, int q) {
+  const int lane = threadIdx.x & 63;
+  double v[kMaxG / 64];
 #pragma unroll
-    for (int t = 0; t < kQB; ++t) acc[t] = 0.0;
-    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+  for (int k = 0; k < kMaxG / 64; ++k) {
+    const int g = lane + 64 * k;
+    v[k] = g < G ? P[(int64_t)g * ncomp + q] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kMaxG / 64; ++k) s += v[k];
+  return wave_sum(s);
+}
+
+// hs[q] = sum of the partials of component q, q < ncomp (all waves of the block help).
+__device__ inline void reduce_into(const double *P, int G, int ncomp, double *hs, int nwaves) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = wave; q < ncomp; q += nwaves) {
+    const double s = sum_partials(P, G, ncomp, q);
+    if (lane == 0) hs[q] = s;
+  }
+  __syncthreads();
+}
+
+// Per-block partial sums of kQB components (acc[t] per thread) -> P[g*ncomp + q0 + t].
+__device__ inline void store_partials(double (&acc)[kQB], double (*red)[kQB], double *Pg, int q0, int nv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < kQB; ++t) {
+    const double v = wave_sum(acc[t]);
+    if (lane == 0) red[wave][t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kQB && q0 + (int)threadIdx.x < nv) {
+    const int t = threadIdx.x;
+    double s = red[0][t];
+    for (int k = 1; k < kRedWaves; ++k) s += red[k][t];
+    Pg[q0 + t] = s;
+  }
+  __syncthreads();
+}
+
+// acc[t] += V_{q0+t} . w over the block's chunk.
+template <bool VEC>
+__device__ inline void chunk_dots(const double *Vb, int64_t ldv, int nv, int q0, const double *wb, int64_t beg,
+                                  int64_t end, double (&acc)[kQB]) {
+#pragma unroll
+  for (int t = 0; t < kQB; ++t) acc[t] = 0.0;
+  if (VEC) {
+#pragma unroll 2
+    for (int64_t i = beg + 2 * threadIdx.x; i < end; i += 2 * kRed) {
+      const double2 wi = *reinterpret_cast<const double2 *>(wb + i);
+#pragma unroll
+      for (int t = 0; t < kQB; ++t)
+        if (q0 + t < nv) {
+          const double2 vi = *reinterpret_cast<const double2 *>(Vb + (int64_t)(q0 + t) * ldv + i);
+          acc[t] = fma(vi.x, wi.x, acc[t]);
+          acc[t] = fma(vi.y, wi.y, acc[t]);
+        }
+    }
+  } else {
+    for (int64_t i = beg + threadIdx.x; i < end; i += kRed) {
       const double wi = wb[i];
 #pragma unroll
       for (int t = 0; t < kQB; ++t)
         if (q0 + t < nv) acc[t] = fma(Vb[(int64_t)(q0 + t) * ldv + i], wi, acc[t]);
     }
-#pragma unroll
-    for (int t = 0; t < kQB; ++t) {
-      const double v = wave_sum(acc[t]);
-      if (lane == 0) red[wave][t] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kQB && q0 + (int)threadIdx.x < nv) {
-      const int t = threadIdx.x;
-      double s = red[0][t];
-      for (int k = 1; k < kWaves; ++k) s += red[k][t];
-      P[((int64_t)b * G + g) * nv + q0 + t] = s;
-    }
-    __syncthreads();
   }
 }
 
-// out[b*ostride + q] = f(sum_g P[(b*G + g)*ncomp + q]) for q < ncomp, f = sqrt if do_sqrt;
-// with add != NULL also out2[b*o2stride + q] = sum + add[b*astride + q].
-__global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ P, int G, int ncomp,
-                                                   double *__restrict__ out, int ostride, int do_sqrt,
-                                                   const double *__restrict__ add, int astride,
-                                                   double *__restrict__ out2, int o2stride) {
-  const int64_t b = blockIdx.x;
+// w -= sum_q V_q hs[q] over the block's chunk; returns the thread's part of |w|^2.
+template <bool VEC>
+__device__ inline double chunk_update(const double *Vb, int64_t ldv, int nv, const double *hs, double *wb,
+                                      int64_t beg, int64_t end) {
+  double nrm = 0.0;
+  if (VEC) {
+#pragma unroll 2
+    for (int64_t i = beg + 2 * threadIdx.x; i < end; i += 2 * kRed) {
+      double2 wi = *reinterpret_cast<const double2 *>(wb + i);
+      for (int q = 0; q < nv; ++q) {
+        const double2 vi = *reinterpret_cast<const double2 *>(Vb + (int64_t)q * ldv + i);
+        wi.x = fma(-vi.x, hs[q], wi.x);
+        wi.y = fma(-vi.y, hs[q], wi.y);
+      }
+      *reinterpret_cast<double2 *>(wb + i) = wi;
+      nrm = fma(wi.x, wi.x, nrm);
+      nrm = fma(wi.y, wi.y, nrm);
+    }
+  } else {
+    for (int64_t i = beg + threadIdx.x; i < end; i += kRed) {
+      double wi = wb[i];
+      for (int q = 0; q < nv; ++q) wi = fma(-Vb[(int64_t)q * ldv + i], hs[q], wi);
+      wb[i] = wi;
+      nrm = fma(wi, wi, nrm);
+    }
+  }
+  return nrm;
+}
+
+__device__ inline double block_sum(double v, double *red) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = wave; q < ncomp; q += kWaves) {
-    double s = 0.0;
-    for (int g = lane; g < G; g += 64) s += P[((int64_t)b * G + g) * ncomp + q];
-    s = wave_sum(s);
-    if (lane == 0) {
-      out[b * ostride + q] = do_sqrt ? sqrt(s) : s;
-      if (add) out2[b * o2stride + q] = s + add[b * astride + q];
-    }
+  v = wave_sum(v);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    s = red[0];
+    for (int k = 1; k < kRedWaves; ++k) s += red[k];
   }
+  __syncthreads();
+  return s;
 }
 
-// w -= sum_q V_q h_q (h from a device array); optional partial sums of |w|^2.
-__global__ __launch_bounds__(kBlock) void k_update(const double *__restrict__ V, int64_t ldv, int nv,
-                                                   const double *__restrict__ h, int hstride,
-                                                   double *__restrict__ w, int64_t N, int G,
-                                                   double *__restrict__ Pnorm) {
-  __shared__ double hs[256];
-  __shared__ double red[kWaves];
+template <bool VEC>
+__global__ __launch_bounds__(kRed) void k_dots(const double *__restrict__ V, int64_t ldv, int nv,
+                                               const double *__restrict__ w, int64_t N, int G,
+                                               double *__restrict__ P) {
+  __shared__ double red[kRedWaves][kQB];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
-  for (int q = threadIdx.x; q < nv; q += kBlock) hs[q] = h[b * hstride + q];
-  __syncthreads();
+  int64_t beg, end;
+  chunk_of(N, G, g, beg, end);
+  const double *wb = w + b * N, *Vb = V + b * N;
+  double *Pg = P + ((int64_t)b * G + g) * nv;
+  for (int q0 = 0; q0 < nv; q0 += kQB) {
+    double acc[kQB];
+    chunk_dots<VEC>(Vb, ldv, nv, q0, wb, beg, end, acc);
+    store_partials(acc, red, Pg, q0, nv);
+  }
+}
+
+// h1 = reduce(Pin); w -= V h1; Pout = partial dots V^T w.  Block 0 stores h1 to hout.
+template <bool VEC>
+__global__ __launch_bounds__(kRed) void k_update_dots(const double *__restrict__ V, int64_t ldv, int nv,
+                                                      const double *__restrict__ Pin, int G, double *__restrict__ w,
+                                                      int64_t N, double *__restrict__ Pout,
+                                                      double *__restrict__ hout, int hstride) {
+  __shared__ double hs[256];
+  __shared__ double red[kRedWaves][kQB];
+  const int g = blockIdx.x;
+  const int64_t b = blockIdx.y;
+  reduce_into(Pin + (int64_t)b * G * nv, G, nv, hs, kRedWaves);
+  if (g == 0)
+    for (int q = threadIdx.x; q < nv; q += kRed) hout[b * hstride + q] = hs[q];
   int64_t beg, end;
   chunk_of(N, G, g, beg, end);
   double *wb = w + b * N;
   const double *Vb = V + b * N;
-  double nrm = 0.0;
-  for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-    double wi = wb[i];
-    for (int q = 0; q < nv; ++q) wi = fma(-Vb[(int64_t)q * ldv + i], hs[q], wi);
-    wb[i] = wi;
-    nrm = fma(wi, wi, nrm);
-  }
-  if (Pnorm) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double v = wave_sum(nrm);
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = red[0];
-      for (int k = 1; k < kWaves; ++k) s += red[k];
-      Pnorm[(int64_t)b * G + g] = s;
-    }
+  (void)chunk_update<VEC>(Vb, ldv, nv, hs, wb, beg, end);
+  __syncthreads();  // the block's own chunk of w is complete before it is re-read
+  double *Pg = Pout + ((int64_t)b * G + g) * nv;
+  for (int q0 = 0; q0 < nv; q0 += kQB) {
+    double acc[kQB];
+    chunk_dots<VEC>(Vb, ldv, nv, q0, wb, beg, end, acc);
+    store_partials(acc, red, Pg, q0, nv);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scale(const double *__restrict__ w, double *__restrict__ v,
-                                                  const double *__restrict__ nrm, int nstride, int64_t N,
-                                                  int64_t total) {
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const double d = nrm[(idx / N) * nstride];
-  v[idx] = d != 0.0 ? w[idx] / d : 0.0;
+// h2 = reduce(Pin); w -= V h2; Pnorm = partial |w|^2.  Block 0 stores the Hessenberg
+// column Hcol[q] = h1[q] + h2[q] (device and, when given, host-mapped memory).
+template <bool VEC>
+__global__ __launch_bounds__(kRed) void k_update_norm(const double *__restrict__ V, int64_t ldv, int nv,
+                                                      const double *__restrict__ Pin, int G, double *__restrict__ w,
+                                                      int64_t N, double *__restrict__ Pnorm,
+                                                      const double *__restrict__ h1, double *__restrict__ Hcol,
+                                                      int hstride, double *__restrict__ host, int host_stride) {
+  __shared__ double hs[256];
+  __shared__ double red[kRedWaves];
+  const int g = blockIdx.x;
+  const int64_t b = blockIdx.y;
+  reduce_into(Pin + (int64_t)b * G * nv, G, nv, hs, kRedWaves);
+  if (g == 0)
+    for (int q = threadIdx.x; q < nv; q += kRed) {
+      const double v = h1[b * hstride + q] + hs[q];
+      Hcol[b * hstride + q] = v;
+      if (host) host[b * host_stride + q] = v;
+    }
+  int64_t beg, end;
+  chunk_of(N, G, g, beg, end);
+  const double nrm = chunk_update<VEC>(V + b * N, ldv, nv, hs, w + b * N, beg, end);
+  const double s = block_sum(nrm, red);
+  if (threadIdx.x == 0) Pnorm[(int64_t)b * G + g] = s;
+}
+
+// nrm = sqrt(reduce(Pn)); v = w / nrm (0 if nrm = 0).  Block 0 stores nrm to out and host.
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_scale_reduce(const double *__restrict__ w, double *__restrict__ v,
+                                                         const double *__restrict__ Pn, int G, int64_t N,
+                                                         double *__restrict__ out, int ostride,
+                                                         double *__restrict__ host, int host_stride) {
+  __shared__ double hs[1];
+  const int64_t b = blockIdx.y;
+  reduce_into(Pn + (int64_t)b * G, G, 1, hs, kBlock / 64);
+  const double d = sqrt(hs[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (out) out[b * ostride] = d;
+    if (host) host[b * host_stride] = d;
+  }
+  const double *wb = w + b * N;
+  double *vb = v + b * N;
+  if (VEC) {
+    for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < N; i += (int64_t)gridDim.x * kBlock * 2) {
+      const double2 x = *reinterpret_cast<const double2 *>(wb + i);
+      *reinterpret_cast<double2 *>(vb + i) = d != 0.0 ? double2{x.x / d, x.y / d} : double2{0.0, 0.0};
+    }
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock)
+      vb[i] = d != 0.0 ? wb[i] / d : 0.0;
+  }
+}
+
+// out = sqrt(reduce(Pn)) to device and host memory (one block per batch entry).
+__global__ __launch_bounds__(kBlock) void k_norm_reduce(const double *__restrict__ Pn, int G,
+                                                        double *__restrict__ out, int ostride,
+                                                        double *__restrict__ host, int host_stride) {
+  __shared__ double hs[1];
+  const int64_t b = blockIdx.x;
+  reduce_into(Pn + (int64_t)b * G, G, 1, hs, kBlock / 64);
+  if (threadIdx.x == 0) {
+    const double d = sqrt(hs[0]);
+    if (out) out[b * ostride] = d;
+    if (host) host[b * host_stride] = d;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_lincomb(double *__restrict__ x, const double *__restrict__ Z,
-                                                    int64_t ldz, int k, const double *__restrict__ y,
-                                                    int ystride, int64_t N, int64_t total) {
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const int64_t b = idx / N;
-  const double *yb = y + b * ystride;
-  double acc = x[idx];
-  for (int q = 0; q < k; ++q) acc = fma(Z[(int64_t)q * ldz + idx], yb[q], acc);
-  x[idx] = acc;
+                                                    int64_t ldz, int k, Coeffs y, int64_t N, int overwrite) {
+  const int64_t b = blockIdx.y;
+  double *xb = x + b * N;
+  const double *Zb = Z + b * N;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock) {
+    double acc = overwrite ? 0.0 : xb[i];
+    for (int q = 0; q < k; ++q) acc = fma(Zb[(int64_t)q * ldz + i], y.v[q], acc);
+    xb[i] = acc;
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_residual(const double *__restrict__ bv, const double *__restrict__ Ax,
-                                                     double *__restrict__ r, int64_t N, int G,
-                                                     double *__restrict__ P) {
-  __shared__ double red[kWaves];
+__global__ __launch_bounds__(kRed) void k_residual(const double *__restrict__ bv, const double *__restrict__ Ax,
+                                                   double *__restrict__ r, int64_t N, int G, double *__restrict__ P) {
+  __shared__ double red[kRedWaves];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
   int64_t beg, end;
   chunk_of(N, G, g, beg, end);
   double nrm = 0.0;
-  for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+#pragma unroll 4
+  for (int64_t i = beg + threadIdx.x; i < end; i += kRed) {
     const int64_t e = b * N + i;
     const double v = bv[e] - Ax[e];
     r[e] = v;
     nrm = fma(v, v, nrm);
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double v = wave_sum(nrm);
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = red[0];
-    for (int k = 1; k < kWaves; ++k) s += red[k];
-    P[b * G + g] = s;
-  }
+  const double s = block_sum(nrm, red);
+  if (threadIdx.x == 0) P[b * G + g] = s;
+}
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+unsigned stream_blocks(int64_t N, int per_thread) {
+  int64_t g = (N + (int64_t)kBlock * per_thread - 1) / ((int64_t)kBlock * per_thread);
+  if (g > 4096) g = 4096;
+  return (unsigned)(g < 1 ? 1 : g);
 }
 
 }  // namespace
 
 int reduction_blocks(int64_t N) {
-  int64_t g = (N + 2047) / 2048;
+  int64_t g = (N + 8191) / 8192;
   if (g < 1) g = 1;
-  if (g > 1024) g = 1024;
+  if (g > kMaxG) g = kMaxG;
   return (int)g;
 }
 
 void launch_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *w, int64_t N, int64_t nbatch,
                  int G, double *P) {
-  hipLaunchKernelGGL(k_dots, dim3(G, (unsigned)nbatch), dim3(kBlock), 0, s, V, ldv, nv, w, N, G, P);
+  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16(V) && aligned16(w);
+  const dim3 grid(G, (unsigned)nbatch), blk(kRed);
+  if (vec)
+    hipLaunchKernelGGL(k_dots<true>, grid, blk, 0, s, V, ldv, nv, w, N, G, P);
+  else
+    hipLaunchKernelGGL(k_dots<false>, grid, blk, 0, s, V, ldv, nv, w, N, G, P);
 }
 
-void launch_reduce(hipStream_t s, const double *P, int G, int ncomp, int64_t nbatch, double *out, int ostride,
-                   bool do_sqrt, const double *add, int astride, double *out2, int o2stride) {
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)nbatch), dim3(kBlock), 0, s, P, G, ncomp, out, ostride,
-                     do_sqrt ? 1 : 0, add, astride, out2, o2stride);
+void launch_update_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G, double *w,
+                        int64_t N, int64_t nbatch, double *Pout, double *hout, int hstride) {
+  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16(V) && aligned16(w);
+  const dim3 grid(G, (unsigned)nbatch), blk(kRed);
+  if (vec)
+    hipLaunchKernelGGL(k_update_dots<true>, grid, blk, 0, s, V, ldv, nv, Pin, G, w, N, Pout, hout, hstride);
+  else
+    hipLaunchKernelGGL(k_update_dots<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, w, N, Pout, hout, hstride);
 }
 
-void launch_update(hipStream_t s, const double *V, int64_t ldv, int nv, const double *h, int hstride, double *w,
-                   int64_t N, int64_t nbatch, int G, double *Pnorm) {
-  hipLaunchKernelGGL(k_update, dim3(G, (unsigned)nbatch), dim3(kBlock), 0, s, V, ldv, nv, h, hstride, w, N, G,
-                     Pnorm);
+void launch_update_norm(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G, double *w,
+                        int64_t N, int64_t nbatch, double *Pnorm, const double *h1, double *Hcol, int hstride,
+                        double *host, int host_stride) {
+  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16(V) && aligned16(w);
+  const dim3 grid(G, (unsigned)nbatch), blk(kRed);
+  if (vec)
+    hipLaunchKernelGGL(k_update_norm<true>, grid, blk, 0, s, V, ldv, nv, Pin, G, w, N, Pnorm, h1, Hcol, hstride,
+                       host, host_stride);
+  else
+    hipLaunchKernelGGL(k_update_norm<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, w, N, Pnorm, h1, Hcol, hstride,
+                       host, host_stride);
 }
 
-void launch_scale(hipStream_t s, const double *w, double *v, const double *nrm, int nstride, int64_t N,
-                  int64_t nbatch) {
-  const int64_t total = N * nbatch;
-  hipLaunchKernelGGL(k_scale, dim3(cdiv(total, kBlock)), dim3(kBlock), 0, s, w, v, nrm, nstride, N, total);
+void launch_scale_reduce(hipStream_t s, const double *w, double *v, const double *Pn, int G, int64_t N,
+                         int64_t nbatch, double *out, int ostride, double *host, int host_stride) {
+  if (N % 2 == 0 && aligned16(w) && aligned16(v))
+    hipLaunchKernelGGL(k_scale_reduce<true>, dim3(stream_blocks(N, 2), (unsigned)nbatch), dim3(kBlock), 0, s, w, v,
+                       Pn, G, N, out, ostride, host, host_stride);
+  else
+    hipLaunchKernelGGL(k_scale_reduce<false>, dim3(stream_blocks(N, 1), (unsigned)nbatch), dim3(kBlock), 0, s, w, v,
+                       Pn, G, N, out, ostride, host, host_stride);
 }
 
-void launch_lincomb(hipStream_t s, double *x, const double *Z, int64_t ldz, int k, const double *y, int ystride,
-                    int64_t N, int64_t nbatch) {
-  const int64_t total = N * nbatch;
-  hipLaunchKernelGGL(k_lincomb, dim3(cdiv(total, kBlock)), dim3(kBlock), 0, s, x, Z, ldz, k, y, ystride, N,
-                     total);
+void launch_norm_reduce(hipStream_t s, const double *Pn, int G, int64_t nbatch, double *out, int ostride,
+                        double *host, int host_stride) {
+  hipLaunchKernelGGL(k_norm_reduce, dim3((unsigned)nbatch), dim3(kBlock), 0, s, Pn, G, out, ostride, host,
+                     host_stride);
+}
+
+void launch_lincomb(hipStream_t s, double *x, const double *Z, int64_t ldz, int k, const Coeffs &y, int64_t N,
+                    int64_t nbatch, bool overwrite) {
+  hipLaunchKernelGGL(k_lincomb, dim3(stream_blocks(N, 1), (unsigned)nbatch), dim3(kBlock), 0, s, x, Z, ldz, k, y, N,
+                     overwrite ? 1 : 0);
 }
 
 void launch_residual(hipStream_t s, const double *b, const double *Ax, double *r, int64_t N, int64_t nbatch, int G,
                      double *P) {
-  hipLaunchKernelGGL(k_residual, dim3(G, (unsigned)nbatch), dim3(kBlock), 0, s, b, Ax, r, N, G, P);
+  hipLaunchKernelGGL(k_residual, dim3(G, (unsigned)nbatch), dim3(kRed), 0, s, b, Ax, r, N, G, P);
 }
 
 }  // namespace fdg

@@ -108,6 +108,242 @@ __global__ __launch_bounds__(kBlock) void k_kron3_window(const double *__restric
   }
 }
 
+// 3D, LDS-tiled: a workgroup owns 64 consecutive i1 (the lanes) x 4 consecutive i2 (the
+// waves) and sweeps a chunk of i3.  For each plane j3 the direction-1 band sums of the
+// rows j2 that the 4 rows i2 need are formed once into LDS (double-buffered by plane
+// parity, so one barrier per plane suffices); every thread then combines its w2 rows
+// into a(j3), c(j3) and keeps the sliding window of planes in registers.
+constexpr int kRowsMax = 12;  // rows j2 a tile of 4 rows i2 may need: 3 + w2 (checked on the host)
+
+template <int WMAX>
+__global__ __launch_bounds__(kBlock) void k_kron3_lds(const double *__restrict__ x, double *__restrict__ y, int n,
+                                                      int nchunk, KronBands bd) {
+  __shared__ double sm[2][kRowsMax][64];
+  __shared__ double sk[2][kRowsMax][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i1 = blockIdx.x * 64 + lane;
+  const int i2a = blockIdx.y * 4;
+  const int i2 = i2a + wave;
+  const int chunk = blockIdx.z % nchunk;
+  const int64_t b = blockIdx.z / nchunk;
+  const int s = chunk * kChunk;
+  const int e = s + kChunk < n ? s + kChunk : n;
+  const int64_t n2 = (int64_t)n * n;
+  const double *xb = x + b * n2 * n;
+  double *yb = y + b * n2 * n;
+  const int w1 = bd.w[0], w2 = bd.w[1], w3 = bd.w[2];
+  const bool act1 = i1 < n, act = act1 && i2 < n;
+  const int i1c = act1 ? i1 : n - 1;
+  const int i2c = i2 < n ? i2 : n - 1;
+  const int i2b = i2a + 3 < n ? i2a + 3 : n - 1;
+  const int R0 = bd.lo[1][i2a];
+  const int NR = bd.lo[1][i2b] + w2 - R0;  // <= kRowsMax
+  double m1[WMAX], k1[WMAX], m2[WMAX], k2[WMAX];
+#pragma unroll
+  for (int t = 0; t < WMAX; ++t) {
+    m1[t] = t < w1 ? bd.M[0][(size_t)i1c * w1 + t] : 0.0;
+    k1[t] = t < w1 ? bd.K[0][(size_t)i1c * w1 + t] : 0.0;
+    m2[t] = t < w2 ? bd.M[1][(size_t)i2c * w2 + t] : 0.0;
+    k2[t] = t < w2 ? bd.K[1][(size_t)i2c * w2 + t] : 0.0;
+  }
+  const int lo1 = bd.lo[0][i1c];
+  const int r2 = bd.lo[1][i2c] - R0;  // first LDS row of this thread's band
+  int parity = 0;
+  auto plane = [&](int j3, double &a, double &c) {
+    // phase 1: rows R0 .. R0+NR-1 of plane j3, direction-1 band sums (wave w takes rows w, w+4, ...)
+    const double *xp = xb + (int64_t)j3 * n2 + lo1;
+    for (int r = wave; r < NR; r += 4) {
+      const double *xr = xp + (int64_t)(R0 + r) * n;
+      double vm = 0.0, vk = 0.0;
+#pragma unroll
+      for (int t1 = 0; t1 < WMAX; ++t1)
+        if (t1 < w1) {
+          const double v = xr[t1];
+          vm = fma(m1[t1], v, vm);
+          vk = fma(k1[t1], v, vk);
+        }
+      sm[parity][r][lane] = vm;
+      sk[parity][r][lane] = vk;
+    }
+    __syncthreads();
+    // phase 2: direction-2 band of this thread's row i2
+    a = 0.0;
+    c = 0.0;
+#pragma unroll
+    for (int t2 = 0; t2 < WMAX; ++t2)
+      if (t2 < w2) {
+        const double vm = sm[parity][r2 + t2][lane], vk = sk[parity][r2 + t2][lane];
+        a = fma(m2[t2], vm, a);
+        c = fma(k2[t2], vm, c);
+        c = fma(m2[t2], vk, c);
+      }
+    parity ^= 1;
+  };
+  double A[WMAX], C[WMAX];
+  int base = bd.lo[2][s];
+#pragma unroll
+  for (int u = 0; u < WMAX; ++u) {
+    const int t = u - (WMAX - w3);
+    if (t >= 0) {
+      plane(base + t, A[u], C[u]);
+    } else {
+      A[u] = 0.0;
+      C[u] = 0.0;
+    }
+  }
+  for (int i3 = s; i3 < e; ++i3) {
+    const int target = bd.lo[2][i3];
+    while (base < target) {
+#pragma unroll
+      for (int u = 0; u < WMAX - 1; ++u) {
+        A[u] = A[u + 1];
+        C[u] = C[u + 1];
+      }
+      plane(base + w3, A[WMAX - 1], C[WMAX - 1]);
+      ++base;
+    }
+    if (act) {
+      const double *m3 = bd.M[2] + (size_t)i3 * w3;
+      const double *k3 = bd.K[2] + (size_t)i3 * w3;
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < WMAX; ++u) {
+        const int t = u - (WMAX - w3);
+        if (t >= 0) {
+          acc = fma(k3[t], A[u], acc);
+          acc = fma(m3[t], C[u], acc);
+        }
+      }
+      yb[(int64_t)i3 * n2 + (int64_t)i2 * n + i1] = acc;
+    }
+  }
+}
+
+// 3D in two passes, both fully parallel:
+//   pass 1, per plane j3 and tile of 64 i1 x 16 i2: the direction-1 band sums of the rows
+//   j2 the tile needs go to LDS once; each thread combines its w2 rows into
+//       a[j3][i2][i1] = sum_j2 M2 sM,   c[j3][i2][i1] = sum_j2 (K2 sM + M2 sK)
+//   pass 2, per output: y[i3] = sum_t3 K3[i3][t3] a[lo3 + t3] + M3[i3][t3] c[lo3 + t3];
+//   a thread produces 4 consecutive i3 and loads the union of their plane bands once.
+constexpr int kPlaneRows = 16;                 // i2 rows per pass-1 tile
+constexpr int kPlaneRowsMax = kPlaneRows + 15; // rows j2 the tile may need (w2 <= 16)
+
+template <int WMAX>
+__global__ __launch_bounds__(kBlock) void k_kron3_planes(const double *__restrict__ x, double *__restrict__ ao,
+                                                         double *__restrict__ co, int n, int nplane, KronBands bd) {
+  __shared__ double sm[kPlaneRowsMax][64];
+  __shared__ double sk[kPlaneRowsMax][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i1 = blockIdx.x * 64 + lane;
+  const int i2a = blockIdx.y * kPlaneRows;
+  const int64_t pl = blockIdx.z;  // b * n + j3
+  const int64_t n2 = (int64_t)n * n;
+  const double *xp = x + pl * n2;
+  const int w1 = bd.w[0], w2 = bd.w[1];
+  const bool act1 = i1 < n;
+  const int i1c = act1 ? i1 : n - 1;
+  const int i2b = i2a + kPlaneRows - 1 < n ? i2a + kPlaneRows - 1 : n - 1;
+  const int R0 = bd.lo[1][i2a];
+  const int NR = bd.lo[1][i2b] + w2 - R0;  // <= kPlaneRowsMax, checked on the host
+  const int lo1 = bd.lo[0][i1c];
+  double m1[WMAX], k1[WMAX];
+#pragma unroll
+  for (int t = 0; t < WMAX; ++t) {
+    m1[t] = t < w1 ? bd.M[0][(size_t)i1c * w1 + t] : 0.0;
+    k1[t] = t < w1 ? bd.K[0][(size_t)i1c * w1 + t] : 0.0;
+  }
+  // rows r = wave + 4 u, u < kRowsPerWave: every load of the tile is issued before use
+  constexpr int kRowsPerWave = (kPlaneRowsMax + 3) / 4;
+  double xv[kRowsPerWave][WMAX];
+#pragma unroll
+  for (int u = 0; u < kRowsPerWave; ++u) {
+    const int r = wave + 4 * u;
+    const double *xr = xp + (int64_t)(R0 + (r < NR ? r : 0)) * n + lo1;
+#pragma unroll
+    for (int t1 = 0; t1 < WMAX; ++t1) xv[u][t1] = (r < NR && t1 < w1) ? xr[t1] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kRowsPerWave; ++u) {
+    const int r = wave + 4 * u;
+    if (r < NR) {
+      double vm = 0.0, vk = 0.0;
+#pragma unroll
+      for (int t1 = 0; t1 < WMAX; ++t1) {
+        vm = fma(m1[t1], xv[u][t1], vm);
+        vk = fma(k1[t1], xv[u][t1], vk);
+      }
+      sm[r][lane] = vm;
+      sk[r][lane] = vk;
+    }
+  }
+  __syncthreads();
+  if (!act1) return;
+#pragma unroll
+  for (int u = 0; u < kPlaneRows / 4; ++u) {
+    const int i2 = i2a + wave + 4 * u;
+    if (i2 > i2b) break;
+    const int r2 = bd.lo[1][i2] - R0;
+    const double *m2 = bd.M[1] + (size_t)i2 * w2;
+    const double *k2 = bd.K[1] + (size_t)i2 * w2;
+    double a = 0.0, c = 0.0;
+#pragma unroll
+    for (int t2 = 0; t2 < WMAX; ++t2)
+      if (t2 < w2) {
+        const double vm = sm[r2 + t2][lane], vk = sk[r2 + t2][lane];
+        a = fma(m2[t2], vm, a);
+        c = fma(k2[t2], vm, c);
+        c = fma(m2[t2], vk, c);
+      }
+    const int64_t o = pl * n2 + (int64_t)i2 * n + i1;
+    ao[o] = a;
+    co[o] = c;
+  }
+}
+
+constexpr int kRowsPerThread = 4;  // consecutive i3 outputs per thread in pass 2
+
+template <int WMAX>
+__global__ __launch_bounds__(kBlock) void k_kron3_mode3(const double *__restrict__ ai, const double *__restrict__ ci,
+                                                        double *__restrict__ y, int n, int ngroups, KronBands bd) {
+  const int64_t n2 = (int64_t)n * n;
+  const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (col >= n2) return;
+  const int grp = blockIdx.y % ngroups;
+  const int64_t b = blockIdx.y / ngroups;
+  const int s = grp * kRowsPerThread;
+  const int e = s + kRowsPerThread < n ? s + kRowsPerThread : n;
+  const int w3 = bd.w[2];
+  const int P0 = bd.lo[2][s];
+  const int np = bd.lo[2][e - 1] + w3 - P0;  // planes needed, <= kRowsPerThread - 1 + WMAX
+  const double *ab = ai + b * n2 * n + col, *cb = ci + b * n2 * n + col;
+  constexpr int NPMAX = kRowsPerThread - 1 + WMAX;
+  double av[NPMAX], cv[NPMAX];
+#pragma unroll
+  for (int q = 0; q < NPMAX; ++q) {
+    const bool ok = q < np;
+    av[q] = ok ? ab[(int64_t)(P0 + q) * n2] : 0.0;
+    cv[q] = ok ? cb[(int64_t)(P0 + q) * n2] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < kRowsPerThread; ++r) {
+    const int i3 = s + r;
+    if (i3 >= e) break;
+    const int off = bd.lo[2][i3] - P0;
+    const double *m3 = bd.M[2] + (size_t)i3 * w3;
+    const double *k3 = bd.K[2] + (size_t)i3 * w3;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NPMAX; ++q) {
+      const int t = q - off;
+      if (t >= 0 && t < w3) {
+        acc = fma(k3[t], av[q], acc);
+        acc = fma(m3[t], cv[q], acc);
+      }
+    }
+    y[b * n2 * n + (int64_t)i3 * n2 + col] = acc;
+  }
+}
+
 // 2D: one thread owns column i1 and sweeps a chunk of i2; window of direction-1 band sums.
 template <int WMAX>
 __global__ __launch_bounds__(kBlock) void k_kron2_window(const double *__restrict__ x, double *__restrict__ y,
@@ -199,11 +435,33 @@ __global__ __launch_bounds__(kBlock) void k_ell_f64(const double *__restrict__ x
 int kron_window_max() { return 16; }
 
 void launch_kron_matvec_f64(hipStream_t s, const double *x, double *y, int d, int n, int64_t nbatch,
-                            const KronBands &bd) {
+                            const KronBands &bd, double *tmp_a, double *tmp_c) {
   int w = 0;
   for (int l = 0; l < d; ++l) w = bd.w[l] > w ? bd.w[l] : w;
   const dim3 blk(kBlock);
   if (d == 3) {
+    if (tmp_a && tmp_c && bd.rows16 <= kPlaneRowsMax && bd.step3 <= 1 && w <= 8 && (int64_t)n * nbatch <= 65535) {
+      const dim3 g1(cdiv(n, 64), cdiv(n, kPlaneRows), (unsigned)(n * nbatch));
+      const int ngroups = (int)cdiv(n, kRowsPerThread);
+      const dim3 g2(cdiv((int64_t)n * n, kBlock), (unsigned)(ngroups * nbatch));
+      if (w <= 4) {
+        hipLaunchKernelGGL(k_kron3_planes<4>, g1, blk, 0, s, x, tmp_a, tmp_c, n, n, bd);
+        hipLaunchKernelGGL(k_kron3_mode3<4>, g2, blk, 0, s, tmp_a, tmp_c, y, n, ngroups, bd);
+      } else {
+        hipLaunchKernelGGL(k_kron3_planes<8>, g1, blk, 0, s, x, tmp_a, tmp_c, n, n, bd);
+        hipLaunchKernelGGL(k_kron3_mode3<8>, g2, blk, 0, s, tmp_a, tmp_c, y, n, ngroups, bd);
+      }
+      return;
+    }
+    if (bd.rows4 <= kRowsMax && w <= 8) {
+      const int nchunk = (int)cdiv(n, kChunk);
+      const dim3 grid(cdiv(n, 64), cdiv(n, 4), (unsigned)(nchunk * nbatch));
+      if (w <= 4)
+        hipLaunchKernelGGL(k_kron3_lds<4>, grid, blk, 0, s, x, y, n, nchunk, bd);
+      else
+        hipLaunchKernelGGL(k_kron3_lds<8>, grid, blk, 0, s, x, y, n, nchunk, bd);
+      return;
+    }
     const dim3 grid(cdiv((int64_t)n * n, kBlock), cdiv(n, kChunk), (unsigned)nbatch);
     if (w <= 4)
       hipLaunchKernelGGL(k_kron3_window<4>, grid, blk, 0, s, x, y, n, bd);
