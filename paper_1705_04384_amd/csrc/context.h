@@ -1,0 +1,124 @@
+// Internal definition of the device context shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "batch_addr.h"
+#include "common.h"
+
+namespace fdg {
+constexpr int kTimerClasses = 4;
+
+struct TimerState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;     // free events
+  std::vector<hipEvent_t> pending;  // start, stop, start, stop, ...
+};
+
+}  // namespace fdg
+
+struct fdg_ctx {
+  int d = 0, n = 0, batch = 1, device = 0;
+  int64_t N = 0;
+  hipStream_t stream = nullptr;
+  int prec = FDG_PREC_FP64;
+  // preconditioner factors, zero-padded ldw x ldw
+  int ldw = 0;
+  bool have_factor[3] = {false, false, false};
+  double *Wv[3] = {nullptr, nullptr, nullptr};  // V_l^T: Y = W X applies V_l^T along mode l
+  double *Wu[3] = {nullptr, nullptr, nullptr};  // U_l
+  double *lam[3] = {nullptr, nullptr, nullptr};
+  float *Wv32[3] = {nullptr, nullptr, nullptr}, *Wu32[3] = {nullptr, nullptr, nullptr};
+  uint16_t *Wv16[3] = {nullptr, nullptr, nullptr}, *Wu16[3] = {nullptr, nullptr, nullptr};
+  float *lam32[3] = {nullptr, nullptr, nullptr};
+  double lam_min[3] = {0, 0, 0};
+  // operator
+  int op_kind = 0;  // 0 none, 1 Kronecker bands, 2 ELL
+  bool have_op[3] = {false, false, false};
+  double *bandM[3] = {nullptr, nullptr, nullptr}, *bandK[3] = {nullptr, nullptr, nullptr};
+  int32_t *bandlo[3] = {nullptr, nullptr, nullptr};
+  int bandw[3] = {0, 0, 0};
+  int bandrows4[3] = {0, 0, 0}, bandrows16[3] = {0, 0, 0}, bandstep[3] = {0, 0, 0};
+  double *mv_a = nullptr, *mv_c = nullptr;  // two-pass Kronecker matvec intermediates
+  int32_t *ell_col = nullptr;
+  double *ell_val = nullptr;
+  int ell_width = 0;
+  // workspace
+  double *t1 = nullptr, *t2 = nullptr;
+  void *t32a = nullptr, *t32b = nullptr;
+  int restart_alloc = 0;
+  double *Vb = nullptr, *Zb = nullptr, *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *Hcol = nullptr,
+         *ydev = nullptr, *hbuf = nullptr, *scal = nullptr;
+  double *hpin = nullptr;      // pinned, device-mapped host memory for the scalars the host needs
+  double *hpin_dev = nullptr;  // its device address
+  unsigned *counters = nullptr;  // last-block counters of the reductions
+  fdg::TimerState timers[fdg::kTimerClasses];
+};
+
+namespace fdg {
+
+inline int hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return FDG_OK;
+  if (e == hipErrorOutOfMemory) return set_error(FDG_ENOMEM, "%s: out of device memory", what);
+  return set_error(FDG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                  \
+  do {                                                \
+    int _st = hip_check((call), #call);               \
+    if (_st != FDG_OK) return _st;                    \
+  } while (0)
+
+template <typename T>
+inline int dalloc(T **p, size_t count) {
+  if (*p) return FDG_OK;
+  return hip_check(hipMalloc((void **)p, count * sizeof(T) + 256), "hipMalloc");
+}
+
+template <typename T>
+inline void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+// Brackets one launch of timer class c with events when that timer is on.
+struct TimedLaunch {
+  fdg_ctx *ctx;
+  int c;
+  hipEvent_t stop = nullptr;
+  TimedLaunch(fdg_ctx *x, int cls) : ctx(x), c(cls) {
+    TimerState &t = ctx->timers[c];
+    if (!t.on) return;
+    hipEvent_t a, b;
+    if (t.pool.size() >= 2) {
+      a = t.pool.back(); t.pool.pop_back();
+      b = t.pool.back(); t.pool.pop_back();
+    } else {
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    }
+    (void)hipEventRecord(a, ctx->stream);
+    t.pending.push_back(a);
+    stop = b;
+  }
+  ~TimedLaunch() {
+    if (!stop) return;
+    (void)hipEventRecord(stop, ctx->stream);
+    ctx->timers[c].pending.push_back(stop);
+  }
+};
+
+
+// P^{-1} for nentries batch entries (entry e at in.at(e) / out.at(e)), FP64 fused passes
+// (n <= 256) with the caller's ping-pong workspace t1, t2 (nentries * N doubles each,
+// contiguous).  aligned32: every entry pointer is 32-byte aligned.
+int apply_prec_entries(fdg_ctx *c, CBatch in, MBatch out, int64_t nentries, bool aligned32, double *t1,
+                       double *t2);
+// y = A x for nentries batch entries (Kronecker operator: two-pass form with the caller's
+// intermediates tmp_a, tmp_c of nentries * N doubles each).
+int matvec_entries(fdg_ctx *c, CBatch x, MBatch y, int64_t nentries, double *tmp_a, double *tmp_c);
+
+}  // namespace fdg

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.h"
+#include "context.h"
 #include "fd_apply.h"
 #include "kernels.h"
 #include "modeprod.h"
@@ -17,107 +18,6 @@
 using namespace fdg;
 
 namespace {
-
-constexpr int kTimerClasses = 4;
-
-struct TimerState {
-  bool on = false;
-  std::vector<hipEvent_t> pool;     // free events
-  std::vector<hipEvent_t> pending;  // start, stop, start, stop, ...
-};
-
-}  // namespace
-
-struct fdg_ctx {
-  int d = 0, n = 0, batch = 1, device = 0;
-  int64_t N = 0;
-  hipStream_t stream = nullptr;
-  int prec = FDG_PREC_FP64;
-  // preconditioner factors, zero-padded ldw x ldw
-  int ldw = 0;
-  bool have_factor[3] = {false, false, false};
-  double *Wv[3] = {nullptr, nullptr, nullptr};  // V_l^T: Y = W X applies V_l^T along mode l
-  double *Wu[3] = {nullptr, nullptr, nullptr};  // U_l
-  double *lam[3] = {nullptr, nullptr, nullptr};
-  float *Wv32[3] = {nullptr, nullptr, nullptr}, *Wu32[3] = {nullptr, nullptr, nullptr};
-  uint16_t *Wv16[3] = {nullptr, nullptr, nullptr}, *Wu16[3] = {nullptr, nullptr, nullptr};
-  float *lam32[3] = {nullptr, nullptr, nullptr};
-  double lam_min[3] = {0, 0, 0};
-  // operator
-  int op_kind = 0;  // 0 none, 1 Kronecker bands, 2 ELL
-  bool have_op[3] = {false, false, false};
-  double *bandM[3] = {nullptr, nullptr, nullptr}, *bandK[3] = {nullptr, nullptr, nullptr};
-  int32_t *bandlo[3] = {nullptr, nullptr, nullptr};
-  int bandw[3] = {0, 0, 0};
-  int bandrows4[3] = {0, 0, 0}, bandrows16[3] = {0, 0, 0}, bandstep[3] = {0, 0, 0};
-  double *mv_a = nullptr, *mv_c = nullptr;  // two-pass Kronecker matvec intermediates
-  int32_t *ell_col = nullptr;
-  double *ell_val = nullptr;
-  int ell_width = 0;
-  // workspace
-  double *t1 = nullptr, *t2 = nullptr;
-  void *t32a = nullptr, *t32b = nullptr;
-  int restart_alloc = 0;
-  double *Vb = nullptr, *Zb = nullptr, *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *Hcol = nullptr,
-         *ydev = nullptr, *hbuf = nullptr, *scal = nullptr;
-  double *hpin = nullptr;      // pinned, device-mapped host memory for the scalars the host needs
-  double *hpin_dev = nullptr;  // its device address
-  unsigned *counters = nullptr;  // last-block counters of the reductions
-  TimerState timers[kTimerClasses];
-};
-
-namespace {
-
-int hip_check(hipError_t e, const char *what) {
-  if (e == hipSuccess) return FDG_OK;
-  if (e == hipErrorOutOfMemory) return set_error(FDG_ENOMEM, "%s: out of device memory", what);
-  return set_error(FDG_EHIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define HIPCHK(call)                                  \
-  do {                                                \
-    int _st = hip_check((call), #call);               \
-    if (_st != FDG_OK) return _st;                    \
-  } while (0)
-
-template <typename T>
-int dalloc(T **p, size_t count) {
-  if (*p) return FDG_OK;
-  return hip_check(hipMalloc((void **)p, count * sizeof(T) + 256), "hipMalloc");
-}
-
-template <typename T>
-void dfree(T *&p) {
-  if (p) (void)hipFree((void *)p);
-  p = nullptr;
-}
-
-// Brackets one launch of timer class c with events when that timer is on.
-struct TimedLaunch {
-  fdg_ctx *ctx;
-  int c;
-  hipEvent_t stop = nullptr;
-  TimedLaunch(fdg_ctx *x, int cls) : ctx(x), c(cls) {
-    TimerState &t = ctx->timers[c];
-    if (!t.on) return;
-    hipEvent_t a, b;
-    if (t.pool.size() >= 2) {
-      a = t.pool.back(); t.pool.pop_back();
-      b = t.pool.back(); t.pool.pop_back();
-    } else {
-      if (hipEventCreate(&a) != hipSuccess) return;
-      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
-    }
-    (void)hipEventRecord(a, ctx->stream);
-    t.pending.push_back(a);
-    stop = b;
-  }
-  ~TimedLaunch() {
-    if (!stop) return;
-    (void)hipEventRecord(stop, ctx->stream);
-    ctx->timers[c].pending.push_back(stop);
-  }
-};
 
 bool finite_all(const double *a, size_t n) {
   for (size_t i = 0; i < n; ++i)
@@ -166,6 +66,8 @@ int check_ready_op(fdg_ctx *c) {
   return set_error(FDG_ENOTREADY, "operator not set");
 }
 
+inline bool al(const void *p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
+
 int do_apply(fdg_ctx *c, const double *b, double *s) {
   int st = ensure_workspace(c);
   if (st != FDG_OK) return st;
@@ -177,35 +79,12 @@ int do_apply(fdg_ctx *c, const double *b, double *s) {
                          c->prec == FDG_PREC_FP32 ? (const void *const *)c->Wu32 : (const void *const *)c->Wu16,
                          c->lam32, c->ldw);
   }
+  if (fd_fused_supported(c->n))
+    return apply_prec_entries(c, cstrided(b, c->N), mstrided(s, c->N), c->batch, al(b, 32) && al(s, 32), c->t1,
+                              c->t2);
   const int n = c->n;
   const int64_t B = c->batch;
   const int64_t n2 = (int64_t)n * n;
-  if (fd_fused_supported(n)) {
-    if (c->d == 3) {
-      {
-        TimedLaunch tl(c, 0);
-        launch_slab_f64(c->stream, b, c->t1, c->Wv[0], c->Wv[1], c->ldw, n, B * n, false, nullptr, nullptr);
-      }
-      {
-        TimedLaunch tl(c, 3);
-        launch_fibre_f64(c->stream, c->t1, c->t2, c->Wv[2], c->Wu[2], c->ldw, n, B, c->lam[0], c->lam[1], c->lam[2]);
-      }
-      {
-        TimedLaunch tl(c, 0);
-        launch_slab_f64(c->stream, c->t2, s, c->Wu[0], c->Wu[1], c->ldw, n, B * n, false, nullptr, nullptr);
-      }
-    } else {
-      {
-        TimedLaunch tl(c, 0);
-        launch_slab_f64(c->stream, b, c->t1, c->Wv[0], c->Wv[1], c->ldw, n, B, true, c->lam[0], c->lam[1]);
-      }
-      {
-        TimedLaunch tl(c, 0);
-        launch_slab_f64(c->stream, c->t1, s, c->Wu[0], c->Wu[1], c->ldw, n, B, false, nullptr, nullptr);
-      }
-    }
-    return hip_check(hipGetLastError(), "apply_prec launch");
-  }
   auto mode = [&](const double *X, double *Y, const double *W, int l) {
     TimedLaunch tl(c, 0);
     if (l == 0) {
@@ -237,30 +116,79 @@ int do_apply(fdg_ctx *c, const double *b, double *s) {
 }
 
 int do_matvec(fdg_ctx *c, const double *x, double *y) {
-  TimedLaunch tl(c, 1);
   if (c->op_kind == 1) {
-    KronBands bd;
-    for (int l = 0; l < 3; ++l) {
-      const int q = l < c->d ? l : 0;
-      bd.M[l] = c->bandM[q];
-      bd.K[l] = c->bandK[q];
-      bd.lo[l] = c->bandlo[q];
-      bd.w[l] = c->bandw[q];
-    }
-    bd.rows4 = c->bandrows4[c->d == 3 ? 1 : 0];
-    bd.rows16 = c->bandrows16[c->d == 3 ? 1 : 0];
-    bd.step3 = c->bandstep[c->d == 3 ? 2 : 0];
+    int st = FDG_OK;
     if (c->d == 3) {
-      int st = dalloc(&c->mv_a, (size_t)c->N * c->batch);
+      st = dalloc(&c->mv_a, (size_t)c->N * c->batch);
       if (st == FDG_OK) st = dalloc(&c->mv_c, (size_t)c->N * c->batch);
       if (st != FDG_OK) return st;
     }
-    launch_kron_matvec_f64(c->stream, x, y, c->d, c->n, c->batch, bd, c->mv_a, c->mv_c);
-  } else {
-    launch_ell_matvec_f64(c->stream, x, y, c->N, c->N, c->ell_width, c->ell_col, c->ell_val, c->batch);
+    return matvec_entries(c, cstrided(x, c->N), mstrided(y, c->N), c->batch, c->mv_a, c->mv_c);
   }
+  TimedLaunch tl(c, 1);
+  launch_ell_matvec_f64(c->stream, x, y, c->N, c->N, c->ell_width, c->ell_col, c->ell_val, c->batch);
   return hip_check(hipGetLastError(), "matvec launch");
 }
+
+}  // namespace
+
+namespace fdg {
+
+int apply_prec_entries(fdg_ctx *c, CBatch in, MBatch out, int64_t nentries, bool aligned32, double *t1, double *t2) {
+  const int n = c->n;
+  const int64_t N = c->N;
+  if (c->d == 3) {
+    {
+      TimedLaunch tl(c, 0);
+      launch_slab_f64(c->stream, in, mstrided(t1, N), c->Wv[0], c->Wv[1], c->ldw, n, nentries, n, false, nullptr,
+                      nullptr, aligned32);
+    }
+    {
+      TimedLaunch tl(c, 3);
+      launch_fibre_f64(c->stream, cstrided(t1, N), mstrided(t2, N), c->Wv[2], c->Wu[2], c->ldw, n, nentries,
+                       c->lam[0], c->lam[1], c->lam[2]);
+    }
+    {
+      TimedLaunch tl(c, 0);
+      launch_slab_f64(c->stream, cstrided(t2, N), out, c->Wu[0], c->Wu[1], c->ldw, n, nentries, n, false, nullptr,
+                      nullptr, aligned32);
+    }
+  } else {
+    {
+      TimedLaunch tl(c, 0);
+      launch_slab_f64(c->stream, in, mstrided(t1, N), c->Wv[0], c->Wv[1], c->ldw, n, nentries, 1, true, c->lam[0],
+                      c->lam[1], aligned32);
+    }
+    {
+      TimedLaunch tl(c, 0);
+      launch_slab_f64(c->stream, cstrided(t1, N), out, c->Wu[0], c->Wu[1], c->ldw, n, nentries, 1, false, nullptr,
+                      nullptr, aligned32);
+    }
+  }
+  return hip_check(hipGetLastError(), "apply_prec launch");
+}
+
+int matvec_entries(fdg_ctx *c, CBatch x, MBatch y, int64_t nentries, double *tmp_a, double *tmp_c) {
+  TimedLaunch tl(c, 1);
+  KronBands bd;
+  for (int l = 0; l < 3; ++l) {
+    const int q = l < c->d ? l : 0;
+    bd.M[l] = c->bandM[q];
+    bd.K[l] = c->bandK[q];
+    bd.lo[l] = c->bandlo[q];
+    bd.w[l] = c->bandw[q];
+  }
+  bd.rows4 = c->bandrows4[c->d == 3 ? 1 : 0];
+  bd.rows16 = c->bandrows16[c->d == 3 ? 1 : 0];
+  bd.step3 = c->bandstep[c->d == 3 ? 2 : 0];
+  if (!launch_kron_matvec_f64(c->stream, x, y, c->d, c->n, nentries, bd, tmp_a, tmp_c))
+    return set_error(FDG_EINVAL, "matvec: this operator shape needs a contiguous batch");
+  return hip_check(hipGetLastError(), "matvec launch");
+}
+
+}  // namespace fdg
+
+namespace {
 
 int ensure_krylov(fdg_ctx *c, int m) {
   if (c->restart_alloc >= m) return FDG_OK;
@@ -561,7 +489,7 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
 
   {  // partials of ||b||^2; reduced by the first scaling of b or read directly below
     TimedLaunch tl(c, 2);
-    launch_dots(c->stream, b, 0, 1, b, N, 1, G, c->P3);
+    launch_dots(c->stream, cstrided(b, 0), 0, IBatch{1, nullptr}, cstrided(b, 0), N, 1, G, 1, c->P3, al(b, 16));
   }
   fdg_info inf;
   std::memset(&inf, 0, sizeof(inf));
@@ -584,7 +512,7 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   bool x_nonzero = (flags & FDG_SOLVE_USE_X0) != 0;
   if (x_nonzero || limit == 0) {
     TimedLaunch tl(c, 2);
-    launch_norm_reduce(c->stream, c->P3, G, 1, bn_dev, 0, bn_hd, 0);
+    launch_norm_reduce(c->stream, c->P3, G, 1, mstrided(bn_dev, 0), mstrided(bn_hd, 0));
   }
   if (!x_nonzero && limit == 0) {  // nothing to iterate: x = 0
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -605,11 +533,12 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       if ((st = do_matvec(c, x, c->t1)) != FDG_OK) return st;
       {
         TimedLaunch tl(c, 2);
-        launch_residual(c->stream, b, c->t1, Vq(0), N, 1, G, c->P3);
+        launch_residual(c->stream, cstrided(b, 0), cstrided(c->t1, 0), mstrided(Vq(0), 0), N, 1, G, c->P3);
       }
       {
         TimedLaunch tl(c, 2);
-        launch_scale_reduce(c->stream, Vq(0), Vq(0), c->P3, G, N, 1, beta_dev, 0, beta_hd, 0);
+        launch_scale_reduce(c->stream, cstrided(Vq(0), 0), mstrided(Vq(0), 0), c->P3, G, N, 1, mstrided(beta_dev, 0),
+                            mstrided(beta_hd, 0), true);
       }
       HIPCHK(hipStreamSynchronize(c->stream));
       if (bnorm < 0.0) learn_bnorm();
@@ -624,7 +553,8 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       if ((!fixed && beta <= target) || total >= limit) break;
     } else {  // x = 0: r = b, v0 = b / ||b|| (||b|| reaches the host with the first column)
       TimedLaunch tl(c, 2);
-      launch_scale_reduce(c->stream, b, Vq(0), c->P3, G, N, 1, bn_dev, 0, bn_hd, 0);
+      launch_scale_reduce(c->stream, cstrided(b, 0), mstrided(Vq(0), 0), c->P3, G, N, 1, mstrided(bn_dev, 0),
+                          mstrided(bn_hd, 0), al(b, 16));
     }
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;  // completed below when ||b|| arrives with the first column
@@ -637,19 +567,22 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       const int nv = j + 1;
       {  // classical Gram-Schmidt: h1 = V^T w
         TimedLaunch tl(c, 2);
-        launch_dots(c->stream, V, N, nv, w, N, 1, G, c->P1);
+        launch_dots(c->stream, cstrided(V, 0), N, IBatch{nv, nullptr}, cstrided(w, 0), N, 1, G, m + 1, c->P1, true);
       }
       {  // w -= V h1; h2 = V^T w (reorthogonalisation)
         TimedLaunch tl(c, 2);
-        launch_update_dots(c->stream, V, N, nv, c->P1, G, w, N, 1, c->P2, h1, 0);
+        launch_update_dots(c->stream, cstrided(V, 0), N, IBatch{nv, nullptr}, c->P1, G, m + 1, mstrided(w, 0), N, 1,
+                           c->P2, mstrided(h1, 0), true);
       }
       {  // w -= V h2; Hessenberg column h1 + h2 to the host; ||w||
         TimedLaunch tl(c, 2);
-        launch_update_norm(c->stream, V, N, nv, c->P2, G, w, N, 1, c->P3, h1, c->Hcol, 0, hcol_d, 0);
+        launch_update_norm(c->stream, cstrided(V, 0), N, IBatch{nv, nullptr}, c->P2, G, m + 1, mstrided(w, 0), N, 1,
+                           c->P3, cstrided(h1, 0), mstrided(c->Hcol, 0), mstrided(hcol_d, 0), true);
       }
       {  // h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}
         TimedLaunch tl(c, 2);
-        launch_scale_reduce(c->stream, w, w, c->P3, G, N, 1, c->Hcol + nv, 0, hcol_d + nv, 0);
+        launch_scale_reduce(c->stream, cstrided(w, 0), mstrided(w, 0), c->P3, G, N, 1, mstrided(c->Hcol + nv, 0),
+                            mstrided(hcol_d + nv, 0), true);
       }
       HIPCHK(hipGetLastError());
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -699,7 +632,8 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
     }
     {
       TimedLaunch tl(c, 2);
-      launch_lincomb(c->stream, x, Z, N, k, y, N, 1, !x_nonzero);
+      launch_lincomb(c->stream, mstrided(x, 0), cstrided(Z, 0), N, IBatch{k, nullptr}, y, nullptr, N, 1,
+                     IBatch{x_nonzero ? 0 : 1, nullptr});
     }
     x_nonzero = true;
     ++restarts;
@@ -707,11 +641,11 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       if ((st = do_matvec(c, x, c->t1)) != FDG_OK) return st;
       {
         TimedLaunch tl(c, 2);
-        launch_residual(c->stream, b, c->t1, Vq(0), N, 1, G, c->P3);
+        launch_residual(c->stream, cstrided(b, 0), cstrided(c->t1, 0), mstrided(Vq(0), 0), N, 1, G, c->P3);
       }
       {
         TimedLaunch tl(c, 2);
-        launch_norm_reduce(c->stream, c->P3, G, 1, beta_dev, 0, beta_hd, 0);
+        launch_norm_reduce(c->stream, c->P3, G, 1, mstrided(beta_dev, 0), mstrided(beta_hd, 0));
       }
       HIPCHK(hipStreamSynchronize(c->stream));
       rbeta = *beta_h;

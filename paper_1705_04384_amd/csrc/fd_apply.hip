@@ -18,6 +18,7 @@
 
 #include <cstdint>
 
+#include "batch_addr.h"
 #include "fd_apply.h"
 
 namespace fdg {
@@ -128,9 +129,9 @@ __device__ inline void gemm_preloaded_a(int kpad, const double (&xa)[MT][KB][4],
 // The LDS buffer holds the W1 column tile during GEMM1 and then Y1 (transposed).
 // ------------------------------------------------------------------------------------
 template <int WAVES, int MT, bool VEC, bool DIV, bool PRE>
-__global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(const double *__restrict__ X, double *__restrict__ Y,
+__global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBatch Y,
                                                      const double *__restrict__ W1, const double *__restrict__ W2,
-                                                     int ldw, int n, int64_t nslab, int ncb, int xcd_remap,
+                                                     int ldw, int n, int64_t nslab, int spe, int ncb, int xcd_remap,
                                                      const double *__restrict__ lam1,
                                                      const double *__restrict__ lam2) {
   constexpr int MPAD = WAVES * MT * 16;
@@ -154,8 +155,9 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(const double *
   }
   if (s >= nslab) return;
   const int64_t n2 = (int64_t)n * n;
-  const double *Xs = X + s * n2;
-  double *Ys = Y + s * n2;
+  const int64_t ent = s / spe, loc = s - ent * spe;  // batch entry and slab inside it
+  const double *__restrict__ Xs = X.at(ent) + loc * n2;
+  double *__restrict__ Ys = Y.at(ent) + loc * n2;
   const int c0 = cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(const double *
 //   GEMM2: S[k3][c] = sum_k Wb[k3][k] T[k][c]        (T back in LDS, transposed)
 // ------------------------------------------------------------------------------------
 template <int WAVES, int MT>
-__global__ __launch_bounds__(64 * WAVES) void k_fibre(const double *__restrict__ X, double *__restrict__ Y,
+__global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
                                                       const double *__restrict__ Wa, const double *__restrict__ Wb,
                                                       int ldw, int n, int ncb, const double *__restrict__ lam1,
                                                       const double *__restrict__ lam2,
@@ -269,8 +271,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(const double *__restrict__
   const int64_t bidx = blockIdx.x / ncb;
   const int cb = (int)(blockIdx.x % ncb);
   const int64_t n2 = (int64_t)n * n;
-  const double *Xb = X + bidx * n2 * n;
-  double *Yb = Y + bidx * n2 * n;
+  const double *__restrict__ Xb = X.at(bidx);
+  double *__restrict__ Yb = Y.at(bidx);
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
@@ -328,33 +330,33 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(const double *__restrict__
 }
 
 template <int WAVES, int MT>
-void slab_launch(hipStream_t s, const double *X, double *Y, const double *W1, const double *W2, int ldw, int n,
-                 int64_t nslab, bool div, const double *lam1, const double *lam2) {
+void slab_launch(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
+                 int64_t nslab, int spe, bool div, const double *lam1, const double *lam2, bool aligned32) {
   const int ncb = (n + kNB - 1) / kNB;
   const int64_t nwg = nslab * ncb;
   const int remap = (nslab % 8 == 0) ? 1 : 0;
-  const bool vec = (n % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 31) == 0);
+  const bool vec = (n % 4 == 0) && aligned32;
   const dim3 grid((unsigned)nwg), blk(64 * WAVES);
   constexpr bool PRE = false;  // preloading the X strip measured slower at n = 128
   if (div) {
     if (vec)
-      hipLaunchKernelGGL((k_slab<WAVES, MT, true, true, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb,
+      hipLaunchKernelGGL((k_slab<WAVES, MT, true, true, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, spe, ncb,
                          remap, lam1, lam2);
     else
-      hipLaunchKernelGGL((k_slab<WAVES, MT, false, true, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb,
-                         remap, lam1, lam2);
+      hipLaunchKernelGGL((k_slab<WAVES, MT, false, true, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, spe,
+                         ncb, remap, lam1, lam2);
   } else {
     if (vec)
-      hipLaunchKernelGGL((k_slab<WAVES, MT, true, false, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb,
-                         remap, lam1, lam2);
+      hipLaunchKernelGGL((k_slab<WAVES, MT, true, false, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, spe,
+                         ncb, remap, lam1, lam2);
     else
-      hipLaunchKernelGGL((k_slab<WAVES, MT, false, false, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb,
-                         remap, lam1, lam2);
+      hipLaunchKernelGGL((k_slab<WAVES, MT, false, false, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, spe,
+                         ncb, remap, lam1, lam2);
   }
 }
 
 template <int WAVES, int MT>
-void fibre_launch(hipStream_t s, const double *X, double *Y, const double *Wa, const double *Wb, int ldw, int n,
+void fibre_launch(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const double *Wb, int ldw, int n,
                   int64_t batch, const double *lam1, const double *lam2, const double *lam3) {
   const int64_t n2 = (int64_t)n * n;
   const int ncb = (int)((n2 + kNB - 1) / kNB);
@@ -387,19 +389,21 @@ static Shape pick_shape(int n) {
 
 #define FDG_SHAPES(X) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(4, 2) X(6, 2) X(8, 2) X(4, 3) X(12, 1)
 
-void launch_slab_f64(hipStream_t s, const double *X, double *Y, const double *W1, const double *W2, int ldw, int n,
-                     int64_t nslab, bool divide, const double *lam1, const double *lam2) {
+void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
+                     int64_t nentries, int spe, bool divide, const double *lam1, const double *lam2,
+                     bool aligned32) {
   const Shape sh = pick_shape(n);
-#define FDG_CASE(W, M)                                                                  \
-  if (sh.waves == W && sh.mt == M) {                                                   \
-    slab_launch<W, M>(s, X, Y, W1, W2, ldw, n, nslab, divide, lam1, lam2);            \
-    return;                                                                            \
+  const int64_t nslab = nentries * spe;
+#define FDG_CASE(W, M)                                                                    \
+  if (sh.waves == W && sh.mt == M) {                                                     \
+    slab_launch<W, M>(s, X, Y, W1, W2, ldw, n, nslab, spe, divide, lam1, lam2, aligned32); \
+    return;                                                                              \
   }
   FDG_SHAPES(FDG_CASE)
 #undef FDG_CASE
 }
 
-void launch_fibre_f64(hipStream_t s, const double *X, double *Y, const double *Wa, const double *Wb, int ldw, int n,
+void launch_fibre_f64(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const double *Wb, int ldw, int n,
                       int64_t batch, const double *lam1, const double *lam2, const double *lam3) {
   const Shape sh = pick_shape(n);
 #define FDG_CASE(W, M)                                                                  \

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "batch_addr.h"
+
 namespace fdg {
 
 // Number of partial-sum blocks of a reduction over vectors of length N.  Depends on N
@@ -37,7 +39,8 @@ struct KronBands {
 };
 // Requires non-decreasing band starts lo[] and w <= kron_window_max().  tmp_a, tmp_c:
 // scratch of nbatch * n^3 doubles each for the two-pass 3D form (may be NULL: one pass).
-void launch_kron_matvec_f64(hipStream_t s, const double *x, double *y, int d, int n, int64_t nbatch,
+// Returns false (nothing launched) for a gathered batch the two-pass form cannot take.
+bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int64_t nbatch,
                             const KronBands &bands, double *tmp_a, double *tmp_c);
 int kron_window_max();
 
@@ -56,28 +59,31 @@ struct Coeffs {
   double v[256];
 };
 
+// Batch entry e of a Krylov kernel: basis (q = 0) at V.at(e), vector q at + q*ldv;
+// nv.at(e) basis vectors; partial g of component q at P[(e*G + g)*ldp + q].
+// aligned16_all: every pointer involved is 16-byte aligned (enables 2-wide accesses).
+
 // P = partial sums of V_q . w, q < nv.
-void launch_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *w, int64_t N,
-                 int64_t nbatch, int G, double *P);
-// h1 = sum(Pin) (block 0 stores it to hout[b*hstride + q]); w -= V h1; Pout = partials of V^T w.
-void launch_update_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G,
-                        double *w, int64_t N, int64_t nbatch, double *Pout, double *hout, int hstride);
-// h2 = sum(Pin); Hcol = h1 + h2 (and host copy); w -= V h2; Pnorm = partials of |w|^2.
-void launch_update_norm(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G,
-                        double *w, int64_t N, int64_t nbatch, double *Pnorm, const double *h1,
-                        double *Hcol, int hstride, double *host, int host_stride);
-// d = sqrt(sum(Pn)); v = w / d (0 if d = 0; v may equal w); d stored to out and host.
-void launch_scale_reduce(hipStream_t s, const double *w, double *v, const double *Pn, int G, int64_t N,
-                         int64_t nbatch, double *out, int ostride, double *host, int host_stride);
-// d = sqrt(sum(Pn)) stored to out and host.
-void launch_norm_reduce(hipStream_t s, const double *Pn, int G, int64_t nbatch, double *out, int ostride,
-                        double *host, int host_stride);
-// x = (overwrite ? 0 : x) + sum_q Z_q y[q], q < k <= 256 (the same coefficients for every
-// batch entry).
-void launch_lincomb(hipStream_t s, double *x, const double *Z, int64_t ldz, int k, const Coeffs &y,
-                    int64_t N, int64_t nbatch, bool overwrite);
-// r = b - Ax and the partials of |r|^2.
-void launch_residual(hipStream_t s, const double *b, const double *Ax, double *r, int64_t N,
-                     int64_t nbatch, int G, double *P);
+void launch_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch w, int64_t N, int64_t nbatch,
+                 int G, int ldp, double *P, bool aligned16_all);
+// h1 = sum(Pin) (block 0 stores it to hout.at(e)); w -= V h1; Pout = partials of V^T w.
+void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const double *Pin, int G, int ldp,
+                        MBatch w, int64_t N, int64_t nbatch, double *Pout, MBatch hout, bool aligned16_all);
+// h2 = sum(Pin); Hcol = h1 + h2 (and host copy); w -= V h2; Pnorm[e*G + g] = partials of |w|^2.
+void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const double *Pin, int G, int ldp,
+                        MBatch w, int64_t N, int64_t nbatch, double *Pnorm, CBatch h1, MBatch Hcol,
+                        MBatch host, bool aligned16_all);
+// d = sqrt(sum(Pn[e*G ..])); v = w / d (0 if d = 0; v may equal w); d to out.at(e)[0], host.at(e)[0].
+void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, const double *Pn, int G, int64_t N,
+                         int64_t nbatch, MBatch out, MBatch host, bool aligned16_all);
+// d = sqrt(sum(Pn[e*G ..])) to out and host.
+void launch_norm_reduce(hipStream_t s, const double *Pn, int G, int64_t nbatch, MBatch out, MBatch host);
+// x = (overwrite ? 0 : x) + sum_q Z_q y_q, q < k.at(e) <= 256; coefficients from ytab[e*256 + q]
+// when ytab is given, else y (shared by every entry).
+void launch_lincomb(hipStream_t s, MBatch x, CBatch Z, int64_t ldz, IBatch k, const Coeffs &y,
+                    const double *ytab, int64_t N, int64_t nbatch, IBatch overwrite);
+// r = b - Ax and the partials P[e*G + g] of |r|^2.
+void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G,
+                     double *P);
 
 }  // namespace fdg

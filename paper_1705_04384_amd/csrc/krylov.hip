@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "batch_addr.h"
 #include "kernels.h"
 
 namespace fdg {
@@ -43,14 +44,15 @@ __device__ inline void chunk_of(int64_t N, int G, int g, int64_t &beg, int64_t &
   end = beg + chunk < N ? beg + chunk : N;
 }
 
-// Fixed-order sum of the G <= 256 partials of component q, valid in every lane.
-__device__ inline double sum_partials(const double *P, int G, int ncomp, int q) {
+// Fixed-order sum of the G <= 256 partials of component q (partial g of component q at
+// P[g * ldp + q]), valid in every lane.
+__device__ inline double sum_partials(const double *P, int G, int ldp, int q) {
   const int lane = threadIdx.x & 63;
   double v[kMaxG / 64];
 #pragma unroll
   for (int k = 0; k < kMaxG / 64; ++k) {
     const int g = lane + 64 * k;
-    v[k] = g < G ? P[(int64_t)g * ncomp + q] : 0.0;
+    v[k] = g < G ? P[(int64_t)g * ldp + q] : 0.0;
   }
   double s = 0.0;
 #pragma unroll
@@ -59,10 +61,10 @@ __device__ inline double sum_partials(const double *P, int G, int ncomp, int q) 
 }
 
 // hs[q] = sum of the partials of component q, q < ncomp (all waves of the block help).
-__device__ inline void reduce_into(const double *P, int G, int ncomp, double *hs, int nwaves) {
+__device__ inline void reduce_into(const double *P, int G, int ldp, int ncomp, double *hs, int nwaves) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int q = wave; q < ncomp; q += nwaves) {
-    const double s = sum_partials(P, G, ncomp, q);
+    const double s = sum_partials(P, G, ldp, q);
     if (lane == 0) hs[q] = s;
   }
   __syncthreads();
@@ -158,16 +160,17 @@ __device__ inline double block_sum(double v, double *red) {
 }
 
 template <bool VEC>
-__global__ __launch_bounds__(kRed) void k_dots(const double *__restrict__ V, int64_t ldv, int nv,
-                                               const double *__restrict__ w, int64_t N, int G,
-                                               double *__restrict__ P) {
+__global__ __launch_bounds__(kRed) void k_dots(CBatch V, int64_t ldv, IBatch nvs, CBatch w, int64_t N, int G,
+                                               int ldp, double *__restrict__ P) {
   __shared__ double red[kRedWaves][kQB];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
+  const int nv = nvs.at(b);
   int64_t beg, end;
   chunk_of(N, G, g, beg, end);
-  const double *wb = w + b * N, *Vb = V + b * N;
-  double *Pg = P + ((int64_t)b * G + g) * nv;
+  const double *__restrict__ wb = w.at(b);
+  const double *__restrict__ Vb = V.at(b);
+  double *Pg = P + ((int64_t)b * G + g) * ldp;
   for (int q0 = 0; q0 < nv; q0 += kQB) {
     double acc[kQB];
     chunk_dots<VEC>(Vb, ldv, nv, q0, wb, beg, end, acc);
@@ -177,24 +180,26 @@ __global__ __launch_bounds__(kRed) void k_dots(const double *__restrict__ V, int
 
 // h1 = reduce(Pin); w -= V h1; Pout = partial dots V^T w.  Block 0 stores h1 to hout.
 template <bool VEC>
-__global__ __launch_bounds__(kRed) void k_update_dots(const double *__restrict__ V, int64_t ldv, int nv,
-                                                      const double *__restrict__ Pin, int G, double *__restrict__ w,
-                                                      int64_t N, double *__restrict__ Pout,
-                                                      double *__restrict__ hout, int hstride) {
+__global__ __launch_bounds__(kRed) void k_update_dots(CBatch V, int64_t ldv, IBatch nvs,
+                                                      const double *__restrict__ Pin, int G, int ldp, MBatch w,
+                                                      int64_t N, double *__restrict__ Pout, MBatch hout) {
   __shared__ double hs[256];
   __shared__ double red[kRedWaves][kQB];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
-  reduce_into(Pin + (int64_t)b * G * nv, G, nv, hs, kRedWaves);
-  if (g == 0)
-    for (int q = threadIdx.x; q < nv; q += kRed) hout[b * hstride + q] = hs[q];
+  const int nv = nvs.at(b);
+  reduce_into(Pin + (int64_t)b * G * ldp, G, ldp, nv, hs, kRedWaves);
+  if (g == 0) {
+    double *ho = hout.at(b);
+    for (int q = threadIdx.x; q < nv; q += kRed) ho[q] = hs[q];
+  }
   int64_t beg, end;
   chunk_of(N, G, g, beg, end);
-  double *wb = w + b * N;
-  const double *Vb = V + b * N;
+  double *__restrict__ wb = w.at(b);
+  const double *__restrict__ Vb = V.at(b);
   (void)chunk_update<VEC>(Vb, ldv, nv, hs, wb, beg, end);
   __syncthreads();  // the block's own chunk of w is complete before it is re-read
-  double *Pg = Pout + ((int64_t)b * G + g) * nv;
+  double *Pg = Pout + ((int64_t)b * G + g) * ldp;
   for (int q0 = 0; q0 < nv; q0 += kQB) {
     double acc[kQB];
     chunk_dots<VEC>(Vb, ldv, nv, q0, wb, beg, end, acc);
@@ -205,45 +210,47 @@ __global__ __launch_bounds__(kRed) void k_update_dots(const double *__restrict__
 // h2 = reduce(Pin); w -= V h2; Pnorm = partial |w|^2.  Block 0 stores the Hessenberg
 // column Hcol[q] = h1[q] + h2[q] (device and, when given, host-mapped memory).
 template <bool VEC>
-__global__ __launch_bounds__(kRed) void k_update_norm(const double *__restrict__ V, int64_t ldv, int nv,
-                                                      const double *__restrict__ Pin, int G, double *__restrict__ w,
-                                                      int64_t N, double *__restrict__ Pnorm,
-                                                      const double *__restrict__ h1, double *__restrict__ Hcol,
-                                                      int hstride, double *__restrict__ host, int host_stride) {
+__global__ __launch_bounds__(kRed) void k_update_norm(CBatch V, int64_t ldv, IBatch nvs,
+                                                      const double *__restrict__ Pin, int G, int ldp, MBatch w,
+                                                      int64_t N, double *__restrict__ Pnorm, CBatch h1, MBatch Hcol,
+                                                      MBatch host) {
   __shared__ double hs[256];
   __shared__ double red[kRedWaves];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
-  reduce_into(Pin + (int64_t)b * G * nv, G, nv, hs, kRedWaves);
-  if (g == 0)
+  const int nv = nvs.at(b);
+  reduce_into(Pin + (int64_t)b * G * ldp, G, ldp, nv, hs, kRedWaves);
+  if (g == 0) {
+    const double *h1b = h1.at(b);
+    double *hc = Hcol.at(b);
+    double *hh = host.valid() ? host.at(b) : nullptr;
     for (int q = threadIdx.x; q < nv; q += kRed) {
-      const double v = h1[b * hstride + q] + hs[q];
-      Hcol[b * hstride + q] = v;
-      if (host) host[b * host_stride + q] = v;
+      const double v = h1b[q] + hs[q];
+      hc[q] = v;
+      if (hh) hh[q] = v;
     }
+  }
   int64_t beg, end;
   chunk_of(N, G, g, beg, end);
-  const double nrm = chunk_update<VEC>(V + b * N, ldv, nv, hs, w + b * N, beg, end);
+  const double nrm = chunk_update<VEC>(V.at(b), ldv, nv, hs, w.at(b), beg, end);
   const double s = block_sum(nrm, red);
   if (threadIdx.x == 0) Pnorm[(int64_t)b * G + g] = s;
 }
 
-// nrm = sqrt(reduce(Pn)); v = w / nrm (0 if nrm = 0).  Block 0 stores nrm to out and host.
+// d = sqrt(reduce(Pn)); v = w / d (0 if d = 0).  Block 0 stores d to out and host.
 template <bool VEC>
-__global__ __launch_bounds__(kBlock) void k_scale_reduce(const double *__restrict__ w, double *__restrict__ v,
-                                                         const double *__restrict__ Pn, int G, int64_t N,
-                                                         double *__restrict__ out, int ostride,
-                                                         double *__restrict__ host, int host_stride) {
+__global__ __launch_bounds__(kBlock) void k_scale_reduce(CBatch w, MBatch v, const double *__restrict__ Pn, int G,
+                                                         int64_t N, MBatch out, MBatch host) {
   __shared__ double hs[1];
   const int64_t b = blockIdx.y;
-  reduce_into(Pn + (int64_t)b * G, G, 1, hs, kBlock / 64);
+  reduce_into(Pn + (int64_t)b * G, G, 1, 1, hs, kBlock / 64);
   const double d = sqrt(hs[0]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (out) out[b * ostride] = d;
-    if (host) host[b * host_stride] = d;
+    if (out.valid()) out.at(b)[0] = d;
+    if (host.valid()) host.at(b)[0] = d;
   }
-  const double *wb = w + b * N;
-  double *vb = v + b * N;
+  const double *wb = w.at(b);
+  double *vb = v.at(b);
   if (VEC) {
     for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < N; i += (int64_t)gridDim.x * kBlock * 2) {
       const double2 x = *reinterpret_cast<const double2 *>(wb + i);
@@ -255,45 +262,50 @@ __global__ __launch_bounds__(kBlock) void k_scale_reduce(const double *__restric
   }
 }
 
-// out = sqrt(reduce(Pn)) to device and host memory (one block per batch entry).
-__global__ __launch_bounds__(kBlock) void k_norm_reduce(const double *__restrict__ Pn, int G,
-                                                        double *__restrict__ out, int ostride,
-                                                        double *__restrict__ host, int host_stride) {
+// d = sqrt(reduce(Pn)) stored to out and host (one block per batch entry).
+__global__ __launch_bounds__(kBlock) void k_norm_reduce(const double *__restrict__ Pn, int G, MBatch out,
+                                                        MBatch host) {
   __shared__ double hs[1];
   const int64_t b = blockIdx.x;
-  reduce_into(Pn + (int64_t)b * G, G, 1, hs, kBlock / 64);
+  reduce_into(Pn + (int64_t)b * G, G, 1, 1, hs, kBlock / 64);
   if (threadIdx.x == 0) {
     const double d = sqrt(hs[0]);
-    if (out) out[b * ostride] = d;
-    if (host) host[b * host_stride] = d;
+    if (out.valid()) out.at(b)[0] = d;
+    if (host.valid()) host.at(b)[0] = d;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_lincomb(double *__restrict__ x, const double *__restrict__ Z,
-                                                    int64_t ldz, int k, Coeffs y, int64_t N, int overwrite) {
+// x = (overwrite ? 0 : x) + sum_q Z_q y_q, q < k; y from a device table (256 per entry)
+// or, without a table, the by-value coefficients shared by every entry.
+__global__ __launch_bounds__(kBlock) void k_lincomb(MBatch x, CBatch Z, int64_t ldz, IBatch ks, Coeffs y,
+                                                    const double *__restrict__ ytab, int64_t N, IBatch overwrite) {
   const int64_t b = blockIdx.y;
-  double *xb = x + b * N;
-  const double *Zb = Z + b * N;
+  double *__restrict__ xb = x.at(b);
+  const double *__restrict__ Zb = Z.at(b);
+  const int k = ks.at(b);
+  const bool ow = overwrite.at(b) != 0;
+  const double *yb = ytab ? ytab + b * 256 : y.v;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock) {
-    double acc = overwrite ? 0.0 : xb[i];
-    for (int q = 0; q < k; ++q) acc = fma(Zb[(int64_t)q * ldz + i], y.v[q], acc);
+    double acc = ow ? 0.0 : xb[i];
+    for (int q = 0; q < k; ++q) acc = fma(Zb[(int64_t)q * ldz + i], yb[q], acc);
     xb[i] = acc;
   }
 }
 
-__global__ __launch_bounds__(kRed) void k_residual(const double *__restrict__ bv, const double *__restrict__ Ax,
-                                                   double *__restrict__ r, int64_t N, int G, double *__restrict__ P) {
+__global__ __launch_bounds__(kRed) void k_residual(CBatch bv, CBatch Ax, MBatch r, int64_t N, int G,
+                                                   double *__restrict__ P) {
   __shared__ double red[kRedWaves];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
   int64_t beg, end;
   chunk_of(N, G, g, beg, end);
+  const double *bb = bv.at(b), *ab = Ax.at(b);
+  double *rb = r.at(b);
   double nrm = 0.0;
 #pragma unroll 4
   for (int64_t i = beg + threadIdx.x; i < end; i += kRed) {
-    const int64_t e = b * N + i;
-    const double v = bv[e] - Ax[e];
-    r[e] = v;
+    const double v = bb[i] - ab[i];
+    rb[i] = v;
     nrm = fma(v, v, nrm);
   }
   const double s = block_sum(nrm, red);
@@ -317,63 +329,58 @@ int reduction_blocks(int64_t N) {
   return (int)g;
 }
 
-void launch_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *w, int64_t N, int64_t nbatch,
-                 int G, double *P) {
-  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16(V) && aligned16(w);
+void launch_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch w, int64_t N, int64_t nbatch, int G,
+                 int ldp, double *P, bool aligned16_all) {
+  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16_all;
   const dim3 grid(G, (unsigned)nbatch), blk(kRed);
   if (vec)
-    hipLaunchKernelGGL(k_dots<true>, grid, blk, 0, s, V, ldv, nv, w, N, G, P);
+    hipLaunchKernelGGL(k_dots<true>, grid, blk, 0, s, V, ldv, nv, w, N, G, ldp, P);
   else
-    hipLaunchKernelGGL(k_dots<false>, grid, blk, 0, s, V, ldv, nv, w, N, G, P);
+    hipLaunchKernelGGL(k_dots<false>, grid, blk, 0, s, V, ldv, nv, w, N, G, ldp, P);
 }
 
-void launch_update_dots(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G, double *w,
-                        int64_t N, int64_t nbatch, double *Pout, double *hout, int hstride) {
-  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16(V) && aligned16(w);
+void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const double *Pin, int G, int ldp, MBatch w,
+                        int64_t N, int64_t nbatch, double *Pout, MBatch hout, bool aligned16_all) {
+  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16_all;
   const dim3 grid(G, (unsigned)nbatch), blk(kRed);
   if (vec)
-    hipLaunchKernelGGL(k_update_dots<true>, grid, blk, 0, s, V, ldv, nv, Pin, G, w, N, Pout, hout, hstride);
+    hipLaunchKernelGGL(k_update_dots<true>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pout, hout);
   else
-    hipLaunchKernelGGL(k_update_dots<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, w, N, Pout, hout, hstride);
+    hipLaunchKernelGGL(k_update_dots<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pout, hout);
 }
 
-void launch_update_norm(hipStream_t s, const double *V, int64_t ldv, int nv, const double *Pin, int G, double *w,
-                        int64_t N, int64_t nbatch, double *Pnorm, const double *h1, double *Hcol, int hstride,
-                        double *host, int host_stride) {
-  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16(V) && aligned16(w);
+void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const double *Pin, int G, int ldp, MBatch w,
+                        int64_t N, int64_t nbatch, double *Pnorm, CBatch h1, MBatch Hcol, MBatch host,
+                        bool aligned16_all) {
+  const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16_all;
   const dim3 grid(G, (unsigned)nbatch), blk(kRed);
   if (vec)
-    hipLaunchKernelGGL(k_update_norm<true>, grid, blk, 0, s, V, ldv, nv, Pin, G, w, N, Pnorm, h1, Hcol, hstride,
-                       host, host_stride);
+    hipLaunchKernelGGL(k_update_norm<true>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pnorm, h1, Hcol, host);
   else
-    hipLaunchKernelGGL(k_update_norm<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, w, N, Pnorm, h1, Hcol, hstride,
-                       host, host_stride);
+    hipLaunchKernelGGL(k_update_norm<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pnorm, h1, Hcol, host);
 }
 
-void launch_scale_reduce(hipStream_t s, const double *w, double *v, const double *Pn, int G, int64_t N,
-                         int64_t nbatch, double *out, int ostride, double *host, int host_stride) {
-  if (N % 2 == 0 && aligned16(w) && aligned16(v))
+void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, const double *Pn, int G, int64_t N, int64_t nbatch,
+                         MBatch out, MBatch host, bool aligned16_all) {
+  if (N % 2 == 0 && aligned16_all)
     hipLaunchKernelGGL(k_scale_reduce<true>, dim3(stream_blocks(N, 2), (unsigned)nbatch), dim3(kBlock), 0, s, w, v,
-                       Pn, G, N, out, ostride, host, host_stride);
+                       Pn, G, N, out, host);
   else
     hipLaunchKernelGGL(k_scale_reduce<false>, dim3(stream_blocks(N, 1), (unsigned)nbatch), dim3(kBlock), 0, s, w, v,
-                       Pn, G, N, out, ostride, host, host_stride);
+                       Pn, G, N, out, host);
 }
 
-void launch_norm_reduce(hipStream_t s, const double *Pn, int G, int64_t nbatch, double *out, int ostride,
-                        double *host, int host_stride) {
-  hipLaunchKernelGGL(k_norm_reduce, dim3((unsigned)nbatch), dim3(kBlock), 0, s, Pn, G, out, ostride, host,
-                     host_stride);
+void launch_norm_reduce(hipStream_t s, const double *Pn, int G, int64_t nbatch, MBatch out, MBatch host) {
+  hipLaunchKernelGGL(k_norm_reduce, dim3((unsigned)nbatch), dim3(kBlock), 0, s, Pn, G, out, host);
 }
 
-void launch_lincomb(hipStream_t s, double *x, const double *Z, int64_t ldz, int k, const Coeffs &y, int64_t N,
-                    int64_t nbatch, bool overwrite) {
-  hipLaunchKernelGGL(k_lincomb, dim3(stream_blocks(N, 1), (unsigned)nbatch), dim3(kBlock), 0, s, x, Z, ldz, k, y, N,
-                     overwrite ? 1 : 0);
+void launch_lincomb(hipStream_t s, MBatch x, CBatch Z, int64_t ldz, IBatch k, const Coeffs &y, const double *ytab,
+                    int64_t N, int64_t nbatch, IBatch overwrite) {
+  hipLaunchKernelGGL(k_lincomb, dim3(stream_blocks(N, 1), (unsigned)nbatch), dim3(kBlock), 0, s, x, Z, ldz, k, y, ytab,
+                     N, overwrite);
 }
 
-void launch_residual(hipStream_t s, const double *b, const double *Ax, double *r, int64_t N, int64_t nbatch, int G,
-                     double *P) {
+void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G, double *P) {
   hipLaunchKernelGGL(k_residual, dim3(G, (unsigned)nbatch), dim3(kRed), 0, s, b, Ax, r, N, G, P);
 }
 

@@ -13,6 +13,7 @@
 
 #include <cstdint>
 
+#include "batch_addr.h"
 #include "kernels.h"
 
 namespace fdg {
@@ -229,8 +230,8 @@ constexpr int kPlaneRows = 16;                 // i2 rows per pass-1 tile
 constexpr int kPlaneRowsMax = kPlaneRows + 15; // rows j2 the tile may need (w2 <= 16)
 
 template <int WMAX>
-__global__ __launch_bounds__(kBlock) void k_kron3_planes(const double *__restrict__ x, double *__restrict__ ao,
-                                                         double *__restrict__ co, int n, int nplane, KronBands bd) {
+__global__ __launch_bounds__(kBlock) void k_kron3_planes(CBatch x, double *__restrict__ ao,
+                                                         double *__restrict__ co, int n, KronBands bd) {
   __shared__ double sm[kPlaneRowsMax][64];
   __shared__ double sk[kPlaneRowsMax][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -238,7 +239,8 @@ __global__ __launch_bounds__(kBlock) void k_kron3_planes(const double *__restric
   const int i2a = blockIdx.y * kPlaneRows;
   const int64_t pl = blockIdx.z;  // b * n + j3
   const int64_t n2 = (int64_t)n * n;
-  const double *xp = x + pl * n2;
+  const int64_t ent = pl / n;
+  const double *__restrict__ xp = x.at(ent) + (pl - ent * n) * n2;
   const int w1 = bd.w[0], w2 = bd.w[1];
   const bool act1 = i1 < n;
   const int i1c = act1 ? i1 : n - 1;
@@ -304,7 +306,7 @@ constexpr int kRowsPerThread = 4;  // consecutive i3 outputs per thread in pass 
 
 template <int WMAX>
 __global__ __launch_bounds__(kBlock) void k_kron3_mode3(const double *__restrict__ ai, const double *__restrict__ ci,
-                                                        double *__restrict__ y, int n, int ngroups, KronBands bd) {
+                                                        MBatch y, int n, int ngroups, KronBands bd) {
   const int64_t n2 = (int64_t)n * n;
   const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (col >= n2) return;
@@ -340,22 +342,20 @@ __global__ __launch_bounds__(kBlock) void k_kron3_mode3(const double *__restrict
         acc = fma(m3[t], cv[q], acc);
       }
     }
-    y[b * n2 * n + (int64_t)i3 * n2 + col] = acc;
+    y.at(b)[(int64_t)i3 * n2 + col] = acc;
   }
 }
 
 // 2D: one thread owns column i1 and sweeps a chunk of i2; window of direction-1 band sums.
 template <int WMAX>
-__global__ __launch_bounds__(kBlock) void k_kron2_window(const double *__restrict__ x, double *__restrict__ y,
-                                                         int n, KronBands bd) {
+__global__ __launch_bounds__(kBlock) void k_kron2_window(CBatch x, MBatch y, int n, KronBands bd) {
   const int i1 = blockIdx.x * kBlock + threadIdx.x;
   if (i1 >= n) return;
   const int s = blockIdx.y * kChunk;
   const int e = s + kChunk < n ? s + kChunk : n;
   const int64_t b = blockIdx.z;
-  const int64_t N = (int64_t)n * n;
-  const double *xb = x + b * N;
-  double *yb = y + b * N;
+  const double *__restrict__ xb = x.at(b);
+  double *__restrict__ yb = y.at(b);
   const int w1 = bd.w[0], w2 = bd.w[1];
   double m1[WMAX], k1[WMAX];
 #pragma unroll
@@ -434,8 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_ell_f64(const double *__restrict__ x
 
 int kron_window_max() { return 16; }
 
-void launch_kron_matvec_f64(hipStream_t s, const double *x, double *y, int d, int n, int64_t nbatch,
-                            const KronBands &bd, double *tmp_a, double *tmp_c) {
+bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int64_t nbatch, const KronBands &bd,
+                            double *tmp_a, double *tmp_c) {
   int w = 0;
   for (int l = 0; l < d; ++l) w = bd.w[l] > w ? bd.w[l] : w;
   const dim3 blk(kBlock);
@@ -445,30 +445,33 @@ void launch_kron_matvec_f64(hipStream_t s, const double *x, double *y, int d, in
       const int ngroups = (int)cdiv(n, kRowsPerThread);
       const dim3 g2(cdiv((int64_t)n * n, kBlock), (unsigned)(ngroups * nbatch));
       if (w <= 4) {
-        hipLaunchKernelGGL(k_kron3_planes<4>, g1, blk, 0, s, x, tmp_a, tmp_c, n, n, bd);
+        hipLaunchKernelGGL(k_kron3_planes<4>, g1, blk, 0, s, x, tmp_a, tmp_c, n, bd);
         hipLaunchKernelGGL(k_kron3_mode3<4>, g2, blk, 0, s, tmp_a, tmp_c, y, n, ngroups, bd);
       } else {
-        hipLaunchKernelGGL(k_kron3_planes<8>, g1, blk, 0, s, x, tmp_a, tmp_c, n, n, bd);
+        hipLaunchKernelGGL(k_kron3_planes<8>, g1, blk, 0, s, x, tmp_a, tmp_c, n, bd);
         hipLaunchKernelGGL(k_kron3_mode3<8>, g2, blk, 0, s, tmp_a, tmp_c, y, n, ngroups, bd);
       }
-      return;
+      return true;
     }
+    if (x.ptrs || y.ptrs) return false;  // the one-pass forms take contiguous batches only
+    const double *xc = x.base;
+    double *yc = y.base;
     if (bd.rows4 <= kRowsMax && w <= 8) {
       const int nchunk = (int)cdiv(n, kChunk);
       const dim3 grid(cdiv(n, 64), cdiv(n, 4), (unsigned)(nchunk * nbatch));
       if (w <= 4)
-        hipLaunchKernelGGL(k_kron3_lds<4>, grid, blk, 0, s, x, y, n, nchunk, bd);
+        hipLaunchKernelGGL(k_kron3_lds<4>, grid, blk, 0, s, xc, yc, n, nchunk, bd);
       else
-        hipLaunchKernelGGL(k_kron3_lds<8>, grid, blk, 0, s, x, y, n, nchunk, bd);
-      return;
+        hipLaunchKernelGGL(k_kron3_lds<8>, grid, blk, 0, s, xc, yc, n, nchunk, bd);
+      return true;
     }
     const dim3 grid(cdiv((int64_t)n * n, kBlock), cdiv(n, kChunk), (unsigned)nbatch);
     if (w <= 4)
-      hipLaunchKernelGGL(k_kron3_window<4>, grid, blk, 0, s, x, y, n, bd);
+      hipLaunchKernelGGL(k_kron3_window<4>, grid, blk, 0, s, xc, yc, n, bd);
     else if (w <= 8)
-      hipLaunchKernelGGL(k_kron3_window<8>, grid, blk, 0, s, x, y, n, bd);
+      hipLaunchKernelGGL(k_kron3_window<8>, grid, blk, 0, s, xc, yc, n, bd);
     else
-      hipLaunchKernelGGL(k_kron3_window<16>, grid, blk, 0, s, x, y, n, bd);
+      hipLaunchKernelGGL(k_kron3_window<16>, grid, blk, 0, s, xc, yc, n, bd);
   } else {
     const dim3 grid(cdiv(n, kBlock), cdiv(n, kChunk), (unsigned)nbatch);
     if (w <= 4)
@@ -478,6 +481,7 @@ void launch_kron_matvec_f64(hipStream_t s, const double *x, double *y, int d, in
     else
       hipLaunchKernelGGL(k_kron2_window<16>, grid, blk, 0, s, x, y, n, bd);
   }
+  return true;
 }
 
 void launch_ell_matvec_f64(hipStream_t s, const double *x, double *y, int64_t nrows, int64_t ld, int width,
