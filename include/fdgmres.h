@@ -40,7 +40,8 @@ typedef enum {
   FDG_EHIP = -3,          /* a HIP runtime call failed                                     */
   FDG_ECOMPLEX = -4,      /* pencil eigenvalues not real and positive (Remark 1 violated)  */
   FDG_ENOTREADY = -5,     /* factors or operator missing for the requested call            */
-  FDG_ENOCONV = -6        /* host eigen-iteration did not converge                         */
+  FDG_ENOCONV = -6,       /* host eigen-iteration did not converge                         */
+  FDG_EFULL = -7          /* server: no free slot or arena space for the request right now  */
 } fdg_status;
 
 typedef enum {
@@ -162,6 +163,52 @@ size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart);
  * launches and their summed duration in milliseconds, and resets the timer. */
 int fdg_timer_enable(fdg_ctx *ctx, int kernel, int enable);
 int fdg_timer_read(fdg_ctx *ctx, int kernel, int64_t *launches, double *total_ms);
+
+/* ---- Request server: continuous batching of many solves on one device ------------------
+ *
+ * A server owns a device arena (one allocation at creation), a pool of host-mapped
+ * pinned memory and `lanes` HIP streams (default priority, non-blocking).  A request is
+ * an fdg_solve on a ready context (factors and operator set, batch 1, any d and n):
+ * admission takes a free slot and run_bytes(ctx, restart) of the arena for its Krylov
+ * bases and scratch, or fails with FDG_EFULL and changes nothing.  fdg_server_step
+ * advances every lane whose previous work has completed: it reads each request's
+ * host-mapped scalars, performs its FP64 Givens update (the same host arithmetic as
+ * fdg_solve) and launches its next phase.  Requests on one lane that share a context
+ * and are at the same kind of phase (even at different Arnoldi indices) go into ONE
+ * launch per kernel through device pointer tables; requests of different shapes run
+ * concurrently on different lanes.  Every request gives bit-for-bit the fdg_solve
+ * result for the same (ctx, b, restart, rtol, maxit, flags): the per-entry arithmetic
+ * and reduction order of every kernel do not depend on the other entries.
+ * The caller keeps b, x and the context alive and unmodified until the request's
+ * completion is returned.  Not thread-safe: one thread drives a server. */
+typedef struct fdg_server fdg_server;
+
+typedef struct {
+  int64_t tag;       /* caller's tag given at admission                                   */
+  int status;        /* FDG_OK, FDG_NOT_CONVERGED or an error of that request             */
+  fdg_info info;     /* as from fdg_solve; ms_total runs from admission to completion     */
+} fdg_done;
+
+/* max_slots in [1, 4096] requests in flight, restart in [1, 255] for every request,
+ * lanes in [1, 16] streams, arena_bytes of device memory. */
+int fdg_server_create(fdg_server **srv, int max_slots, int restart, int lanes, size_t arena_bytes);
+int fdg_server_destroy(fdg_server *srv);
+/* Arena bytes one request on this context takes (0 for a NULL context). */
+size_t fdg_server_run_bytes(const fdg_ctx *ctx, int restart);
+/* Admit a request: b, x device N-vectors of ctx; rtol, maxit, flags as fdg_solve.  Its
+ * first phase is launched by the next fdg_server_step. */
+int fdg_server_admit(fdg_server *srv, fdg_ctx *ctx, const double *b, double *x, double rtol, int maxit,
+                     int flags, int64_t tag);
+/* Advance the lanes that are ready; wait up to wait_us microseconds (polling) for one to
+ * become ready if none is.  Writes up to cap completed requests to done (completions
+ * beyond cap are returned by later calls) and their count to *ndone. */
+int fdg_server_step(fdg_server *srv, int wait_us, fdg_done *done, int cap, int *ndone);
+/* Requests admitted and not yet returned as completed. */
+int fdg_server_pending(const fdg_server *srv);
+/* Counters since creation: lane services, phase groups launched, requests in those
+ * groups, and the largest group. */
+int fdg_server_stats(const fdg_server *srv, int64_t *services, int64_t *groups, int64_t *grouped_runs,
+                     int64_t *max_group);
 
 const char *fdg_status_str(int status);
 const char *fdg_last_error(void);

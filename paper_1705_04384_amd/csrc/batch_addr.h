@@ -28,6 +28,7 @@ inline CBatch cstrided(const double *p, int64_t stride) { return CBatch{p, strid
 inline MBatch mstrided(double *p, int64_t stride) { return MBatch{p, stride, nullptr}; }
 inline CBatch cgather(const double *const *ptrs) { return CBatch{nullptr, 0, ptrs}; }
 inline MBatch mgather(double *const *ptrs) { return MBatch{nullptr, 0, ptrs}; }
+inline CBatch as_const(const MBatch &m) { return CBatch{m.base, m.stride, (const double *const *)m.ptrs}; }
 
 // Per-entry integer (e.g. the number of basis vectors): table[e] when given, else uniform.
 struct IBatch {

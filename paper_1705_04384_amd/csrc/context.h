@@ -42,7 +42,6 @@ struct fdg_ctx {
   int32_t *bandlo[3] = {nullptr, nullptr, nullptr};
   int bandw[3] = {0, 0, 0};
   int bandrows4[3] = {0, 0, 0}, bandrows16[3] = {0, 0, 0}, bandstep[3] = {0, 0, 0};
-  double *mv_a = nullptr, *mv_c = nullptr;  // two-pass Kronecker matvec intermediates
   int32_t *ell_col = nullptr;
   double *ell_val = nullptr;
   int ell_width = 0;
@@ -51,10 +50,9 @@ struct fdg_ctx {
   void *t32a = nullptr, *t32b = nullptr;
   int restart_alloc = 0;
   double *Vb = nullptr, *Zb = nullptr, *P1 = nullptr, *P2 = nullptr, *P3 = nullptr, *Hcol = nullptr,
-         *ydev = nullptr, *hbuf = nullptr, *scal = nullptr;
+         *hbuf = nullptr, *scal = nullptr;
   double *hpin = nullptr;      // pinned, device-mapped host memory for the scalars the host needs
   double *hpin_dev = nullptr;  // its device address
-  unsigned *counters = nullptr;  // last-block counters of the reductions
   fdg::TimerState timers[fdg::kTimerClasses];
 };
 
@@ -84,14 +82,16 @@ inline void dfree(T *&p) {
   p = nullptr;
 }
 
-// Brackets one launch of timer class c with events when that timer is on.
+// Brackets one launch of timer class c on stream s with events when that timer is on
+// and the caller asks for timing.
 struct TimedLaunch {
   fdg_ctx *ctx;
   int c;
+  hipStream_t s;
   hipEvent_t stop = nullptr;
-  TimedLaunch(fdg_ctx *x, int cls) : ctx(x), c(cls) {
+  TimedLaunch(fdg_ctx *x, int cls, hipStream_t st, bool want) : ctx(x), c(cls), s(st) {
     TimerState &t = ctx->timers[c];
-    if (!t.on) return;
+    if (!want || !t.on) return;
     hipEvent_t a, b;
     if (t.pool.size() >= 2) {
       a = t.pool.back(); t.pool.pop_back();
@@ -100,25 +100,39 @@ struct TimedLaunch {
       if (hipEventCreate(&a) != hipSuccess) return;
       if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
     }
-    (void)hipEventRecord(a, ctx->stream);
+    (void)hipEventRecord(a, s);
     t.pending.push_back(a);
     stop = b;
   }
   ~TimedLaunch() {
     if (!stop) return;
-    (void)hipEventRecord(stop, ctx->stream);
+    (void)hipEventRecord(stop, s);
     ctx->timers[c].pending.push_back(stop);
   }
 };
 
+// Where a launch goes: the stream, and whether the context's kernel timers record it.
+struct Exec {
+  hipStream_t stream = nullptr;
+  bool timed = false;
+};
 
-// P^{-1} for nentries batch entries (entry e at in.at(e) / out.at(e)), FP64 fused passes
-// (n <= 256) with the caller's ping-pong workspace t1, t2 (nentries * N doubles each,
-// contiguous).  aligned32: every entry pointer is 32-byte aligned.
-int apply_prec_entries(fdg_ctx *c, CBatch in, MBatch out, int64_t nentries, bool aligned32, double *t1,
-                       double *t2);
-// y = A x for nentries batch entries (Kronecker operator: two-pass form with the caller's
-// intermediates tmp_a, tmp_c of nentries * N doubles each).
-int matvec_entries(fdg_ctx *c, CBatch x, MBatch y, int64_t nentries, double *tmp_a, double *tmp_c);
+// Largest number of entries one gathered launch takes.
+constexpr int kMaxGroupEntries = 64;
+
+// P^{-1} for nent batch entries (entry e at in.at(e) / out.at(e)), with per-entry scratch
+// t1, t2 (N doubles each) and, for a low-precision context, t32a, t32b (N floats each,
+// contiguous over the entries).  A gathered batch (pointer tables) needs a context that
+// groupable() accepts; strided batches take every path.  gathered_aligned32: every
+// gathered entry pointer is 32-byte aligned (ignored for strided batches).
+int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nent, MBatch t1, MBatch t2,
+                  void *t32a, void *t32b, bool gathered_aligned32);
+// y = A x for nent batch entries, scratch t1, t2 as for apply_entries.
+int matvec_entries(fdg_ctx *c, const Exec &ex, CBatch x, MBatch y, int64_t nent, MBatch t1, MBatch t2);
+// FDG_OK when the preconditioner factors and the operator are set, else FDG_ENOTREADY.
+int ctx_ready(fdg_ctx *c);
+// The context's apply and matvec accept gathered batches (FP64 fused FD passes and a
+// matvec form with per-entry scratch).
+bool groupable(const fdg_ctx *c);
 
 }  // namespace fdg

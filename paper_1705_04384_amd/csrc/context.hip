@@ -14,6 +14,7 @@
 #include "fd_apply.h"
 #include "kernels.h"
 #include "modeprod.h"
+#include "solve_run.h"
 
 using namespace fdg;
 
@@ -68,108 +69,18 @@ int check_ready_op(fdg_ctx *c) {
 
 inline bool al(const void *p, int bytes) { return (reinterpret_cast<uintptr_t>(p) % bytes) == 0; }
 
-int do_apply(fdg_ctx *c, const double *b, double *s) {
-  int st = ensure_workspace(c);
-  if (st != FDG_OK) return st;
-  if (c->prec != FDG_PREC_FP64) {
-    if ((st = ensure_lowp_workspace(c)) != FDG_OK) return st;
-    TimedLaunch tl(c, 0);
-    return fd_apply_lowp(c->stream, c->prec, c->d, c->n, c->batch, b, s, c->t32a, c->t32b,
-                         c->prec == FDG_PREC_FP32 ? (const void *const *)c->Wv32 : (const void *const *)c->Wv16,
-                         c->prec == FDG_PREC_FP32 ? (const void *const *)c->Wu32 : (const void *const *)c->Wu16,
-                         c->lam32, c->ldw);
-  }
-  if (fd_fused_supported(c->n))
-    return apply_prec_entries(c, cstrided(b, c->N), mstrided(s, c->N), c->batch, al(b, 32) && al(s, 32), c->t1,
-                              c->t2);
-  const int n = c->n;
-  const int64_t B = c->batch;
-  const int64_t n2 = (int64_t)n * n;
-  auto mode = [&](const double *X, double *Y, const double *W, int l) {
-    TimedLaunch tl(c, 0);
-    if (l == 0) {
-      const int64_t rows = B * (c->d == 3 ? n2 : n);
-      launch_modeprod_f64(c->stream, X, Y, W, c->ldw, n, rows, 0, 1, n, 1);
-    } else if (l == 1) {
-      const int64_t outer = B * (c->d == 3 ? n : 1);
-      launch_modeprod_f64(c->stream, X, Y, W, c->ldw, n, n, n2, n, 1, outer);
-    } else {
-      launch_modeprod_f64(c->stream, X, Y, W, c->ldw, n, n2, n2 * n, n2, 1, B);
-    }
-  };
-  if (c->d == 3) {
-    mode(b, c->t1, c->Wv[0], 0);
-    mode(c->t1, c->t2, c->Wv[1], 1);
-    mode(c->t2, c->t1, c->Wv[2], 2);
-    launch_divide_f64(c->stream, c->t1, 3, n, B, c->lam[0], c->lam[1], c->lam[2]);
-    mode(c->t1, c->t2, c->Wu[0], 0);
-    mode(c->t2, c->t1, c->Wu[1], 1);
-    mode(c->t1, s, c->Wu[2], 2);
-  } else {
-    mode(b, c->t1, c->Wv[0], 0);
-    mode(c->t1, c->t2, c->Wv[1], 1);
-    launch_divide_f64(c->stream, c->t2, 2, n, B, c->lam[0], c->lam[1], nullptr);
-    mode(c->t2, c->t1, c->Wu[0], 0);
-    mode(c->t1, s, c->Wu[1], 1);
-  }
-  return hip_check(hipGetLastError(), "apply_prec launch");
-}
-
-int do_matvec(fdg_ctx *c, const double *x, double *y) {
-  if (c->op_kind == 1) {
-    int st = FDG_OK;
-    if (c->d == 3) {
-      st = dalloc(&c->mv_a, (size_t)c->N * c->batch);
-      if (st == FDG_OK) st = dalloc(&c->mv_c, (size_t)c->N * c->batch);
-      if (st != FDG_OK) return st;
-    }
-    return matvec_entries(c, cstrided(x, c->N), mstrided(y, c->N), c->batch, c->mv_a, c->mv_c);
-  }
-  TimedLaunch tl(c, 1);
-  launch_ell_matvec_f64(c->stream, x, y, c->N, c->N, c->ell_width, c->ell_col, c->ell_val, c->batch);
-  return hip_check(hipGetLastError(), "matvec launch");
-}
-
 }  // namespace
 
 namespace fdg {
 
-int apply_prec_entries(fdg_ctx *c, CBatch in, MBatch out, int64_t nentries, bool aligned32, double *t1, double *t2) {
-  const int n = c->n;
-  const int64_t N = c->N;
-  if (c->d == 3) {
-    {
-      TimedLaunch tl(c, 0);
-      launch_slab_f64(c->stream, in, mstrided(t1, N), c->Wv[0], c->Wv[1], c->ldw, n, nentries, n, false, nullptr,
-                      nullptr, aligned32);
-    }
-    {
-      TimedLaunch tl(c, 3);
-      launch_fibre_f64(c->stream, cstrided(t1, N), mstrided(t2, N), c->Wv[2], c->Wu[2], c->ldw, n, nentries,
-                       c->lam[0], c->lam[1], c->lam[2]);
-    }
-    {
-      TimedLaunch tl(c, 0);
-      launch_slab_f64(c->stream, cstrided(t2, N), out, c->Wu[0], c->Wu[1], c->ldw, n, nentries, n, false, nullptr,
-                      nullptr, aligned32);
-    }
-  } else {
-    {
-      TimedLaunch tl(c, 0);
-      launch_slab_f64(c->stream, in, mstrided(t1, N), c->Wv[0], c->Wv[1], c->ldw, n, nentries, 1, true, c->lam[0],
-                      c->lam[1], aligned32);
-    }
-    {
-      TimedLaunch tl(c, 0);
-      launch_slab_f64(c->stream, cstrided(t1, N), out, c->Wu[0], c->Wu[1], c->ldw, n, nentries, 1, false, nullptr,
-                      nullptr, aligned32);
-    }
-  }
-  return hip_check(hipGetLastError(), "apply_prec launch");
+int ctx_ready(fdg_ctx *c) {
+  int st = check_ready_prec(c);
+  if (st == FDG_OK) st = check_ready_op(c);
+  return st;
 }
 
-int matvec_entries(fdg_ctx *c, CBatch x, MBatch y, int64_t nentries, double *tmp_a, double *tmp_c) {
-  TimedLaunch tl(c, 1);
+namespace {
+KronBands ctx_bands(const fdg_ctx *c) {
   KronBands bd;
   for (int l = 0; l < 3; ++l) {
     const int q = l < c->d ? l : 0;
@@ -181,7 +92,112 @@ int matvec_entries(fdg_ctx *c, CBatch x, MBatch y, int64_t nentries, double *tmp
   bd.rows4 = c->bandrows4[c->d == 3 ? 1 : 0];
   bd.rows16 = c->bandrows16[c->d == 3 ? 1 : 0];
   bd.step3 = c->bandstep[c->d == 3 ? 2 : 0];
-  if (!launch_kron_matvec_f64(c->stream, x, y, c->d, c->n, nentries, bd, tmp_a, tmp_c))
+  return bd;
+}
+}  // namespace
+
+bool groupable(const fdg_ctx *c) {
+  if (c->prec != FDG_PREC_FP64 || !fd_fused_supported(c->n)) return false;
+  if (c->op_kind == 2 || c->d == 2) return true;
+  int w = 0;
+  for (int l = 0; l < c->d; ++l) w = std::max(w, c->bandw[l]);
+  KronBands bd = ctx_bands(c);
+  return kron_two_pass_ok(c->d, c->n, kMaxGroupEntries, bd);
+}
+
+int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nent, MBatch t1, MBatch t2,
+                  void *t32a, void *t32b, bool gathered_aligned32) {
+  const int n = c->n;
+  const int64_t N = c->N;
+  const bool gathered = in.ptrs || out.ptrs || t1.ptrs || t2.ptrs;
+  if (c->prec != FDG_PREC_FP64) {
+    if (gathered) return set_error(FDG_EINVAL, "apply: gathered batches need the FP64 preconditioner");
+    TimedLaunch tl(c, 0, ex.stream, ex.timed);
+    return fd_apply_lowp(ex.stream, c->prec, c->d, n, nent, in.base, out.base, t32a, t32b,
+                         c->prec == FDG_PREC_FP32 ? (const void *const *)c->Wv32 : (const void *const *)c->Wv16,
+                         c->prec == FDG_PREC_FP32 ? (const void *const *)c->Wu32 : (const void *const *)c->Wu16,
+                         c->lam32, c->ldw);
+  }
+  if (fd_fused_supported(n)) {
+    // 32-byte aligned entries allow 4-wide loads (load width only; the arithmetic is the same)
+    const bool a32 = in.ptrs || out.ptrs
+                         ? gathered_aligned32
+                         : al(in.base, 32) && al(out.base, 32) &&
+                               (nent == 1 || (in.stride % 4 == 0 && out.stride % 4 == 0));
+    if (c->d == 3) {
+      {
+        TimedLaunch tl(c, 0, ex.stream, ex.timed);
+        launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, n, false, nullptr, nullptr, a32);
+      }
+      {
+        TimedLaunch tl(c, 3, ex.stream, ex.timed);
+        launch_fibre_f64(ex.stream, as_const(t1), t2, c->Wv[2], c->Wu[2], c->ldw, n, nent, c->lam[0], c->lam[1],
+                         c->lam[2]);
+      }
+      {
+        TimedLaunch tl(c, 0, ex.stream, ex.timed);
+        launch_slab_f64(ex.stream, as_const(t2), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, n, false, nullptr,
+                        nullptr, a32);
+      }
+    } else {
+      {
+        TimedLaunch tl(c, 0, ex.stream, ex.timed);
+        launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, 1, true, c->lam[0], c->lam[1], a32);
+      }
+      {
+        TimedLaunch tl(c, 0, ex.stream, ex.timed);
+        launch_slab_f64(ex.stream, as_const(t1), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, 1, false, nullptr, nullptr,
+                        a32);
+      }
+    }
+    return hip_check(hipGetLastError(), "apply_prec launch");
+  }
+  if (gathered) return set_error(FDG_EINVAL, "apply: gathered batches need n <= 256");
+  // unfused mode products over a contiguous batch (n > 256)
+  const int64_t B = nent;
+  const int64_t n2 = (int64_t)n * n;
+  double *T1 = t1.base, *T2 = t2.base;
+  const double *b = in.base;
+  double *s = out.base;
+  (void)N;
+  auto mode = [&](const double *X, double *Y, const double *W, int l) {
+    TimedLaunch tl(c, 0, ex.stream, ex.timed);
+    if (l == 0) {
+      const int64_t rows = B * (c->d == 3 ? n2 : n);
+      launch_modeprod_f64(ex.stream, X, Y, W, c->ldw, n, rows, 0, 1, n, 1);
+    } else if (l == 1) {
+      const int64_t outer = B * (c->d == 3 ? n : 1);
+      launch_modeprod_f64(ex.stream, X, Y, W, c->ldw, n, n, n2, n, 1, outer);
+    } else {
+      launch_modeprod_f64(ex.stream, X, Y, W, c->ldw, n, n2, n2 * n, n2, 1, B);
+    }
+  };
+  if (c->d == 3) {
+    mode(b, T1, c->Wv[0], 0);
+    mode(T1, T2, c->Wv[1], 1);
+    mode(T2, T1, c->Wv[2], 2);
+    launch_divide_f64(ex.stream, T1, 3, n, B, c->lam[0], c->lam[1], c->lam[2]);
+    mode(T1, T2, c->Wu[0], 0);
+    mode(T2, T1, c->Wu[1], 1);
+    mode(T1, s, c->Wu[2], 2);
+  } else {
+    mode(b, T1, c->Wv[0], 0);
+    mode(T1, T2, c->Wv[1], 1);
+    launch_divide_f64(ex.stream, T2, 2, n, B, c->lam[0], c->lam[1], nullptr);
+    mode(T2, T1, c->Wu[0], 0);
+    mode(T1, s, c->Wu[1], 1);
+  }
+  return hip_check(hipGetLastError(), "apply_prec launch");
+}
+
+int matvec_entries(fdg_ctx *c, const Exec &ex, CBatch x, MBatch y, int64_t nent, MBatch t1, MBatch t2) {
+  TimedLaunch tl(c, 1, ex.stream, ex.timed);
+  if (c->op_kind == 2) {
+    launch_ell_matvec_f64(ex.stream, x, y, c->N, c->N, c->ell_width, c->ell_col, c->ell_val, nent);
+    return hip_check(hipGetLastError(), "matvec launch");
+  }
+  const KronBands bd = ctx_bands(c);
+  if (!launch_kron_matvec_f64(ex.stream, x, y, c->d, c->n, nent, bd, t1, t2))
     return set_error(FDG_EINVAL, "matvec: this operator shape needs a contiguous batch");
   return hip_check(hipGetLastError(), "matvec launch");
 }
@@ -190,12 +206,31 @@ int matvec_entries(fdg_ctx *c, CBatch x, MBatch y, int64_t nentries, double *tmp
 
 namespace {
 
+// The context's own stream and workspace, for the apply / matvec entry points.
+int ctx_apply(fdg_ctx *c, const double *b, double *s) {
+  int st = ensure_workspace(c);
+  if (st != FDG_OK) return st;
+  if (c->prec != FDG_PREC_FP64 && (st = ensure_lowp_workspace(c)) != FDG_OK) return st;
+  return apply_entries(c, Exec{c->stream, true}, cstrided(b, c->N), mstrided(s, c->N), c->batch,
+                       mstrided(c->t1, c->N), mstrided(c->t2, c->N), c->t32a, c->t32b, false);
+}
+
+int ctx_matvec(fdg_ctx *c, const double *x, double *y) {
+  int st = ensure_workspace(c);
+  if (st != FDG_OK) return st;
+  return matvec_entries(c, Exec{c->stream, true}, cstrided(x, c->N), mstrided(y, c->N), c->batch,
+                        mstrided(c->t1, c->N), mstrided(c->t2, c->N));
+}
+
+}  // namespace
+
+namespace {
+
 int ensure_krylov(fdg_ctx *c, int m) {
   if (c->restart_alloc >= m) return FDG_OK;
-  dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol); dfree(c->ydev);
+  dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol);
   dfree(c->hbuf); dfree(c->scal);
   if (c->hpin) { (void)hipHostFree(c->hpin); c->hpin = nullptr; }
-  dfree(c->counters);
   c->restart_alloc = 0;
   const size_t NB = (size_t)c->N * c->batch;
   const int G = reduction_blocks(c->N);
@@ -206,7 +241,6 @@ int ensure_krylov(fdg_ctx *c, int m) {
   if ((st = dalloc(&c->P2, (size_t)G * (m + 1) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->P3, (size_t)G * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->Hcol, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
-  if ((st = dalloc(&c->ydev, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->hbuf, (size_t)2 * (m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->scal, (size_t)4 * c->batch)) != FDG_OK) return st;
   HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * (size_t)(2 * m + 8) * c->batch, hipHostMallocMapped));
@@ -258,14 +292,12 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
     dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandlo[l]);
   }
   dfree(c->ell_col); dfree(c->ell_val);
-  dfree(c->mv_a); dfree(c->mv_c);
   dfree(c->t1); dfree(c->t2);
   if (c->t32a) (void)hipFree(c->t32a);
   if (c->t32b) (void)hipFree(c->t32b);
-  dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol); dfree(c->ydev);
+  dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol);
   dfree(c->hbuf); dfree(c->scal);
   if (c->hpin) (void)hipHostFree(c->hpin);
-  dfree(c->counters);
   for (auto &t : c->timers) {
     for (auto e : t.pool) (void)hipEventDestroy(e);
     for (auto e : t.pending) (void)hipEventDestroy(e);
@@ -447,7 +479,7 @@ extern "C" int fdg_apply_prec(fdg_ctx *c, const double *b, double *s) {
   if (b == s) return set_error(FDG_EINVAL, "apply_prec: input and output alias");
   int st = check_ready_prec(c);
   if (st != FDG_OK) return st;
-  return do_apply(c, b, s);
+  return ctx_apply(c, b, s);
 }
 
 extern "C" int fdg_matvec(fdg_ctx *c, const double *x, double *y) {
@@ -456,13 +488,12 @@ extern "C" int fdg_matvec(fdg_ctx *c, const double *x, double *y) {
   if (x == y) return set_error(FDG_EINVAL, "matvec: input and output alias");
   int st = check_ready_op(c);
   if (st != FDG_OK) return st;
-  return do_matvec(c, x, y);
+  return ctx_matvec(c, x, y);
 }
 
 extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, int restart, int maxit, int flags,
                          fdg_info *info) {
   clear_error();
-  const auto t0 = std::chrono::steady_clock::now();
   if (!c || !b || !x) return set_error(FDG_EINVAL, "solve: NULL argument");
   if (b == x) return set_error(FDG_EINVAL, "solve: b and x alias");
   if (c->batch != 1) return set_error(FDG_EINVAL, "solve: context batch must be 1");
@@ -472,192 +503,34 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   if ((st = check_ready_prec(c)) != FDG_OK) return st;
   if ((st = check_ready_op(c)) != FDG_OK) return st;
   if ((st = ensure_workspace(c)) != FDG_OK) return st;
-  const int m = restart;
-  if ((st = ensure_krylov(c, m)) != FDG_OK) return st;
-  const int64_t N = c->N;
-  const int G = reduction_blocks(N);
-  const bool fixed = (flags & FDG_SOLVE_FIXED_ITERS) != 0;
-  const int limit = maxit;
-  double *V = c->Vb, *Z = c->Zb;
-  auto Vq = [&](int q) { return V + (size_t)q * N; };
-  auto Zq = [&](int q) { return Z + (size_t)q * N; };
-  double *bn_dev = c->scal, *beta_dev = c->scal + 1;
-  double *h1 = c->hbuf;
-  // host-mapped scalars: [0, m+2) Hessenberg column, m+2 ||b||, m+3 residual norm
-  volatile double *hcol_h = c->hpin, *bn_h = c->hpin + m + 2, *beta_h = c->hpin + m + 3;
-  double *hcol_d = c->hpin_dev, *bn_hd = c->hpin_dev + m + 2, *beta_hd = c->hpin_dev + m + 3;
-
-  {  // partials of ||b||^2; reduced by the first scaling of b or read directly below
-    TimedLaunch tl(c, 2);
-    launch_dots(c->stream, cstrided(b, 0), 0, IBatch{1, nullptr}, cstrided(b, 0), N, 1, G, 1, c->P3, al(b, 16));
-  }
-  fdg_info inf;
-  std::memset(&inf, 0, sizeof(inf));
-  double bnorm = -1.0, target = 0.0;
-  auto learn_bnorm = [&]() {  // ||b|| has arrived in host-mapped memory (after a sync)
-    bnorm = *bn_h;
-    target = rtol * bnorm;
-  };
-  auto finish = [&](bool converged) {
-    inf.converged = converged ? 1 : 0;
-    inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (info) *info = inf;
-    return converged ? FDG_OK : FDG_NOT_CONVERGED;
-  };
-  auto zero_x = [&]() -> int {
-    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, c->stream));
+  if (c->prec != FDG_PREC_FP64 && (st = ensure_lowp_workspace(c)) != FDG_OK) return st;
+  if ((st = ensure_krylov(c, restart)) != FDG_OK) return st;
+  RunBufs rb;
+  rb.V = c->Vb;
+  rb.Z = c->Zb;
+  rb.t1 = c->t1;
+  rb.t2 = c->t2;
+  rb.t32a = c->t32a;
+  rb.t32b = c->t32b;
+  rb.P1 = c->P1;
+  rb.P2 = c->P2;
+  rb.P3 = c->P3;
+  rb.Hcol = c->Hcol;
+  rb.h1 = c->hbuf;
+  rb.scal = c->scal;
+  rb.hh = c->hpin;
+  rb.hh_dev = c->hpin_dev;
+  SolveRun run;
+  run.init(c, rb, restart, b, x, rtol, maxit, flags);
+  SolveRun *rp = &run;
+  const Exec ex{c->stream, true};
+  while (!run.finished()) {
+    if ((st = enqueue_phase(ex, &rp, 1, nullptr)) != FDG_OK) return st;
     HIPCHK(hipStreamSynchronize(c->stream));
-    return FDG_OK;
-  };
-  bool x_nonzero = (flags & FDG_SOLVE_USE_X0) != 0;
-  if (x_nonzero || limit == 0) {
-    TimedLaunch tl(c, 2);
-    launch_norm_reduce(c->stream, c->P3, G, 1, mstrided(bn_dev, 0), mstrided(bn_hd, 0));
+    run.consume();
   }
-  if (!x_nonzero && limit == 0) {  // nothing to iterate: x = 0
-    HIPCHK(hipStreamSynchronize(c->stream));
-    learn_bnorm();
-    if ((st = zero_x()) != FDG_OK) return st;
-    inf.rel_res_true = bnorm > 0.0 ? 1.0 : 0.0;
-    return finish(bnorm == 0.0);
-  }
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
-  Coeffs y;
-  auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
-  int total = 0, restarts = 0;
-  double last_est = 1.0, rbeta = 0.0;
-  bool breakdown = false;
-  while (true) {
-    double beta = 0.0;
-    if (x_nonzero) {  // r = b - A x, v0 = r / ||r||; ||r|| read on the host
-      if ((st = do_matvec(c, x, c->t1)) != FDG_OK) return st;
-      {
-        TimedLaunch tl(c, 2);
-        launch_residual(c->stream, cstrided(b, 0), cstrided(c->t1, 0), mstrided(Vq(0), 0), N, 1, G, c->P3);
-      }
-      {
-        TimedLaunch tl(c, 2);
-        launch_scale_reduce(c->stream, cstrided(Vq(0), 0), mstrided(Vq(0), 0), c->P3, G, N, 1, mstrided(beta_dev, 0),
-                            mstrided(beta_hd, 0), true);
-      }
-      HIPCHK(hipStreamSynchronize(c->stream));
-      if (bnorm < 0.0) learn_bnorm();
-      beta = *beta_h;
-      if (bnorm == 0.0) {  // b = 0: the solution is x = 0 exactly
-        if ((st = zero_x()) != FDG_OK) return st;
-        inf.rel_res_true = 0.0;
-        return finish(true);
-      }
-      rbeta = beta;
-      inf.rel_res_true = beta / bnorm;
-      if ((!fixed && beta <= target) || total >= limit) break;
-    } else {  // x = 0: r = b, v0 = b / ||b|| (||b|| reaches the host with the first column)
-      TimedLaunch tl(c, 2);
-      launch_scale_reduce(c->stream, cstrided(b, 0), mstrided(Vq(0), 0), c->P3, G, N, 1, mstrided(bn_dev, 0),
-                          mstrided(bn_hd, 0), al(b, 16));
-    }
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;  // completed below when ||b|| arrives with the first column
-    int k = 0;
-    breakdown = false;
-    for (int j = 0; j < m; ++j) {
-      if ((st = do_apply(c, Vq(j), Zq(j))) != FDG_OK) return st;
-      if ((st = do_matvec(c, Zq(j), Vq(j + 1))) != FDG_OK) return st;
-      double *w = Vq(j + 1);
-      const int nv = j + 1;
-      {  // classical Gram-Schmidt: h1 = V^T w
-        TimedLaunch tl(c, 2);
-        launch_dots(c->stream, cstrided(V, 0), N, IBatch{nv, nullptr}, cstrided(w, 0), N, 1, G, m + 1, c->P1, true);
-      }
-      {  // w -= V h1; h2 = V^T w (reorthogonalisation)
-        TimedLaunch tl(c, 2);
-        launch_update_dots(c->stream, cstrided(V, 0), N, IBatch{nv, nullptr}, c->P1, G, m + 1, mstrided(w, 0), N, 1,
-                           c->P2, mstrided(h1, 0), true);
-      }
-      {  // w -= V h2; Hessenberg column h1 + h2 to the host; ||w||
-        TimedLaunch tl(c, 2);
-        launch_update_norm(c->stream, cstrided(V, 0), N, IBatch{nv, nullptr}, c->P2, G, m + 1, mstrided(w, 0), N, 1,
-                           c->P3, cstrided(h1, 0), mstrided(c->Hcol, 0), mstrided(hcol_d, 0), true);
-      }
-      {  // h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}
-        TimedLaunch tl(c, 2);
-        launch_scale_reduce(c->stream, cstrided(w, 0), mstrided(w, 0), c->P3, G, N, 1, mstrided(c->Hcol + nv, 0),
-                            mstrided(hcol_d + nv, 0), true);
-      }
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(c->stream));
-      if (bnorm < 0.0) {
-        learn_bnorm();
-        g[0] = bnorm;
-        if (bnorm == 0.0) {  // b = 0: x = 0 exactly
-          if ((st = zero_x()) != FDG_OK) return st;
-          inf.rel_res_true = 0.0;
-          return finish(true);
-        }
-      }
-      for (int q = 0; q <= nv; ++q) Hij(q, j) = hcol_h[q];
-      double wn0 = 0.0;
-      for (int q = 0; q <= nv; ++q) wn0 += Hij(q, j) * Hij(q, j);
-      wn0 = std::sqrt(wn0);
-      const double hn = Hij(j + 1, j);
-      for (int i = 0; i < j; ++i) {
-        const double a = Hij(i, j), bb = Hij(i + 1, j);
-        Hij(i, j) = cs[i] * a + sn[i] * bb;
-        Hij(i + 1, j) = -sn[i] * a + cs[i] * bb;
-      }
-      {
-        const double a = Hij(j, j), bb = Hij(j + 1, j);
-        if (bb == 0.0) {
-          cs[j] = 1.0; sn[j] = 0.0;
-        } else {
-          const double r = std::hypot(a, bb);
-          cs[j] = a / r; sn[j] = bb / r;
-          Hij(j, j) = r;
-        }
-        Hij(j + 1, j) = 0.0;
-      }
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++total;
-      k = j + 1;
-      last_est = std::fabs(g[j + 1]) / bnorm;
-      breakdown = hn <= 1e-14 * wn0;
-      if (total >= limit || breakdown) break;
-      if (!fixed && std::fabs(g[j + 1]) <= target) break;
-    }
-    for (int i = k - 1; i >= 0; --i) {
-      double sacc = g[i];
-      for (int q = i + 1; q < k; ++q) sacc -= Hij(i, q) * y.v[q];
-      y.v[i] = sacc / Hij(i, i);
-    }
-    {
-      TimedLaunch tl(c, 2);
-      launch_lincomb(c->stream, mstrided(x, 0), cstrided(Z, 0), N, IBatch{k, nullptr}, y, nullptr, N, 1,
-                     IBatch{x_nonzero ? 0 : 1, nullptr});
-    }
-    x_nonzero = true;
-    ++restarts;
-    if (total >= limit) {  // final true residual
-      if ((st = do_matvec(c, x, c->t1)) != FDG_OK) return st;
-      {
-        TimedLaunch tl(c, 2);
-        launch_residual(c->stream, cstrided(b, 0), cstrided(c->t1, 0), mstrided(Vq(0), 0), N, 1, G, c->P3);
-      }
-      {
-        TimedLaunch tl(c, 2);
-        launch_norm_reduce(c->stream, c->P3, G, 1, mstrided(beta_dev, 0), mstrided(beta_hd, 0));
-      }
-      HIPCHK(hipStreamSynchronize(c->stream));
-      rbeta = *beta_h;
-      inf.rel_res_true = rbeta / bnorm;
-      break;
-    }
-  }
-  inf.iterations = total;
-  inf.restarts = restarts;
-  inf.breakdown = breakdown ? 1 : 0;
-  inf.rel_res_est = last_est;
-  return finish(rbeta <= target);
+  if (info) *info = run.info();
+  return run.status();
 }
 
 extern "C" size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart) {

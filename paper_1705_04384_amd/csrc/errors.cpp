@@ -32,6 +32,7 @@ extern "C" const char *fdg_status_str(int status) {
     case FDG_ECOMPLEX: return "FDG_ECOMPLEX";
     case FDG_ENOTREADY: return "FDG_ENOTREADY";
     case FDG_ENOCONV: return "FDG_ENOCONV";
+    case FDG_EFULL: return "FDG_EFULL";
     default: return "FDG_UNKNOWN";
   }
 }

@@ -38,15 +38,18 @@ struct KronBands {
   int step3;   // max over i of lo3[i+1] - lo3[i]
 };
 // Requires non-decreasing band starts lo[] and w <= kron_window_max().  tmp_a, tmp_c:
-// scratch of nbatch * n^3 doubles each for the two-pass 3D form (may be NULL: one pass).
+// per-entry scratch of n^3 doubles each for the two-pass 3D form (invalid: one pass).
 // Returns false (nothing launched) for a gathered batch the two-pass form cannot take.
 bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int64_t nbatch,
-                            const KronBands &bands, double *tmp_a, double *tmp_c);
+                            const KronBands &bands, MBatch tmp_a, MBatch tmp_c);
 int kron_window_max();
+// The 3D matvec of nbatch entries can take the two-pass form (which accepts gathered
+// batches); always true in 2D.
+bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bands);
 
 // Slot-major ELL: entry (row, slot) at col[slot*ld + row], val[slot*ld + row].
-void launch_ell_matvec_f64(hipStream_t s, const double *x, double *y, int64_t nrows, int64_t ld,
-                           int width, const int32_t *col, const double *val, int64_t nbatch);
+void launch_ell_matvec_f64(hipStream_t s, CBatch x, MBatch y, int64_t nrows, int64_t ld, int width,
+                           const int32_t *col, const double *val, int64_t nbatch);
 
 // ---- Krylov vector kernels --------------------------------------------------------------
 // Vectors of a basis are stored q-major: element (q, b, i) at V[q*ldv + b*N + i].
@@ -60,30 +63,32 @@ struct Coeffs {
 };
 
 // Batch entry e of a Krylov kernel: basis (q = 0) at V.at(e), vector q at + q*ldv;
-// nv.at(e) basis vectors; partial g of component q at P[(e*G + g)*ldp + q].
-// aligned16_all: every pointer involved is 16-byte aligned (enables 2-wide accesses).
+// nv.at(e) basis vectors; partial g of component q at P.at(e)[g*ldp + q] (one partial per
+// block for norms: P.at(e)[g]).  aligned16_all: every pointer involved is 16-byte aligned
+// (enables 2-wide accesses, which changes the summation order).
 
 // P = partial sums of V_q . w, q < nv.
 void launch_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch w, int64_t N, int64_t nbatch,
-                 int G, int ldp, double *P, bool aligned16_all);
+                 int G, int ldp, MBatch P, bool aligned16_all);
 // h1 = sum(Pin) (block 0 stores it to hout.at(e)); w -= V h1; Pout = partials of V^T w.
-void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const double *Pin, int G, int ldp,
-                        MBatch w, int64_t N, int64_t nbatch, double *Pout, MBatch hout, bool aligned16_all);
-// h2 = sum(Pin); Hcol = h1 + h2 (and host copy); w -= V h2; Pnorm[e*G + g] = partials of |w|^2.
-void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const double *Pin, int G, int ldp,
-                        MBatch w, int64_t N, int64_t nbatch, double *Pnorm, CBatch h1, MBatch Hcol,
+void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch Pin, int G, int ldp,
+                        MBatch w, int64_t N, int64_t nbatch, MBatch Pout, MBatch hout, bool aligned16_all);
+// h2 = sum(Pin); Hcol = h1 + h2 (and host copy); w -= V h2; Pnorm = partials of |w|^2.
+void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch Pin, int G, int ldp,
+                        MBatch w, int64_t N, int64_t nbatch, MBatch Pnorm, CBatch h1, MBatch Hcol,
                         MBatch host, bool aligned16_all);
-// d = sqrt(sum(Pn[e*G ..])); v = w / d (0 if d = 0; v may equal w); d to out.at(e)[0], host.at(e)[0].
-void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, const double *Pn, int G, int64_t N,
-                         int64_t nbatch, MBatch out, MBatch host, bool aligned16_all);
-// d = sqrt(sum(Pn[e*G ..])) to out and host.
-void launch_norm_reduce(hipStream_t s, const double *Pn, int G, int64_t nbatch, MBatch out, MBatch host);
+// d = sqrt(sum of Pn.at(e)[g], g < G); v = w / d (0 if d = 0; v may equal w); d to
+// out.at(e)[0] and host.at(e)[0] (either may be invalid).
+void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, CBatch Pn, int G, int64_t N, int64_t nbatch,
+                         MBatch out, MBatch host, bool aligned16_all);
+// d = sqrt(sum of Pn.at(e)[g]) to out and host.
+void launch_norm_reduce(hipStream_t s, CBatch Pn, int G, int64_t nbatch, MBatch out, MBatch host);
 // x = (overwrite ? 0 : x) + sum_q Z_q y_q, q < k.at(e) <= 256; coefficients from ytab[e*256 + q]
 // when ytab is given, else y (shared by every entry).
 void launch_lincomb(hipStream_t s, MBatch x, CBatch Z, int64_t ldz, IBatch k, const Coeffs &y,
                     const double *ytab, int64_t N, int64_t nbatch, IBatch overwrite);
-// r = b - Ax and the partials P[e*G + g] of |r|^2.
+// r = b - Ax and the partials P.at(e)[g] of |r|^2.
 void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G,
-                     double *P);
+                     MBatch P);
 
 }  // namespace fdg

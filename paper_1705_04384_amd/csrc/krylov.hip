@@ -161,7 +161,7 @@ __device__ inline double block_sum(double v, double *red) {
 
 template <bool VEC>
 __global__ __launch_bounds__(kRed) void k_dots(CBatch V, int64_t ldv, IBatch nvs, CBatch w, int64_t N, int G,
-                                               int ldp, double *__restrict__ P) {
+                                               int ldp, MBatch P) {
   __shared__ double red[kRedWaves][kQB];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kRed) void k_dots(CBatch V, int64_t ldv, IBatch nvs
   chunk_of(N, G, g, beg, end);
   const double *__restrict__ wb = w.at(b);
   const double *__restrict__ Vb = V.at(b);
-  double *Pg = P + ((int64_t)b * G + g) * ldp;
+  double *Pg = P.at(b) + (int64_t)g * ldp;
   for (int q0 = 0; q0 < nv; q0 += kQB) {
     double acc[kQB];
     chunk_dots<VEC>(Vb, ldv, nv, q0, wb, beg, end, acc);
@@ -180,15 +180,14 @@ __global__ __launch_bounds__(kRed) void k_dots(CBatch V, int64_t ldv, IBatch nvs
 
 // h1 = reduce(Pin); w -= V h1; Pout = partial dots V^T w.  Block 0 stores h1 to hout.
 template <bool VEC>
-__global__ __launch_bounds__(kRed) void k_update_dots(CBatch V, int64_t ldv, IBatch nvs,
-                                                      const double *__restrict__ Pin, int G, int ldp, MBatch w,
-                                                      int64_t N, double *__restrict__ Pout, MBatch hout) {
+__global__ __launch_bounds__(kRed) void k_update_dots(CBatch V, int64_t ldv, IBatch nvs, CBatch Pin, int G,
+                                                      int ldp, MBatch w, int64_t N, MBatch Pout, MBatch hout) {
   __shared__ double hs[256];
   __shared__ double red[kRedWaves][kQB];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
   const int nv = nvs.at(b);
-  reduce_into(Pin + (int64_t)b * G * ldp, G, ldp, nv, hs, kRedWaves);
+  reduce_into(Pin.at(b), G, ldp, nv, hs, kRedWaves);
   if (g == 0) {
     double *ho = hout.at(b);
     for (int q = threadIdx.x; q < nv; q += kRed) ho[q] = hs[q];
@@ -199,7 +198,7 @@ __global__ __launch_bounds__(kRed) void k_update_dots(CBatch V, int64_t ldv, IBa
   const double *__restrict__ Vb = V.at(b);
   (void)chunk_update<VEC>(Vb, ldv, nv, hs, wb, beg, end);
   __syncthreads();  // the block's own chunk of w is complete before it is re-read
-  double *Pg = Pout + ((int64_t)b * G + g) * ldp;
+  double *Pg = Pout.at(b) + (int64_t)g * ldp;
   for (int q0 = 0; q0 < nv; q0 += kQB) {
     double acc[kQB];
     chunk_dots<VEC>(Vb, ldv, nv, q0, wb, beg, end, acc);
@@ -210,16 +209,15 @@ __global__ __launch_bounds__(kRed) void k_update_dots(CBatch V, int64_t ldv, IBa
 // h2 = reduce(Pin); w -= V h2; Pnorm = partial |w|^2.  Block 0 stores the Hessenberg
 // column Hcol[q] = h1[q] + h2[q] (device and, when given, host-mapped memory).
 template <bool VEC>
-__global__ __launch_bounds__(kRed) void k_update_norm(CBatch V, int64_t ldv, IBatch nvs,
-                                                      const double *__restrict__ Pin, int G, int ldp, MBatch w,
-                                                      int64_t N, double *__restrict__ Pnorm, CBatch h1, MBatch Hcol,
-                                                      MBatch host) {
+__global__ __launch_bounds__(kRed) void k_update_norm(CBatch V, int64_t ldv, IBatch nvs, CBatch Pin, int G,
+                                                      int ldp, MBatch w, int64_t N, MBatch Pnorm, CBatch h1,
+                                                      MBatch Hcol, MBatch host) {
   __shared__ double hs[256];
   __shared__ double red[kRedWaves];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
   const int nv = nvs.at(b);
-  reduce_into(Pin + (int64_t)b * G * ldp, G, ldp, nv, hs, kRedWaves);
+  reduce_into(Pin.at(b), G, ldp, nv, hs, kRedWaves);
   if (g == 0) {
     const double *h1b = h1.at(b);
     double *hc = Hcol.at(b);
@@ -234,16 +232,16 @@ __global__ __launch_bounds__(kRed) void k_update_norm(CBatch V, int64_t ldv, IBa
   chunk_of(N, G, g, beg, end);
   const double nrm = chunk_update<VEC>(V.at(b), ldv, nv, hs, w.at(b), beg, end);
   const double s = block_sum(nrm, red);
-  if (threadIdx.x == 0) Pnorm[(int64_t)b * G + g] = s;
+  if (threadIdx.x == 0) Pnorm.at(b)[g] = s;
 }
 
 // d = sqrt(reduce(Pn)); v = w / d (0 if d = 0).  Block 0 stores d to out and host.
 template <bool VEC>
-__global__ __launch_bounds__(kBlock) void k_scale_reduce(CBatch w, MBatch v, const double *__restrict__ Pn, int G,
-                                                         int64_t N, MBatch out, MBatch host) {
+__global__ __launch_bounds__(kBlock) void k_scale_reduce(CBatch w, MBatch v, CBatch Pn, int G, int64_t N, MBatch out,
+                                                         MBatch host) {
   __shared__ double hs[1];
   const int64_t b = blockIdx.y;
-  reduce_into(Pn + (int64_t)b * G, G, 1, 1, hs, kBlock / 64);
+  reduce_into(Pn.at(b), G, 1, 1, hs, kBlock / 64);
   const double d = sqrt(hs[0]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (out.valid()) out.at(b)[0] = d;
@@ -263,11 +261,10 @@ __global__ __launch_bounds__(kBlock) void k_scale_reduce(CBatch w, MBatch v, con
 }
 
 // d = sqrt(reduce(Pn)) stored to out and host (one block per batch entry).
-__global__ __launch_bounds__(kBlock) void k_norm_reduce(const double *__restrict__ Pn, int G, MBatch out,
-                                                        MBatch host) {
+__global__ __launch_bounds__(kBlock) void k_norm_reduce(CBatch Pn, int G, MBatch out, MBatch host) {
   __shared__ double hs[1];
   const int64_t b = blockIdx.x;
-  reduce_into(Pn + (int64_t)b * G, G, 1, 1, hs, kBlock / 64);
+  reduce_into(Pn.at(b), G, 1, 1, hs, kBlock / 64);
   if (threadIdx.x == 0) {
     const double d = sqrt(hs[0]);
     if (out.valid()) out.at(b)[0] = d;
@@ -292,8 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_lincomb(MBatch x, CBatch Z, int64_t 
   }
 }
 
-__global__ __launch_bounds__(kRed) void k_residual(CBatch bv, CBatch Ax, MBatch r, int64_t N, int G,
-                                                   double *__restrict__ P) {
+__global__ __launch_bounds__(kRed) void k_residual(CBatch bv, CBatch Ax, MBatch r, int64_t N, int G, MBatch P) {
   __shared__ double red[kRedWaves];
   const int g = blockIdx.x;
   const int64_t b = blockIdx.y;
@@ -309,7 +305,7 @@ __global__ __launch_bounds__(kRed) void k_residual(CBatch bv, CBatch Ax, MBatch 
     nrm = fma(v, v, nrm);
   }
   const double s = block_sum(nrm, red);
-  if (threadIdx.x == 0) P[b * G + g] = s;
+  if (threadIdx.x == 0) P.at(b)[g] = s;
 }
 
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -330,7 +326,7 @@ int reduction_blocks(int64_t N) {
 }
 
 void launch_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch w, int64_t N, int64_t nbatch, int G,
-                 int ldp, double *P, bool aligned16_all) {
+                 int ldp, MBatch P, bool aligned16_all) {
   const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16_all;
   const dim3 grid(G, (unsigned)nbatch), blk(kRed);
   if (vec)
@@ -339,8 +335,8 @@ void launch_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch w, int6
     hipLaunchKernelGGL(k_dots<false>, grid, blk, 0, s, V, ldv, nv, w, N, G, ldp, P);
 }
 
-void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const double *Pin, int G, int ldp, MBatch w,
-                        int64_t N, int64_t nbatch, double *Pout, MBatch hout, bool aligned16_all) {
+void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch Pin, int G, int ldp, MBatch w,
+                        int64_t N, int64_t nbatch, MBatch Pout, MBatch hout, bool aligned16_all) {
   const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16_all;
   const dim3 grid(G, (unsigned)nbatch), blk(kRed);
   if (vec)
@@ -349,8 +345,8 @@ void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const d
     hipLaunchKernelGGL(k_update_dots<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pout, hout);
 }
 
-void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const double *Pin, int G, int ldp, MBatch w,
-                        int64_t N, int64_t nbatch, double *Pnorm, CBatch h1, MBatch Hcol, MBatch host,
+void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch Pin, int G, int ldp, MBatch w,
+                        int64_t N, int64_t nbatch, MBatch Pnorm, CBatch h1, MBatch Hcol, MBatch host,
                         bool aligned16_all) {
   const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16_all;
   const dim3 grid(G, (unsigned)nbatch), blk(kRed);
@@ -360,7 +356,7 @@ void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, const d
     hipLaunchKernelGGL(k_update_norm<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pnorm, h1, Hcol, host);
 }
 
-void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, const double *Pn, int G, int64_t N, int64_t nbatch,
+void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, CBatch Pn, int G, int64_t N, int64_t nbatch,
                          MBatch out, MBatch host, bool aligned16_all) {
   if (N % 2 == 0 && aligned16_all)
     hipLaunchKernelGGL(k_scale_reduce<true>, dim3(stream_blocks(N, 2), (unsigned)nbatch), dim3(kBlock), 0, s, w, v,
@@ -370,7 +366,7 @@ void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, const double *Pn, in
                        Pn, G, N, out, host);
 }
 
-void launch_norm_reduce(hipStream_t s, const double *Pn, int G, int64_t nbatch, MBatch out, MBatch host) {
+void launch_norm_reduce(hipStream_t s, CBatch Pn, int G, int64_t nbatch, MBatch out, MBatch host) {
   hipLaunchKernelGGL(k_norm_reduce, dim3((unsigned)nbatch), dim3(kBlock), 0, s, Pn, G, out, host);
 }
 
@@ -380,7 +376,7 @@ void launch_lincomb(hipStream_t s, MBatch x, CBatch Z, int64_t ldz, IBatch k, co
                      N, overwrite);
 }
 
-void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G, double *P) {
+void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G, MBatch P) {
   hipLaunchKernelGGL(k_residual, dim3(G, (unsigned)nbatch), dim3(kRed), 0, s, b, Ax, r, N, G, P);
 }
 

@@ -230,8 +230,8 @@ constexpr int kPlaneRows = 16;                 // i2 rows per pass-1 tile
 constexpr int kPlaneRowsMax = kPlaneRows + 15; // rows j2 the tile may need (w2 <= 16)
 
 template <int WMAX>
-__global__ __launch_bounds__(kBlock) void k_kron3_planes(CBatch x, double *__restrict__ ao,
-                                                         double *__restrict__ co, int n, KronBands bd) {
+__global__ __launch_bounds__(kBlock) void k_kron3_planes(CBatch x, MBatch ao, MBatch co, int n,
+                                                         KronBands bd) {
   __shared__ double sm[kPlaneRowsMax][64];
   __shared__ double sk[kPlaneRowsMax][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -240,7 +240,10 @@ __global__ __launch_bounds__(kBlock) void k_kron3_planes(CBatch x, double *__res
   const int64_t pl = blockIdx.z;  // b * n + j3
   const int64_t n2 = (int64_t)n * n;
   const int64_t ent = pl / n;
-  const double *__restrict__ xp = x.at(ent) + (pl - ent * n) * n2;
+  const int64_t j3 = pl - ent * n;
+  const double *__restrict__ xp = x.at(ent) + j3 * n2;
+  double *__restrict__ ap = ao.at(ent) + j3 * n2;
+  double *__restrict__ cp = co.at(ent) + j3 * n2;
   const int w1 = bd.w[0], w2 = bd.w[1];
   const bool act1 = i1 < n;
   const int i1c = act1 ? i1 : n - 1;
@@ -296,17 +299,17 @@ __global__ __launch_bounds__(kBlock) void k_kron3_planes(CBatch x, double *__res
         c = fma(k2[t2], vm, c);
         c = fma(m2[t2], vk, c);
       }
-    const int64_t o = pl * n2 + (int64_t)i2 * n + i1;
-    ao[o] = a;
-    co[o] = c;
+    const int64_t o = (int64_t)i2 * n + i1;
+    ap[o] = a;
+    cp[o] = c;
   }
 }
 
 constexpr int kRowsPerThread = 4;  // consecutive i3 outputs per thread in pass 2
 
 template <int WMAX>
-__global__ __launch_bounds__(kBlock) void k_kron3_mode3(const double *__restrict__ ai, const double *__restrict__ ci,
-                                                        MBatch y, int n, int ngroups, KronBands bd) {
+__global__ __launch_bounds__(kBlock) void k_kron3_mode3(CBatch ai, CBatch ci, MBatch y, int n, int ngroups,
+                                                        KronBands bd) {
   const int64_t n2 = (int64_t)n * n;
   const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (col >= n2) return;
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_kron3_mode3(const double *__restrict
   const int w3 = bd.w[2];
   const int P0 = bd.lo[2][s];
   const int np = bd.lo[2][e - 1] + w3 - P0;  // planes needed, <= kRowsPerThread - 1 + WMAX
-  const double *ab = ai + b * n2 * n + col, *cb = ci + b * n2 * n + col;
+  const double *ab = ai.at(b) + col, *cb = ci.at(b) + col;
   constexpr int NPMAX = kRowsPerThread - 1 + WMAX;
   double av[NPMAX], cv[NPMAX];
 #pragma unroll
@@ -414,42 +417,48 @@ __global__ __launch_bounds__(kBlock) void k_kron2_window(CBatch x, MBatch y, int
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_ell_f64(const double *__restrict__ x, double *__restrict__ y,
-                                                    int64_t nrows, int64_t ld, int width,
+__global__ __launch_bounds__(kBlock) void k_ell_f64(CBatch x, MBatch y, int64_t nrows, int64_t ld, int width,
                                                     const int32_t *__restrict__ col,
-                                                    const double *__restrict__ val, int64_t total) {
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const int64_t b = idx / nrows, row = idx - b * nrows;
-  const double *xb = x + b * nrows;
+                                                    const double *__restrict__ val) {
+  const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (row >= nrows) return;
+  const int64_t b = blockIdx.y;
+  const double *__restrict__ xb = x.at(b);
   double acc = 0.0;
   for (int t = 0; t < width; ++t) {
     const int64_t e = (int64_t)t * ld + row;
     acc = fma(val[e], xb[col[e]], acc);
   }
-  y[idx] = acc;
+  y.at(b)[row] = acc;
 }
 
 }  // namespace
 
 int kron_window_max() { return 16; }
 
+bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bd) {
+  if (d != 3) return true;
+  int w = 0;
+  for (int l = 0; l < d; ++l) w = bd.w[l] > w ? bd.w[l] : w;
+  return bd.rows16 <= kPlaneRowsMax && bd.step3 <= 1 && w <= 8 && (int64_t)n * nbatch <= 65535;
+}
+
 bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int64_t nbatch, const KronBands &bd,
-                            double *tmp_a, double *tmp_c) {
+                            MBatch tmp_a, MBatch tmp_c) {
   int w = 0;
   for (int l = 0; l < d; ++l) w = bd.w[l] > w ? bd.w[l] : w;
   const dim3 blk(kBlock);
   if (d == 3) {
-    if (tmp_a && tmp_c && bd.rows16 <= kPlaneRowsMax && bd.step3 <= 1 && w <= 8 && (int64_t)n * nbatch <= 65535) {
+    if (tmp_a.valid() && tmp_c.valid() && kron_two_pass_ok(d, n, nbatch, bd)) {
       const dim3 g1(cdiv(n, 64), cdiv(n, kPlaneRows), (unsigned)(n * nbatch));
       const int ngroups = (int)cdiv(n, kRowsPerThread);
       const dim3 g2(cdiv((int64_t)n * n, kBlock), (unsigned)(ngroups * nbatch));
       if (w <= 4) {
         hipLaunchKernelGGL(k_kron3_planes<4>, g1, blk, 0, s, x, tmp_a, tmp_c, n, bd);
-        hipLaunchKernelGGL(k_kron3_mode3<4>, g2, blk, 0, s, tmp_a, tmp_c, y, n, ngroups, bd);
+        hipLaunchKernelGGL(k_kron3_mode3<4>, g2, blk, 0, s, as_const(tmp_a), as_const(tmp_c), y, n, ngroups, bd);
       } else {
         hipLaunchKernelGGL(k_kron3_planes<8>, g1, blk, 0, s, x, tmp_a, tmp_c, n, bd);
-        hipLaunchKernelGGL(k_kron3_mode3<8>, g2, blk, 0, s, tmp_a, tmp_c, y, n, ngroups, bd);
+        hipLaunchKernelGGL(k_kron3_mode3<8>, g2, blk, 0, s, as_const(tmp_a), as_const(tmp_c), y, n, ngroups, bd);
       }
       return true;
     }
@@ -484,11 +493,10 @@ bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int
   return true;
 }
 
-void launch_ell_matvec_f64(hipStream_t s, const double *x, double *y, int64_t nrows, int64_t ld, int width,
+void launch_ell_matvec_f64(hipStream_t s, CBatch x, MBatch y, int64_t nrows, int64_t ld, int width,
                            const int32_t *col, const double *val, int64_t nbatch) {
-  const int64_t total = nrows * nbatch;
-  hipLaunchKernelGGL(k_ell_f64, dim3(cdiv(total, kBlock)), dim3(kBlock), 0, s, x, y, nrows, ld, width, col, val,
-                     total);
+  hipLaunchKernelGGL(k_ell_f64, dim3(cdiv(nrows, kBlock), (unsigned)nbatch), dim3(kBlock), 0, s, x, y, nrows, ld,
+                     width, col, val);
 }
 
 }  // namespace fdg

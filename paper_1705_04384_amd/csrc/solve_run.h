@@ -1,0 +1,119 @@
+// One flexible GMRES solve as a host-side state machine over device phases.
+//
+// A solve alternates between a phase of device work (kernels enqueued on a stream) and a
+// host step that reads the few scalars the phase left in host-mapped memory (Hessenberg
+// column, norms), updates the Givens least-squares problem in FP64 and chooses the next
+// phase.  The single-solve entry point drives one run with a stream synchronisation per
+// phase; the request server drives many runs, and launches the phases of runs that share
+// a context and a step mask together (gathered batch entries).  Both use the same
+// kernels with the same per-entry reduction order, so a solve gives the same bits alone
+// or inside any mix.
+#pragma once
+
+#include <chrono>
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "context.h"
+#include "kernels.h"
+
+namespace fdg {
+
+// Device memory of one solve (N doubles each unless stated).
+struct RunBufs {
+  double *V = nullptr;                    // (m+1) N: Arnoldi basis
+  double *Z = nullptr;                    // m N: preconditioned directions
+  double *t1 = nullptr, *t2 = nullptr;    // apply / matvec scratch
+  void *t32a = nullptr, *t32b = nullptr;  // low-precision apply scratch, N floats each
+  double *P1 = nullptr, *P2 = nullptr;    // G (m+1) partial sums each
+  double *P3 = nullptr;                   // G partial sums
+  double *Hcol = nullptr, *h1 = nullptr;  // m+2 each
+  double *scal = nullptr;                 // 2: ||b||, residual norm
+  volatile double *hh = nullptr;          // host-mapped, m+4: column [0, m+2), ||b||, residual norm
+  double *hh_dev = nullptr;               // device address of hh
+};
+
+// Device bytes of RunBufs for an N-vector solve with restart m (each piece 256-aligned).
+size_t run_bytes(int64_t N, int m, bool lowp);
+// Carves RunBufs out of [base, base + run_bytes(...)); hh / hh_dev are set by the caller.
+RunBufs carve_run(char *base, int64_t N, int m, bool lowp);
+
+// Steps of a phase, executed in this order.
+enum : unsigned {
+  kStepBDots = 1u << 0,    // P3 = partials of |b|^2
+  kStepBNorm = 1u << 1,    // |b| -> scal[0], hh[m+2]
+  kStepBScale = 1u << 2,   // V0 = b / |b|; |b| -> scal[0], hh[m+2]
+  kStepLincomb = 1u << 3,  // x = (x or 0) + Z y
+  kStepRes = 1u << 4,      // Z0 = A x; V0 = b - Z0; P3 = partials of |V0|^2
+  kStepRScale = 1u << 5,   // V0 /= |V0|; |V0| -> scal[1], hh[m+3]
+  kStepRNorm = 1u << 6,    // |V0| -> scal[1], hh[m+3]
+  kStepIter = 1u << 7,     // Z_j = P^-1 V_j; V_{j+1} = A Z_j; CGS2; column -> Hcol, hh
+  kStepZeroX = 1u << 8,    // x = 0
+};
+
+struct Phase {
+  unsigned steps = 0;      // 0: the solve is finished
+  int j = 0;               // Arnoldi index of kStepIter
+  int k = 0;               // coefficients of kStepLincomb
+  bool overwrite = false;  // kStepLincomb starts from x = 0
+};
+
+class SolveRun {
+ public:
+  // Binds a solve of A x = b (device vectors of ctx->N doubles) to its buffers and sets
+  // the first phase.  Arguments are validated by the caller.
+  void init(fdg_ctx *c, const RunBufs &bufs, int restart, const double *b, double *x, double rtol, int maxit,
+            int flags);
+  // The phase to enqueue next (or in flight).
+  const Phase &phase() const { return ph_; }
+  bool finished() const { return ph_.steps == 0; }
+  // The phase in flight has completed (stream or event synchronised): read its results,
+  // advance the least-squares state and set the next phase.
+  void consume();
+  int status() const { return status_; }
+  const fdg_info &info() const { return info_; }
+  const Coeffs &coeffs() const { return y_; }
+
+  fdg_ctx *ctx = nullptr;
+  RunBufs buf;
+  int m = 0;
+  int64_t N = 0;
+  int G = 0;
+  const double *b = nullptr;
+  double *x = nullptr;
+
+ private:
+  double &Hij(int i, int jj) { return H_[(size_t)i * m + jj]; }
+  void finish(bool converged);
+  void zero_then_finish(bool converged);
+
+  Phase ph_;
+  double rtol_ = 0.0, bnorm_ = -1.0, target_ = 0.0, last_est_ = 1.0, rbeta_ = 0.0;
+  int limit_ = 0, total_ = 0, restarts_ = 0, status_ = FDG_OK;
+  bool fixed_ = false, x_nonzero_ = false, breakdown_ = false, pending_conv_ = false;
+  std::vector<double> H_, cs_, sn_, g_;
+  Coeffs y_;
+  fdg_info info_{};
+  std::chrono::steady_clock::time_point t0_;
+};
+
+// Bump allocator over a pinned host staging buffer mirrored in device memory: pointer
+// tables of gathered launches are written on the host and copied once per phase group.
+struct TableArena {
+  char *host = nullptr;
+  char *dev = nullptr;
+  size_t cap = 0, used = 0, flushed = 0;
+  void reset() { used = flushed = 0; }
+  // Host and device addresses of a fresh 16-byte aligned block, or false when full.
+  bool alloc(size_t bytes, void **h, void **d);
+  // Copies the blocks allocated since the last flush to the device on stream s.
+  int flush(hipStream_t s);
+};
+
+// Enqueues the current phase of nrun runs (same context, same step mask; nrun <= the
+// group limit) on ex.stream.  One run uses plain pointers; several use pointer tables
+// from tab, which must then be non-null.
+int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *tab);
+
+}  // namespace fdg

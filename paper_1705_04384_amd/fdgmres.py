@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfdgmres.so")
 
 FDG_OK = 0
 FDG_NOT_CONVERGED = 1
+FDG_EFULL = -7
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 SOLVE_USE_X0 = 1
 SOLVE_FIXED_ITERS = 2
@@ -37,6 +38,10 @@ class fdg_info(ctypes.Structure):
                 ("rel_res_true", ctypes.c_double), ("ms_total", ctypes.c_double)]
 
 
+class fdg_done(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int), ("info", fdg_info)]
+
+
 _lib = None
 
 EXPORTS = [
@@ -44,6 +49,8 @@ EXPORTS = [
     "fdg_create", "fdg_destroy", "fdg_set_prec_factors", "fdg_set_precision",
     "fdg_set_operator_kron", "fdg_set_operator_csr", "fdg_apply_prec", "fdg_matvec", "fdg_solve",
     "fdg_footprint_bytes", "fdg_timer_enable", "fdg_timer_read", "fdg_status_str", "fdg_last_error",
+    "fdg_server_create", "fdg_server_destroy", "fdg_server_run_bytes", "fdg_server_admit", "fdg_server_step",
+    "fdg_server_pending", "fdg_server_stats",
 ]
 
 
@@ -74,6 +81,17 @@ def lib():
     L.fdg_footprint_bytes.restype = ctypes.c_size_t
     L.fdg_timer_enable.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     L.fdg_timer_read.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, _dp]
+    L.fdg_server_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_size_t]
+    L.fdg_server_destroy.argtypes = [ctypes.c_void_p]
+    L.fdg_server_run_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.fdg_server_run_bytes.restype = ctypes.c_size_t
+    L.fdg_server_admit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int64]
+    L.fdg_server_step.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(fdg_done), ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_int)]
+    L.fdg_server_pending.argtypes = [ctypes.c_void_p]
+    L.fdg_server_stats.argtypes = [ctypes.c_void_p, _i64p, _i64p, _i64p, _i64p]
     L.fdg_status_str.argtypes = [ctypes.c_int]
     L.fdg_status_str.restype = ctypes.c_char_p
     L.fdg_last_error.argtypes = []
@@ -210,6 +228,67 @@ class Context:
         cnt = ctypes.c_int64(); ms = ctypes.c_double()
         _check(lib().fdg_timer_read(self._h, kernel, ctypes.byref(cnt), ctypes.byref(ms)))
         return cnt.value, ms.value
+
+
+class Server:
+    """Request server of the C ABI (fdg_server_*): continuous batching of solves."""
+
+    def __init__(self, max_slots, restart=30, lanes=4, arena_bytes=8 << 30):
+        h = ctypes.c_void_p()
+        _check(lib().fdg_server_create(ctypes.byref(h), max_slots, restart, lanes, arena_bytes))
+        self._h = h
+        self.restart = restart
+        self._cap = max_slots
+        self._done = (fdg_done * max_slots)()
+
+    def close(self):
+        if self._h:
+            lib().fdg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run_bytes(self, ctx):
+        return int(lib().fdg_server_run_bytes(ctx._h, self.restart))
+
+    def admit(self, ctx, b, x, rtol=1e-8, maxit=1000, flags=0, tag=0):
+        """True when admitted, False when no slot or arena space is free (FDG_EFULL)."""
+        st = lib().fdg_server_admit(self._h, ctx._h, _dev_ptr(b), _dev_ptr(x), rtol, maxit, flags, tag)
+        _check(st, allow=(FDG_OK, FDG_EFULL))
+        return st == FDG_OK
+
+    def step(self, wait_us=0):
+        """Advances ready lanes; returns [(tag, status, info dict)] of completed requests."""
+        nd = ctypes.c_int()
+        _check(lib().fdg_server_step(self._h, int(wait_us), self._done, self._cap, ctypes.byref(nd)))
+        out = []
+        for k in range(nd.value):
+            d = self._done[k]
+            out.append((d.tag, d.status, {f: getattr(d.info, f) for f, _ in fdg_info._fields_}))
+        return out
+
+    def pending(self):
+        return int(lib().fdg_server_pending(self._h))
+
+    def stats(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(lib().fdg_server_stats(self._h, *[ctypes.byref(a) for a in v]))
+        return dict(zip(("services", "groups", "grouped_runs", "max_group"), (a.value for a in v)))
+
+
+def unit_context(d, n, M, K, U, V, lam, batch=1, stream=None, prec=PREC_FP64):
+    """Context of the unit-domain problem from given 1D factors (operator eq. 2.7 / 2.9 and
+    its FD preconditioner, the same factors in every direction)."""
+    ctx = Context(d, n, batch=batch, stream=stream)
+    for l in range(d):
+        ctx.set_prec_factors(l, U, V, lam)
+        ctx.set_operator_kron(l, M, K)
+    ctx.set_precision(prec)
+    return ctx
 
 
 def unit_problem(d, p, n, batch=1, stream=None, prec=PREC_FP64):

@@ -28,7 +28,8 @@ def serving_requests(count, rate_per_s, seed=SEED_ARRIVALS):
     Returns a list of dicts (arrival time in seconds, d, p, n, rhs seed):
     d in {2, 3} with equal probability, p uniform in {2..6}, n uniform in
     [32, 256] for d = 2 and in [16, 128] for d = 3 (n counts unknowns per
-    direction and is at least p - 1 + 12)."""
+    direction, so every request has E = n + 2 - p >= 12 knot spans).  The
+    shapes do not depend on the rate: the gaps are unit-rate draws scaled by it."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate_per_s, count)
     t = np.cumsum(gaps) - gaps[0]
