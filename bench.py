@@ -7,6 +7,13 @@ a seeded N(0, 1) vector.  The operator is applied as the Kronecker sum of eq. 2.
 preconditioner by the FD solve of eq. 4.9.  Inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
+Serving (field "serving"): 2000 requests with Poisson arrivals, d in {2, 3}, p in 2..6,
+n in [32, 256] (2D) / [16, 128] (3D), N(0, 1) right-hand sides, FP64 FGMRES(30) to
+rtol 1e-8, through the request server (continuous batching) and, as the baseline, the
+same stream solved one request at a time; closed-loop saturation throughput, then
+p50/p99 latency at arrival rates of 0.8x and 0.5x the served saturation, with a warm
+factor cache and (0.8x) a cold one.
+
 Extra fields: the P^{-1} apply rate (algorithmic 12 n^4 flops per apply), the roofline
 of the dominant kernel (the FP64 MFMA mode product, 2 n^4 flops per launch) from HIP
 events recorded around every launch in the timed region, and the oracle (CPU, FP64)
@@ -34,7 +41,75 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-solves", type=int, default=4)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with 3 device copies of 256 MiB (known bytes, to scale HBM counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_slab_fd_unit128_p4_traffic.md")
+FD_SOURCE = os.path.join(ROOT, "paper_1705_04384_amd", "csrc", "fd_apply.hip")
+
+
+def measured_traffic():
+    """HBM bytes per k_slab launch from the committed counter summary, or None when the
+    summary is missing or was taken on a different version of the FD kernel source."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(FD_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        line = line.strip().lstrip("-").strip()
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("fd_apply.hip sha256") != src:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def serving(count):
+    """The serving workload: served vs one-by-one, warm and cold factor cache."""
+    from paper_1705_04384_amd import fdgmres, inputs, serve
+    reqs = inputs.serving_requests(count, 1.0)  # unit-rate arrival times, scaled per run
+    cache = serve.FactorCache(threads=16)
+    t = time.perf_counter()
+    cache.warm(reqs)
+    setup_s = time.perf_counter() - t
+    bufs = serve.stage(reqs)
+    lanes, slots, arena = 4, 256, 48 << 30
+    srv = fdgmres.Server(max_slots=slots, restart=30, lanes=lanes, arena_bytes=arena)
+    out = {"workload": f"{count} requests, Poisson arrivals (seed {inputs.SEED_ARRIVALS}), d in {{2,3}}, "
+                       "p in 2..6, n in [32,256] (2D) / [16,128] (3D), N(0,1) RHS (seed 1000+r), unit domain, "
+                       "FP64 FGMRES(30) to rtol 1e-8; RHS resident in HBM; latency = completion - arrival",
+           "server": {"lanes": lanes, "max_slots": slots, "arena_gib": arena >> 30},
+           "warm_setup_s": setup_s, "distinct_shapes": len(cache.ctxs)}
+    res, mk = serve.run_served(srv, cache, reqs, bufs, time_scale=0.0)
+    sat = serve.summarize(res, mk)
+    res1, mk1 = serve.run_one_by_one(cache, reqs, bufs, time_scale=0.0)
+    out["closed_loop"] = {"served": sat, "one_by_one": serve.summarize(res1, mk1)}
+    for frac in (0.8, 0.5):
+        rate = frac * sat["solves_per_s"]
+        r_s, m_s = serve.run_served(srv, cache, reqs, bufs, time_scale=1.0 / rate)
+        r_o, m_o = serve.run_one_by_one(cache, reqs, bufs, time_scale=1.0 / rate)
+        out[f"open_loop_{frac}"] = {"rate_per_s": rate, "served": serve.summarize(r_s, m_s),
+                                    "one_by_one": serve.summarize(r_o, m_o)}
+    out["server"]["stats"] = srv.stats()
+    cache.close()
+    cold = serve.FactorCache(threads=16)
+    rate = 0.8 * sat["solves_per_s"]
+    r_c, m_c = serve.run_served(srv, cold, reqs, bufs, time_scale=1.0 / rate)
+    out["cold_cache_open_loop_0.8"] = {"rate_per_s": rate, "served": serve.summarize(r_c, m_c)}
+    cold.close()
+    srv.close()
+    return out
 
 
 def cpu_baseline(p, n, f, noise, count):
@@ -147,16 +222,24 @@ def main():
                        "frac_fp64_mfma": apply_flops / t_apply / 1e12 / PEAK_FP64_TFLOPS},
         "roofline": {"kernel": "k_slab (FD modes 1+2, FP64 MFMA)", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(),
                      "launches": launches, "avg_launch_us": avg_s * 1e6,
                      "flops_per_launch": pass_flops},
         "fibre_pass": {"kernel": "k_fibre (FD mode 3 + divide + mode 3, FP64 MFMA)", "launches": f_launches,
                        "avg_launch_us": f_avg_s * 1e6,
                        "tflops": pass_flops / f_avg_s / 1e12 if f_launches else None},
     }
+    ctx.close()
+    if args.copy_calibration:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    if not args.no_serve:
+        out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, n, f, noise, args.cpu_solves)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 
