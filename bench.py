@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--cpu-solves", type=int, default=4)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the deformed-cube and precision-sweep fields")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with 3 device copies of 256 MiB (known bytes, to scale HBM counters)")
     return ap.parse_args()
@@ -109,6 +110,93 @@ def serving(count):
     out["cold_cache_open_loop_0.8"] = {"rate_per_s": rate, "served": serve.summarize(r_c, m_c)}
     cold.close()
     srv.close()
+    return out
+
+
+def timed_solves(ctx, b, x, reps, **kw):
+    """Average wall time of reps solves plus the per-class kernel time (HIP events)."""
+    import torch
+    from paper_1705_04384_amd import fdgmres
+    classes = (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE, fdgmres.TIMER_MATVEC, fdgmres.TIMER_KRYLOV)
+    info = ctx.solve(b, x, **kw)  # warm-up
+    torch.cuda.synchronize()
+    for c in classes:
+        ctx.timer_read(c)
+        ctx.timer_enable(c, True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        info = ctx.solve(b, x, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    split = {}
+    for c, name in zip(classes, ("fd_slab", "fd_fibre", "matvec", "krylov")):
+        ctx.timer_enable(c, False)
+        cnt, ms = ctx.timer_read(c)
+        split[name] = {"launches_per_solve": cnt / reps, "ms_per_solve": ms / reps}
+    return dt, info, split
+
+
+def deformed_96():
+    """Deformed cube, p = 3, n = 96: CSR operator (27 nnz per row), FD preconditioner."""
+    import torch
+    from paper_1705_04384_amd import fdgmres, inputs
+    p, n = 3, 96
+    N = n ** 3
+    t = time.perf_counter()
+    ctx = fdgmres.deformed_problem(p, n, 0.1)
+    setup = time.perf_counter() - t
+    b = torch.from_numpy(inputs.rhs_uniform(inputs.SEED_DEFORMED_96, N)).cuda()
+    x = torch.empty_like(b)
+    dt, info, split = timed_solves(ctx, b, x, 5, rtol=1e-8, restart=30)
+    mv = split["matvec"]
+    spmv_bytes = ctx.nnz * 12 + 2 * N * 8
+    spmv_s = mv["ms_per_solve"] / 1e3 / max(mv["launches_per_solve"], 1)
+    out = {"workload": f"deformed cube (cyclic sin map, amplitude 0.1), p={p}, n={n} (N={N}), CSR {ctx.nnz} nnz "
+                       "(27/row) on the device as ELL, U[-1,1] RHS, FGMRES(30) to rtol 1e-8, FP64",
+           "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": info["iterations"],
+           "restarts": info["restarts"], "rel_res_true": info["rel_res_true"], "setup_s": setup,
+           "kernel_ms_per_solve": split,
+           "spmv": {"avg_us": spmv_s * 1e6, "algorithmic_bytes": spmv_bytes,
+                    "gbps": spmv_bytes / spmv_s / 1e9, "frac_hbm": spmv_bytes / spmv_s / 8e12}}
+    ctx.close()
+    return out
+
+
+def precision_sweep_192():
+    """Unit cube, p = 6, n = 192, FGMRES(50): P^-1 in FP64, FP32 and BF16 (FP32 accumulate).
+    k* = the fixed iteration count at which the solution is within 1e-8 of the FP64 solve
+    (itself checked against the oracle by the test suite); timed solves use k*."""
+    import torch
+    from paper_1705_04384_amd import fdgmres, inputs
+    d, p, n = 3, 6, 192
+    N = n ** d
+    b = torch.from_numpy(inputs.rhs_normal(inputs.SEED_SWEEP_192, N)).cuda()
+    x = torch.empty_like(b)
+    out = {"workload": f"unit cube, p={p}, n={n} (N={N}), N(0,1) RHS, FGMRES(50), outer FP64"}
+    ctx = fdgmres.unit_problem(d, p, n)
+    dt, info, split = timed_solves(ctx, b, x, 5, rtol=1e-8, restart=50)
+    x64 = x.clone()
+    out["fp64"] = {"ms_per_solve": dt * 1e3, "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
+                   "kernel_ms_per_solve": split}
+    ctx.close()
+    for name, prec in (("fp32", fdgmres.PREC_FP32), ("bf16", fdgmres.PREC_BF16)):
+        ctx = fdgmres.unit_problem(d, p, n, prec=prec)
+        k_star, err = None, None
+        for k in range(1, 13):
+            ctx.solve(b, x, rtol=0.0, restart=50, maxit=k, flags=fdgmres.SOLVE_FIXED_ITERS)
+            err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+            if err <= 1e-8:
+                k_star = k
+                break
+        entry = {"k_star": k_star, "err_vs_fp64": err}
+        if k_star is not None:
+            dt, info, split = timed_solves(ctx, b, x, 5, rtol=0.0, restart=50, maxit=k_star,
+                                           flags=fdgmres.SOLVE_FIXED_ITERS)
+            entry.update({"ms_per_solve": dt * 1e3, "rel_res_true": info["rel_res_true"],
+                          "speedup_vs_fp64": out["fp64"]["ms_per_solve"] / (dt * 1e3),
+                          "kernel_ms_per_solve": split})
+        out[name] = entry
+        ctx.close()
     return out
 
 
@@ -236,6 +324,9 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+    if not args.no_extra:
+        out["deformed_96"] = deformed_96()
+        out["precision_sweep_192"] = precision_sweep_192()
     if not args.no_serve:
         out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:
