@@ -92,6 +92,7 @@ KronBands ctx_bands(const fdg_ctx *c) {
   bd.rows4 = c->bandrows4[c->d == 3 ? 1 : 0];
   bd.rows16 = c->bandrows16[c->d == 3 ? 1 : 0];
   bd.step3 = c->bandstep[c->d == 3 ? 2 : 0];
+  for (int l = 0; l < 3; ++l) bd.step[l] = c->bandstep[l < c->d ? l : 0];
   return bd;
 }
 }  // namespace
@@ -102,7 +103,7 @@ bool groupable(const fdg_ctx *c) {
   int w = 0;
   for (int l = 0; l < c->d; ++l) w = std::max(w, c->bandw[l]);
   KronBands bd = ctx_bands(c);
-  return kron_two_pass_ok(c->d, c->n, kMaxGroupEntries, bd);
+  return kron_fused_ok(c->n, kMaxGroupEntries, bd) || kron_two_pass_ok(c->d, c->n, kMaxGroupEntries, bd);
 }
 
 int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nent, MBatch t1, MBatch t2,

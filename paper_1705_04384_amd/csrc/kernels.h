@@ -36,6 +36,7 @@ struct KronBands {
   int rows4;   // max over i of lo2[min(i+3, n-1)] + w2 - lo2[i]: rows j2 that 4 rows i2 need
   int rows16;  // the same for 16 rows i2 (aligned tiles)
   int step3;   // max over i of lo3[i+1] - lo3[i]
+  int step[3];  // max over i of lo_l[i+1] - lo_l[i], per direction
 };
 // Requires non-decreasing band starts lo[] and w <= kron_window_max().  tmp_a, tmp_c:
 // per-entry scratch of n^3 doubles each for the two-pass 3D form (invalid: one pass).
@@ -46,6 +47,9 @@ int kron_window_max();
 // The 3D matvec of nbatch entries can take the two-pass form (which accepts gathered
 // batches); always true in 2D.
 bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bands);
+// The one-pass 3D form applies (band width <= 8, band starts growing by <= 1 per row in
+// directions 1 and 2); it needs no scratch and accepts gathered batches.
+bool kron_fused_ok(int n, int64_t nbatch, const KronBands &bands);
 
 // Slot-major ELL: entry (row, slot) at col[slot*ld + row], val[slot*ld + row].
 void launch_ell_matvec_f64(hipStream_t s, CBatch x, MBatch y, int64_t nrows, int64_t ld, int width,

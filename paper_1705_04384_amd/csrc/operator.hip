@@ -1,14 +1,18 @@
 // Operator matvecs: the unit-domain collocation matrix of eq. 2.9 / 2.7 applied from its
 // banded univariate factors, and a slot-major ELL matvec for an assembled matrix.
 //
-// Unit domain, 3D: y = (K3 x M2 x M1 + M3 x K2 x M1 + M3 x M2 x K1) x, sum-factorised.
-// One thread owns an output column (i2, i1) and sweeps a chunk of i3.  For every plane
-// j3 it needs, it forms the direction-1 band sums sM = M1 x, sK = K1 x on the rows
-// j2 of the i2 band and then the direction-2 sums
-//     a(j3)  = sum_j2 M2 sM,      c(j3) = sum_j2 (K2 sM + M2 sK);
-// the output is y(i3) = sum_j3 K3 a(j3) + M3 c(j3).  Band starts are non-decreasing in
-// the row index, so the planes j3 a chunk needs form a sliding window kept in registers:
-// each output row costs one new plane (2 w1 w2 + 3 w2 FMAs) plus 2 w3 FMAs.
+// Unit domain, 3D: y = (K3 x M2 x M1 + M3 x K2 x M1 + M3 x M2 x K1) x, sum-factorised:
+// per plane j3 the direction-1 band sums sM = M1 x, sK = K1 x, then the direction-2 sums
+//     a(j3) = sum_j2 M2 sM,      c(j3) = sum_j2 (K2 sM + M2 sK),
+// and the output y(i3) = sum_j3 K3 a(j3) + M3 c(j3) over the direction-3 band.
+// Forms, in order of preference:
+//   k_kron3_wpp     one pass, one wave per plane (bands up to 8 wide whose starts grow by
+//                   at most 1 per row in directions 1 and 2); no scratch, gathered batches;
+//   k_kron3_planes  two passes through per-plane intermediates a, c (scratch);
+//   + k_kron3_mode3
+//   k_kron3_lds /   one pass, a thread per output column sweeping i3 with a sliding
+//   k_kron3_window  window of planes in registers (contiguous batches only).
+// 2D: k_kron2_window, the same sliding window over i2.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,6 +26,15 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kChunk = 16;  // output rows of the sweep direction per thread
+
+// Shape of the one-pass 3D matvec: i2 rows per tile and i3 outputs per workgroup
+// (overridable at build time for tuning sweeps).
+#ifndef FDG_MV_T2
+#define FDG_MV_T2 2
+#endif
+#ifndef FDG_MV_C3
+#define FDG_MV_C3 16
+#endif
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -432,9 +445,168 @@ __global__ __launch_bounds__(kBlock) void k_ell_f64(CBatch x, MBatch y, int64_t 
   y.at(b)[row] = acc;
 }
 
+// One-pass 3D form, one wave per plane.  A workgroup of 8 waves owns a tile of 64
+// columns i1 x T2 rows i2 and a chunk of C3 outputs i3.  Each wave takes planes j3 of
+// the chunk's band: it loads the plane's rows (all issued at once), forms the
+// direction-1 band sums per row through a one-row LDS buffer of its own (no workgroup
+// barrier) and the direction-2 sums a = M2 sM, c = K2 sM + M2 sK in registers, and
+// stores a and c of its T2 x 64 tile to LDS.  After one barrier every wave forms outputs
+// y = sum K3 a + M3 c over the direction-3 band.  Two workgroup barriers in all.
+// Requires band starts that grow by at most 1 per row in directions 1 and 2.
+template <int WMAX, int T2, int C3>
+__global__ __launch_bounds__(512) void k_kron3_wpp(CBatch x, MBatch y, int n, int ntx, int nty, int nchunk,
+                                                   KronBands bd) {
+  constexpr int NWV = 8;
+  constexpr int RMAX = T2 + WMAX - 1;    // rows j2 a tile may need
+  constexpr int CW = 64 + WMAX;          // staged columns j1 per row
+  constexpr int NPLMAX = C3 + WMAX - 1;  // planes j3 a chunk may need
+  __shared__ double xrow[NWV][CW];
+  __shared__ double cm2[T2][RMAX], ck2[T2][RMAX];  // direction-2 coefficient of staged row r for output u
+  __shared__ double c3k[C3][WMAX], c3m[C3][WMAX];
+  __shared__ int lo3s[C3];
+  __shared__ double As[NPLMAX][T2][64], Cs[NPLMAX][T2][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nb = (int64_t)gridDim.x;
+  int64_t t = blockIdx.x;
+  if ((nb & 7) == 0) t = (t & 7) * (nb >> 3) + (t >> 3);
+  const int tx = (int)(t % ntx);
+  int64_t rest = t / ntx;
+  const int ty = (int)(rest % nty);
+  rest /= nty;
+  const int64_t ent = rest / nchunk;
+  const int s3 = (int)(rest - ent * nchunk) * C3;
+  const int i1a = tx * 64;
+  const int i1 = i1a + lane;
+  const int i2a = ty * T2;
+  const int e3 = s3 + C3 < n ? s3 + C3 : n;
+  const int64_t n2 = (int64_t)n * n;
+  const double *__restrict__ xb = x.at(ent);
+  double *__restrict__ yb = y.at(ent);
+  const int w1 = bd.w[0], w2 = bd.w[1], w3 = bd.w[2];
+  const bool act1 = i1 < n;
+  const int i1c = act1 ? i1 : n - 1;
+  const int L0 = bd.lo[0][i1a];
+  const int off1 = bd.lo[0][i1c] - L0;  // in [0, 63]
+  const int i2b = i2a + T2 - 1 < n ? i2a + T2 - 1 : n - 1;
+  const int R0 = bd.lo[1][i2a];
+  const int NR = bd.lo[1][i2b] + w2 - R0;  // <= RMAX
+  const int P0 = bd.lo[2][s3];
+  const int NPL = bd.lo[2][e3 - 1] + w3 - P0;  // <= NPLMAX
+  const int ncols = n - L0;
+  double m1[WMAX], k1[WMAX];
+#pragma unroll
+  for (int q = 0; q < WMAX; ++q) {
+    m1[q] = q < w1 ? bd.M[0][(size_t)i1c * w1 + q] : 0.0;
+    k1[q] = q < w1 ? bd.K[0][(size_t)i1c * w1 + q] : 0.0;
+  }
+  // coefficient tables (read from global memory before any LDS store)
+  double vm2 = 0.0, vk2 = 0.0, vm3 = 0.0, vk3 = 0.0;
+  int vlo3 = 1 << 30;
+  if (threadIdx.x < T2 * RMAX) {
+    const int u = threadIdx.x / RMAX, r = threadIdx.x - u * RMAX;
+    const int i2 = i2a + u;
+    if (i2 <= i2b) {
+      const int tt = R0 + r - bd.lo[1][i2];
+      if (tt >= 0 && tt < w2) {
+        vm2 = bd.M[1][(size_t)i2 * w2 + tt];
+        vk2 = bd.K[1][(size_t)i2 * w2 + tt];
+      }
+    }
+  }
+  if (threadIdx.x < C3 * WMAX) {
+    const int q = threadIdx.x / WMAX, tt = threadIdx.x - q * WMAX;
+    if (s3 + q < e3 && tt < w3) {
+      vm3 = bd.M[2][(size_t)(s3 + q) * w3 + tt];
+      vk3 = bd.K[2][(size_t)(s3 + q) * w3 + tt];
+    }
+  }
+  if (threadIdx.x < C3 && s3 + (int)threadIdx.x < e3) vlo3 = bd.lo[2][s3 + threadIdx.x];
+  if (threadIdx.x < T2 * RMAX) {
+    const int u = threadIdx.x / RMAX, r = threadIdx.x - u * RMAX;
+    cm2[u][r] = vm2;
+    ck2[u][r] = vk2;
+  }
+  if (threadIdx.x < C3 * WMAX) {
+    const int q = threadIdx.x / WMAX, tt = threadIdx.x - q * WMAX;
+    c3m[q][tt] = vm3;
+    c3k[q][tt] = vk3;
+  }
+  if (threadIdx.x < C3) lo3s[threadIdx.x] = vlo3;
+  __syncthreads();
+  for (int pl = wave; pl < NPL; pl += NWV) {
+    const double *xp = xb + (int64_t)(P0 + pl) * n2 + (int64_t)R0 * n + L0;
+    double xr[RMAX], xh[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      xr[r] = (r < NR && lane < ncols) ? xp[(int64_t)r * n + lane] : 0.0;
+      xh[r] = (r < NR && lane < WMAX && 64 + lane < ncols) ? xp[(int64_t)r * n + 64 + lane] : 0.0;
+    }
+    double hm[RMAX], hk[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+      xrow[wave][lane] = xr[r];
+      if (lane < WMAX) xrow[wave][64 + lane] = xh[r];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double vm = 0.0, vk = 0.0;
+#pragma unroll
+      for (int q = 0; q < WMAX; ++q)
+        if (q < w1) {
+          const double v = xrow[wave][off1 + q];
+          vm = fma(m1[q], v, vm);
+          vk = fma(k1[q], v, vk);
+        }
+      hm[r] = vm;
+      hk[r] = vk;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int u = 0; u < T2; ++u) {
+      double a = 0.0, c = 0.0;
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) {
+        const double cm = cm2[u][r], ck = ck2[u][r];
+        a = fma(cm, hm[r], a);
+        c = fma(ck, hm[r], c);
+        c = fma(cm, hk[r], c);
+      }
+      As[pl][u][lane] = a;
+      Cs[pl][u][lane] = c;
+    }
+  }
+  __syncthreads();
+  if (!act1) return;
+  for (int idx = wave; idx < C3 * T2; idx += NWV) {
+    const int q = idx / T2, u = idx - q * T2;
+    const int i2 = i2a + u;
+    if (s3 + q >= e3 || i2 > i2b) continue;
+    const int b3 = lo3s[q] - P0;
+    double acc = 0.0;
+#pragma unroll
+    for (int tt = 0; tt < WMAX; ++tt)
+      if (tt < w3) {
+        acc = fma(c3k[q][tt], As[b3 + tt][u][lane], acc);
+        acc = fma(c3m[q][tt], Cs[b3 + tt][u][lane], acc);
+      }
+    yb[(int64_t)(s3 + q) * n2 + (int64_t)i2 * n + i1] = acc;
+  }
+}
+
 }  // namespace
 
 int kron_window_max() { return 16; }
+
+bool kron_fused_ok(int n, int64_t nbatch, const KronBands &bd) {
+#ifdef FDG_MV_NOFUSED  // tuning builds only: compare against the two-pass form
+  return false;
+#endif
+  int w = 0;
+  for (int l = 0; l < 3; ++l) w = bd.w[l] > w ? bd.w[l] : w;
+  return w <= 8 && bd.step[0] <= 1 && bd.step[1] <= 1 && (int64_t)n * n * nbatch < ((int64_t)1 << 31);
+}
 
 bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bd) {
   if (d != 3) return true;
@@ -448,6 +620,18 @@ bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int
   int w = 0;
   for (int l = 0; l < d; ++l) w = bd.w[l] > w ? bd.w[l] : w;
   const dim3 blk(kBlock);
+  if (d == 3 && kron_fused_ok(n, nbatch, bd)) {
+    constexpr int T2 = FDG_MV_T2, C3 = FDG_MV_C3;
+    const int ntx = (int)cdiv(n, 64), nty = (int)cdiv(n, T2), nchunk = (int)cdiv(n, C3);
+    const dim3 grid((unsigned)((int64_t)ntx * nty * nchunk * nbatch));
+    if (w <= 4)
+      hipLaunchKernelGGL((k_kron3_wpp<4, T2, C3>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd);
+    else if (w <= 6)
+      hipLaunchKernelGGL((k_kron3_wpp<6, T2, C3>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd);
+    else
+      hipLaunchKernelGGL((k_kron3_wpp<8, T2, C3>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd);
+    return true;
+  }
   if (d == 3) {
     if (tmp_a.valid() && tmp_c.valid() && kron_two_pass_ok(d, n, nbatch, bd)) {
       const dim3 g1(cdiv(n, 64), cdiv(n, kPlaneRows), (unsigned)(n * nbatch));
