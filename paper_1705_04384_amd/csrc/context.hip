@@ -244,7 +244,7 @@ int ensure_krylov(fdg_ctx *c, int m) {
   if ((st = dalloc(&c->Hcol, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->hbuf, (size_t)2 * (m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->scal, (size_t)4 * c->batch)) != FDG_OK) return st;
-  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * (size_t)(2 * m + 8) * c->batch, hipHostMallocMapped));
+  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * (size_t)host_doubles(m) * c->batch, hipHostMallocMapped));
   HIPCHK(hipHostGetDevicePointer((void **)&c->hpin_dev, c->hpin, 0));
 
   c->restart_alloc = m;

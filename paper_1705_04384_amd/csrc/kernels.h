@@ -85,14 +85,18 @@ void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch 
 // out.at(e)[0] and host.at(e)[0] (either may be invalid).
 void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, CBatch Pn, int G, int64_t N, int64_t nbatch,
                          MBatch out, MBatch host, bool aligned16_all);
+// v = w / d (0 if d = 0; v may equal w), d = dtab[e] when dtab is given, else dval.
+void launch_scale_by(hipStream_t s, CBatch w, MBatch v, const double *dtab, double dval, int64_t N,
+                     int64_t nbatch, bool aligned16_all);
 // d = sqrt(sum of Pn.at(e)[g]) to out and host.
 void launch_norm_reduce(hipStream_t s, CBatch Pn, int G, int64_t nbatch, MBatch out, MBatch host);
 // x = (overwrite ? 0 : x) + sum_q Z_q y_q, q < k.at(e) <= 256; coefficients from ytab[e*256 + q]
 // when ytab is given, else y (shared by every entry).
 void launch_lincomb(hipStream_t s, MBatch x, CBatch Z, int64_t ldz, IBatch k, const Coeffs &y,
                     const double *ytab, int64_t N, int64_t nbatch, IBatch overwrite);
-// r = b - Ax and the partials P.at(e)[g] of |r|^2.
+// r = b - Ax and the partials P.at(e)[g] of |r|^2 (2-wide accesses, and so a different
+// summation order, when every pointer is 16-byte aligned and N is even).
 void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G,
-                     MBatch P);
+                     MBatch P, bool aligned16_all);
 
 }  // namespace fdg

@@ -249,10 +249,51 @@ __global__ __launch_bounds__(kBlock) void k_scale_reduce(CBatch w, MBatch v, CBa
   }
   const double *wb = w.at(b);
   double *vb = v.at(b);
+  if (VEC) {  // 4 double2 per thread per step, all loads issued before the stores
+    const int64_t step = (int64_t)gridDim.x * kBlock * 8;  // elements per step of the grid
+    for (int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 2; base < N; base += step) {
+      double2 xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * kBlock * 2 * gridDim.x;
+        xv[u] = i < N ? *reinterpret_cast<const double2 *>(wb + i) : double2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * kBlock * 2 * gridDim.x;
+        if (i < N)
+          *reinterpret_cast<double2 *>(vb + i) = d != 0.0 ? double2{xv[u].x / d, xv[u].y / d} : double2{0.0, 0.0};
+      }
+    }
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock)
+      vb[i] = d != 0.0 ? wb[i] / d : 0.0;
+  }
+}
+
+// v = w / d with d given per entry (table) or shared (value); 0 where d = 0.
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_scale_by(CBatch w, MBatch v, const double *__restrict__ dtab, double dval,
+                                                     int64_t N) {
+  const int64_t b = blockIdx.y;
+  const double d = dtab ? dtab[b] : dval;
+  const double *wb = w.at(b);
+  double *vb = v.at(b);
   if (VEC) {
-    for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 2; i < N; i += (int64_t)gridDim.x * kBlock * 2) {
-      const double2 x = *reinterpret_cast<const double2 *>(wb + i);
-      *reinterpret_cast<double2 *>(vb + i) = d != 0.0 ? double2{x.x / d, x.y / d} : double2{0.0, 0.0};
+    const int64_t step = (int64_t)gridDim.x * kBlock * 8;
+    for (int64_t base = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 2; base < N; base += step) {
+      double2 xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * kBlock * 2 * gridDim.x;
+        xv[u] = i < N ? *reinterpret_cast<const double2 *>(wb + i) : double2{0.0, 0.0};
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * kBlock * 2 * gridDim.x;
+        if (i < N)
+          *reinterpret_cast<double2 *>(vb + i) = d != 0.0 ? double2{xv[u].x / d, xv[u].y / d} : double2{0.0, 0.0};
+      }
     }
   } else {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock)
@@ -282,13 +323,33 @@ __global__ __launch_bounds__(kBlock) void k_lincomb(MBatch x, CBatch Z, int64_t 
   const int k = ks.at(b);
   const bool ow = overwrite.at(b) != 0;
   const double *yb = ytab ? ytab + b * 256 : y.v;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kBlock) {
-    double acc = ow ? 0.0 : xb[i];
-    for (int q = 0; q < k; ++q) acc = fma(Zb[(int64_t)q * ldz + i], yb[q], acc);
-    xb[i] = acc;
+  // 4 elements per thread per step (independent loads of every Z_q in flight together)
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < N; i0 += 4 * stride) {
+    double acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + u * stride;
+      acc[u] = (ow || i >= N) ? 0.0 : xb[i];
+    }
+    for (int q = 0; q < k; ++q) {
+      const double yq = yb[q];
+      const double *zq = Zb + (int64_t)q * ldz;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * stride;
+        if (i < N) acc[u] = fma(zq[i], yq, acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < N) xb[i] = acc[u];
+    }
   }
 }
 
+template <bool VEC>
 __global__ __launch_bounds__(kRed) void k_residual(CBatch bv, CBatch Ax, MBatch r, int64_t N, int G, MBatch P) {
   __shared__ double red[kRedWaves];
   const int g = blockIdx.x;
@@ -298,11 +359,23 @@ __global__ __launch_bounds__(kRed) void k_residual(CBatch bv, CBatch Ax, MBatch 
   const double *bb = bv.at(b), *ab = Ax.at(b);
   double *rb = r.at(b);
   double nrm = 0.0;
+  if (VEC) {
 #pragma unroll 4
-  for (int64_t i = beg + threadIdx.x; i < end; i += kRed) {
-    const double v = bb[i] - ab[i];
-    rb[i] = v;
-    nrm = fma(v, v, nrm);
+    for (int64_t i = beg + 2 * threadIdx.x; i < end; i += 2 * kRed) {
+      const double2 x = *reinterpret_cast<const double2 *>(bb + i);
+      const double2 a = *reinterpret_cast<const double2 *>(ab + i);
+      const double2 v = {x.x - a.x, x.y - a.y};
+      *reinterpret_cast<double2 *>(rb + i) = v;
+      nrm = fma(v.x, v.x, nrm);
+      nrm = fma(v.y, v.y, nrm);
+    }
+  } else {
+#pragma unroll 4
+    for (int64_t i = beg + threadIdx.x; i < end; i += kRed) {
+      const double v = bb[i] - ab[i];
+      rb[i] = v;
+      nrm = fma(v, v, nrm);
+    }
   }
   const double s = block_sum(nrm, red);
   if (threadIdx.x == 0) P.at(b)[g] = s;
@@ -359,11 +432,21 @@ void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch 
 void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, CBatch Pn, int G, int64_t N, int64_t nbatch,
                          MBatch out, MBatch host, bool aligned16_all) {
   if (N % 2 == 0 && aligned16_all)
-    hipLaunchKernelGGL(k_scale_reduce<true>, dim3(stream_blocks(N, 2), (unsigned)nbatch), dim3(kBlock), 0, s, w, v,
+    hipLaunchKernelGGL(k_scale_reduce<true>, dim3(stream_blocks(N, 8), (unsigned)nbatch), dim3(kBlock), 0, s, w, v,
                        Pn, G, N, out, host);
   else
     hipLaunchKernelGGL(k_scale_reduce<false>, dim3(stream_blocks(N, 1), (unsigned)nbatch), dim3(kBlock), 0, s, w, v,
                        Pn, G, N, out, host);
+}
+
+void launch_scale_by(hipStream_t s, CBatch w, MBatch v, const double *dtab, double dval, int64_t N, int64_t nbatch,
+                     bool aligned16_all) {
+  if (N % 2 == 0 && aligned16_all)
+    hipLaunchKernelGGL(k_scale_by<true>, dim3(stream_blocks(N, 8), (unsigned)nbatch), dim3(kBlock), 0, s, w, v, dtab,
+                       dval, N);
+  else
+    hipLaunchKernelGGL(k_scale_by<false>, dim3(stream_blocks(N, 1), (unsigned)nbatch), dim3(kBlock), 0, s, w, v, dtab,
+                       dval, N);
 }
 
 void launch_norm_reduce(hipStream_t s, CBatch Pn, int G, int64_t nbatch, MBatch out, MBatch host) {
@@ -372,12 +455,16 @@ void launch_norm_reduce(hipStream_t s, CBatch Pn, int G, int64_t nbatch, MBatch 
 
 void launch_lincomb(hipStream_t s, MBatch x, CBatch Z, int64_t ldz, IBatch k, const Coeffs &y, const double *ytab,
                     int64_t N, int64_t nbatch, IBatch overwrite) {
-  hipLaunchKernelGGL(k_lincomb, dim3(stream_blocks(N, 1), (unsigned)nbatch), dim3(kBlock), 0, s, x, Z, ldz, k, y, ytab,
+  hipLaunchKernelGGL(k_lincomb, dim3(stream_blocks(N, 4), (unsigned)nbatch), dim3(kBlock), 0, s, x, Z, ldz, k, y, ytab,
                      N, overwrite);
 }
 
-void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G, MBatch P) {
-  hipLaunchKernelGGL(k_residual, dim3(G, (unsigned)nbatch), dim3(kRed), 0, s, b, Ax, r, N, G, P);
+void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G, MBatch P,
+                     bool aligned16_all) {
+  if (N % 2 == 0 && aligned16_all)
+    hipLaunchKernelGGL(k_residual<true>, dim3(G, (unsigned)nbatch), dim3(kRed), 0, s, b, Ax, r, N, G, P);
+  else
+    hipLaunchKernelGGL(k_residual<false>, dim3(G, (unsigned)nbatch), dim3(kRed), 0, s, b, Ax, r, N, G, P);
 }
 
 }  // namespace fdg

@@ -94,7 +94,7 @@ struct fdg_server {
   char *arena = nullptr;
   size_t arena_bytes = 0;
   ArenaAlloc alloc;
-  double *pin = nullptr, *pin_dev = nullptr;  // host-mapped, max_slots * (m + 4)
+  double *pin = nullptr, *pin_dev = nullptr;  // host-mapped, max_slots * host_doubles(m)
   std::vector<Slot> slots;
   std::vector<int> free_slots;
   std::vector<Lane> lanes;
@@ -239,7 +239,7 @@ extern "C" int fdg_server_create(fdg_server **out, int max_slots, int restart, i
   s->arena_bytes = arena_bytes;
   if ((st = hip_check(hipMalloc((void **)&s->arena, arena_bytes), "server arena")) != FDG_OK) return fail(st);
   s->alloc.init(arena_bytes);
-  const size_t pin_bytes = sizeof(double) * (size_t)max_slots * (restart + 4);
+  const size_t pin_bytes = sizeof(double) * (size_t)max_slots * host_doubles(restart);
   if ((st = hip_check(hipHostMalloc((void **)&s->pin, pin_bytes, hipHostMallocMapped), "server pinned")) != FDG_OK)
     return fail(st);
   if ((st = hip_check(hipHostGetDevicePointer((void **)&s->pin_dev, s->pin, 0), "hipHostGetDevicePointer")) !=
@@ -294,8 +294,8 @@ extern "C" int fdg_server_admit(fdg_server *s, fdg_ctx *c, const double *b, doub
   sl.bytes = bytes;
   sl.tag = tag;
   RunBufs rb = carve_run(s->arena + off, c->N, s->m, lowp);
-  rb.hh = s->pin + (size_t)idx * (s->m + 4);
-  rb.hh_dev = s->pin_dev + (size_t)idx * (s->m + 4);
+  rb.hh = s->pin + (size_t)idx * host_doubles(s->m);
+  rb.hh_dev = s->pin_dev + (size_t)idx * host_doubles(s->m);
   sl.run.init(c, rb, s->m, b, x, rtol, maxit, flags);
   // lane: one already serving this context (shared launches), else the least loaded
   int lane = -1;

@@ -30,9 +30,15 @@ struct RunBufs {
   double *P3 = nullptr;                   // G partial sums
   double *Hcol = nullptr, *h1 = nullptr;  // m+2 each
   double *scal = nullptr;                 // 2: ||b||, residual norm
-  volatile double *hh = nullptr;          // host-mapped, m+4: column [0, m+2), ||b||, residual norm
+  volatile double *hh = nullptr;          // host-mapped, host_doubles(m): see below
   double *hh_dev = nullptr;               // device address of hh
 };
+
+// Host-mapped doubles of one solve: Hessenberg column [0, m+2), ||b|| at m+2, and from
+// m+4 the per-block partial sums of a squared norm (at most 256), which the host adds in
+// block order.
+constexpr int kHostPartials = 256;
+inline int host_doubles(int m) { return m + 4 + kHostPartials; }
 
 // Device bytes of RunBufs for an N-vector solve with restart m (each piece 256-aligned).
 size_t run_bytes(int64_t N, int m, bool lowp);
@@ -45,18 +51,19 @@ enum : unsigned {
   kStepBNorm = 1u << 1,    // |b| -> scal[0], hh[m+2]
   kStepBScale = 1u << 2,   // V0 = b / |b|; |b| -> scal[0], hh[m+2]
   kStepLincomb = 1u << 3,  // x = (x or 0) + Z y
-  kStepRes = 1u << 4,      // Z0 = A x; V0 = b - Z0; P3 = partials of |V0|^2
-  kStepRScale = 1u << 5,   // V0 /= |V0|; |V0| -> scal[1], hh[m+3]
-  kStepRNorm = 1u << 6,    // |V0| -> scal[1], hh[m+3]
-  kStepIter = 1u << 7,     // Z_j = P^-1 V_j; V_{j+1} = A Z_j; CGS2; column -> Hcol, hh
-  kStepZeroX = 1u << 8,    // x = 0
+  kStepRes = 1u << 4,      // Z0 = A x; V0 = b - Z0; partials of |V0|^2 -> hh[m+4 ..]
+  kStepScaleV = 1u << 5,   // V_j /= div (the norm the host formed from the partials)
+  kStepIter = 1u << 6,     // Z_j = P^-1 V_j; w = V_{j+1} = A Z_j; CGS2; column -> hh,
+                           // partials of |w|^2 -> hh[m+4 ..] (w is scaled by the next phase)
+  kStepZeroX = 1u << 7,    // x = 0
 };
 
 struct Phase {
   unsigned steps = 0;      // 0: the solve is finished
-  int j = 0;               // Arnoldi index of kStepIter
+  int j = 0;               // Arnoldi index of kStepIter / kStepScaleV
   int k = 0;               // coefficients of kStepLincomb
   bool overwrite = false;  // kStepLincomb starts from x = 0
+  double div = 1.0;        // divisor of kStepScaleV
 };
 
 class SolveRun {
@@ -85,6 +92,7 @@ class SolveRun {
 
  private:
   double &Hij(int i, int jj) { return H_[(size_t)i * m + jj]; }
+  double host_norm() const;  // sqrt of the block-ordered sum of the G partials in hh
   void finish(bool converged);
   void zero_then_finish(bool converged);
 

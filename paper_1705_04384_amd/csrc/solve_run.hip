@@ -84,8 +84,8 @@ void SolveRun::init(fdg_ctx *c, const RunBufs &bufs, int restart, const double *
   t0_ = std::chrono::steady_clock::now();
   ph_ = Phase{};
   if (x_nonzero_) {
-    // ||b||, then r = b - A x and v0 = r / ||r|| (||r|| decides whether to iterate)
-    ph_.steps = kStepBDots | kStepBNorm | kStepRes | kStepRScale;
+    // ||b||, then r = b - A x (||r|| decides whether to iterate)
+    ph_.steps = kStepBDots | kStepBNorm | kStepRes;
   } else if (limit_ == 0) {
     ph_.steps = kStepBDots | kStepBNorm;  // nothing to iterate: x = 0
   } else {
@@ -106,6 +106,12 @@ void SolveRun::finish(bool converged) {
   ph_ = Phase{};
 }
 
+double SolveRun::host_norm() const {
+  double sum = 0.0;
+  for (int g = 0; g < G; ++g) sum += buf.hh[m + 4 + g];
+  return std::sqrt(sum);
+}
+
 void SolveRun::zero_then_finish(bool converged) {
   pending_conv_ = converged;
   ph_ = Phase{};
@@ -123,15 +129,9 @@ void SolveRun::consume() {
     bnorm_ = buf.hh[m + 2];
     target_ = rtol_ * bnorm_;
   };
-  if (st & kStepRNorm) {  // final true residual
-    rbeta_ = buf.hh[m + 3];
-    info_.rel_res_true = rbeta_ / bnorm_;
-    finish(rbeta_ <= target_);
-    return;
-  }
-  if (st & kStepRScale) {  // start of a cycle from a nonzero x
+  if (st & kStepRes) {  // true residual r = b - A x in V0, its norm from the partials
     if (bnorm_ < 0.0) learn_bnorm();
-    const double beta = buf.hh[m + 3];
+    const double beta = host_norm();
     if (bnorm_ == 0.0) {  // b = 0: the solution is x = 0 exactly
       info_.rel_res_true = 0.0;
       last_est_ = 0.0;
@@ -144,11 +144,12 @@ void SolveRun::consume() {
       finish(rbeta_ <= target_);
       return;
     }
-    std::fill(g_.begin(), g_.end(), 0.0);
+    std::fill(g_.begin(), g_.end(), 0.0);  // next cycle from v0 = r / ||r||
     g_[0] = beta;
     ph_ = Phase{};
-    ph_.steps = kStepIter;
+    ph_.steps = kStepScaleV | kStepIter;
     ph_.j = 0;
+    ph_.div = beta;
     return;
   }
   if (!(st & kStepIter)) {  // ||b|| only (no iteration allowed, x = 0)
@@ -158,7 +159,7 @@ void SolveRun::consume() {
     zero_then_finish(bnorm_ == 0.0);
     return;
   }
-  // an Arnoldi step completed: Hessenberg column j in hh[0 .. j+1]
+  // an Arnoldi step completed: Hessenberg column j in hh[0 .. j], |w|^2 partials
   const int j = ph_.j;
   if (bnorm_ < 0.0) {
     learn_bnorm();
@@ -171,7 +172,8 @@ void SolveRun::consume() {
     }
   }
   const int nv = j + 1;
-  for (int q = 0; q <= nv; ++q) Hij(q, j) = buf.hh[q];
+  for (int q = 0; q < nv; ++q) Hij(q, j) = buf.hh[q];
+  Hij(nv, j) = host_norm();
   double wn0 = 0.0;
   for (int q = 0; q <= nv; ++q) wn0 += Hij(q, j) * Hij(q, j);
   wn0 = std::sqrt(wn0);
@@ -201,10 +203,11 @@ void SolveRun::consume() {
   breakdown_ = hn <= 1e-14 * wn0;
   const bool end_cycle =
       total_ >= limit_ || breakdown_ || j + 1 >= m || (!fixed_ && std::fabs(g_[j + 1]) <= target_);
-  if (!end_cycle) {
+  if (!end_cycle) {  // v_{j+1} = w / h_{j+1,j}, then the next Arnoldi step
     ph_ = Phase{};
-    ph_.steps = kStepIter;
+    ph_.steps = kStepScaleV | kStepIter;
     ph_.j = j + 1;
+    ph_.div = hn;
     return;
   }
   const int k = j + 1;
@@ -214,7 +217,7 @@ void SolveRun::consume() {
     y_.v[i] = s / Hij(i, i);
   }
   ph_ = Phase{};
-  ph_.steps = kStepLincomb | kStepRes | (total_ >= limit_ ? kStepRNorm : kStepRScale);
+  ph_.steps = kStepLincomb | kStepRes;
   ph_.k = k;
   ph_.overwrite = !x_nonzero_;
   x_nonzero_ = true;
@@ -278,6 +281,15 @@ struct Gather {
     for (int e = 0; e < n; ++e) hp[e] = f(*runs[e]);
     return IBatch{0, (const int32_t *)d};
   }
+  // Divisors of kStepScaleV, one per entry (several runs only).
+  const double *dtab() {
+    if (n == 1) return nullptr;
+    void *h, *d;
+    if (!tab->alloc(sizeof(double) * n, &h, &d)) { full = true; return nullptr; }
+    double *hp = (double *)h;
+    for (int e = 0; e < n; ++e) hp[e] = runs[e]->phase().div;
+    return (const double *)d;
+  }
   // Least-squares coefficients, 256 per entry (several runs only).
   const double *ytab() {
     if (n == 1) return nullptr;
@@ -320,13 +332,12 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
   const MBatch T2 = ga.m([](R r) { return r.buf.t2; });
   const MBatch P3 = ga.m([](R r) { return r.buf.P3; });
   const MBatch Sb = ga.m([](R r) { return r.buf.scal; });
-  const MBatch Sr = ga.m([](R r) { return r.buf.scal + 1; });
   const MBatch Hb = ga.m([m](R r) { return r.buf.hh_dev + m + 2; });
-  const MBatch Hr = ga.m([m](R r) { return r.buf.hh_dev + m + 3; });
-  MBatch X, Z0, Vj, Zj, Vj1, P1, P2, H1, Hc, Hh, Hcn, Hhn;
+  const MBatch Hp = ga.m([m](R r) { return r.buf.hh_dev + m + 4; });  // host-summed partials
+  MBatch X, Z0, Vj, Zj, Vj1, P1, P2, H1, Hc, Hh;
   CBatch Zb;
   IBatch K, OW, NV;
-  const double *ytab = nullptr;
+  const double *ytab = nullptr, *dtab = nullptr;
   if (steps & (kStepLincomb | kStepRes)) {
     X = ga.m([](R r) { return r.x; });
     Z0 = ga.m([](R r) { return r.buf.Z; });
@@ -337,8 +348,11 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
     OW = ga.i([](R r) { return r.phase().overwrite ? 1 : 0; });
     ytab = ga.ytab();
   }
-  if (steps & kStepIter) {
+  if (steps & (kStepIter | kStepScaleV)) {
     Vj = ga.m([](R r) { return r.buf.V + (size_t)r.phase().j * r.N; });
+  }
+  if (steps & kStepScaleV) dtab = ga.dtab();
+  if (steps & kStepIter) {
     Zj = ga.m([](R r) { return r.buf.Z + (size_t)r.phase().j * r.N; });
     Vj1 = ga.m([](R r) { return r.buf.V + (size_t)(r.phase().j + 1) * r.N; });
     NV = ga.i([](R r) { return r.phase().j + 1; });
@@ -347,8 +361,6 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
     H1 = ga.m([](R r) { return r.buf.h1; });
     Hc = ga.m([](R r) { return r.buf.Hcol; });
     Hh = ga.m([](R r) { return r.buf.hh_dev; });
-    Hcn = ga.m([](R r) { return r.buf.Hcol + r.phase().j + 1; });
-    Hhn = ga.m([](R r) { return r.buf.hh_dev + r.phase().j + 1; });
   }
   if (ga.full) return set_error(FDG_ENOMEM, "enqueue_phase: pointer-table arena full");
   if (nrun > 1) {
@@ -388,15 +400,11 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
   if (steps & kStepRes) {
     if ((st = matvec_entries(c, ex, as_const(X), Z0, nrun, T1, T2)) != FDG_OK) return st;
     TimedLaunch tl(c, 2, s, timed);
-    launch_residual(s, B, as_const(Z0), V0, N, nrun, G, P3);
+    launch_residual(s, B, as_const(Z0), V0, N, nrun, G, Hp, b16);
   }
-  if (steps & kStepRScale) {
+  if (steps & kStepScaleV) {  // v_j = w / ||w|| with the norm formed on the host
     TimedLaunch tl(c, 2, s, timed);
-    launch_scale_reduce(s, as_const(V0), V0, as_const(P3), G, N, nrun, Sr, Hr, true);
-  }
-  if (steps & kStepRNorm) {
-    TimedLaunch tl(c, 2, s, timed);
-    launch_norm_reduce(s, as_const(P3), G, nrun, Sr, Hr);
+    launch_scale_by(s, as_const(Vj), Vj, dtab, r0.phase().div, N, nrun, true);
   }
   if (steps & kStepIter) {
     if ((st = apply_entries(c, ex, as_const(Vj), Zj, nrun, T1, T2, r0.buf.t32a, r0.buf.t32b, a32)) != FDG_OK)
@@ -410,13 +418,9 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
       TimedLaunch tl(c, 2, s, timed);
       launch_update_dots(s, Vb, N, NV, as_const(P1), G, ldp, Vj1, N, nrun, P2, H1, true);
     }
-    {  // w -= V h2; Hessenberg column h1 + h2 (device and host-mapped); ||w||
+    {  // w -= V h2; Hessenberg column h1 + h2 (device and host-mapped); |w|^2 partials
       TimedLaunch tl(c, 2, s, timed);
-      launch_update_norm(s, Vb, N, NV, as_const(P2), G, ldp, Vj1, N, nrun, P3, as_const(H1), Hc, Hh, true);
-    }
-    {  // h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}
-      TimedLaunch tl(c, 2, s, timed);
-      launch_scale_reduce(s, as_const(Vj1), Vj1, as_const(P3), G, N, nrun, Hcn, Hhn, true);
+      launch_update_norm(s, Vb, N, NV, as_const(P2), G, ldp, Vj1, N, nrun, Hp, as_const(H1), Hc, Hh, true);
     }
   }
   return hip_check(hipGetLastError(), "solve phase launch");
