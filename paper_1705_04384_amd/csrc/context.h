@@ -53,6 +53,7 @@ struct fdg_ctx {
          *hbuf = nullptr, *scal = nullptr;
   double *hpin = nullptr;      // pinned, device-mapped host memory for the scalars the host needs
   double *hpin_dev = nullptr;  // its device address
+  hipEvent_t phase_ev = nullptr;  // end of a solve phase, polled by the host
   fdg::TimerState timers[fdg::kTimerClasses];
 };
 
@@ -129,6 +130,10 @@ int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nen
                   void *t32a, void *t32b, bool gathered_aligned32);
 // y = A x for nent batch entries, scratch t1, t2 as for apply_entries.
 int matvec_entries(fdg_ctx *c, const Exec &ex, CBatch x, MBatch y, int64_t nent, MBatch t1, MBatch t2);
+// r = b - A x with one partial sum of |r|^2 per workgroup written to part.at(e)[g],
+// g < residual_partials(c); only for contexts where residual_partials(c) > 0.
+int residual_entries(fdg_ctx *c, const Exec &ex, CBatch x, CBatch b, MBatch r, int64_t nent, MBatch part);
+int residual_partials(const fdg_ctx *c);
 // FDG_OK when the preconditioner factors and the operator are set, else FDG_ENOTREADY.
 int ctx_ready(fdg_ctx *c);
 // The context's apply and matvec accept gathered batches (FP64 fused FD passes and a

@@ -191,6 +191,18 @@ int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nen
   return hip_check(hipGetLastError(), "apply_prec launch");
 }
 
+int residual_partials(const fdg_ctx *c) {
+  if (c->op_kind != 1) return 0;
+  return kron_residual_partials(c->d, c->n, ctx_bands(c));
+}
+
+int residual_entries(fdg_ctx *c, const Exec &ex, CBatch x, CBatch b, MBatch r, int64_t nent, MBatch part) {
+  TimedLaunch tl(c, 1, ex.stream, ex.timed);
+  if (c->op_kind != 1 || !launch_kron_residual_f64(ex.stream, x, b, r, c->d, c->n, nent, ctx_bands(c), part))
+    return set_error(FDG_EINVAL, "residual: the fused form does not apply to this operator");
+  return hip_check(hipGetLastError(), "residual launch");
+}
+
 int matvec_entries(fdg_ctx *c, const Exec &ex, CBatch x, MBatch y, int64_t nent, MBatch t1, MBatch t2) {
   TimedLaunch tl(c, 1, ex.stream, ex.timed);
   if (c->op_kind == 2) {
@@ -299,6 +311,7 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
   dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol);
   dfree(c->hbuf); dfree(c->scal);
   if (c->hpin) (void)hipHostFree(c->hpin);
+  if (c->phase_ev) (void)hipEventDestroy(c->phase_ev);
   for (auto &t : c->timers) {
     for (auto e : t.pool) (void)hipEventDestroy(e);
     for (auto e : t.pending) (void)hipEventDestroy(e);
@@ -521,13 +534,21 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   rb.scal = c->scal;
   rb.hh = c->hpin;
   rb.hh_dev = c->hpin_dev;
+  if (!c->phase_ev) HIPCHK(hipEventCreateWithFlags(&c->phase_ev, hipEventDisableTiming));
   SolveRun run;
   run.init(c, rb, restart, b, x, rtol, maxit, flags);
   SolveRun *rp = &run;
   const Exec ex{c->stream, true};
   while (!run.finished()) {
     if ((st = enqueue_phase(ex, &rp, 1, nullptr)) != FDG_OK) return st;
-    HIPCHK(hipStreamSynchronize(c->stream));
+    // wait for the phase by polling its event: the host sees the results as soon as
+    // the last kernel ends, without a blocking wake-up
+    HIPCHK(hipEventRecord(c->phase_ev, c->stream));
+    hipError_t e;
+    while ((e = hipEventQuery(c->phase_ev)) == hipErrorNotReady) {
+    }
+    (void)hipGetLastError();
+    HIPCHK(e);
     run.consume();
   }
   if (info) *info = run.info();

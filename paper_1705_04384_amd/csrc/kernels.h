@@ -47,6 +47,13 @@ int kron_window_max();
 // The 3D matvec of nbatch entries can take the two-pass form (which accepts gathered
 // batches); always true in 2D.
 bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bands);
+// r = b - A x with the one-pass 3D form, and one partial sum of |r|^2 per workgroup at
+// part.at(e)[g], g < kron_residual_partials(d, n, bands) (block order).  Returns false
+// (nothing launched) when that form does not apply.
+bool launch_kron_residual_f64(hipStream_t s, CBatch x, CBatch rhs, MBatch r, int d, int n, int64_t nbatch,
+                              const KronBands &bands, MBatch part);
+// Number of partials launch_kron_residual_f64 writes per entry, 0 if it does not apply.
+int kron_residual_partials(int d, int n, const KronBands &bands);
 // The one-pass 3D form applies (band width <= 8, band starts growing by <= 1 per row in
 // directions 1 and 2); it needs no scratch and accepts gathered batches.
 bool kron_fused_ok(int n, int64_t nbatch, const KronBands &bands);

@@ -453,9 +453,10 @@ __global__ __launch_bounds__(kBlock) void k_ell_f64(CBatch x, MBatch y, int64_t 
 // stores a and c of its T2 x 64 tile to LDS.  After one barrier every wave forms outputs
 // y = sum K3 a + M3 c over the direction-3 band.  Two workgroup barriers in all.
 // Requires band starts that grow by at most 1 per row in directions 1 and 2.
-template <int WMAX, int T2, int C3>
+// RES: store r = b - A x instead of A x, and one partial of |r|^2 per workgroup.
+template <int WMAX, int T2, int C3, bool RES>
 __global__ __launch_bounds__(512) void k_kron3_wpp(CBatch x, MBatch y, int n, int ntx, int nty, int nchunk,
-                                                   KronBands bd) {
+                                                   KronBands bd, CBatch rhs, MBatch part) {
   constexpr int NWV = 8;
   constexpr int RMAX = T2 + WMAX - 1;    // rows j2 a tile may need
   constexpr int CW = 64 + WMAX;          // staged columns j1 per row
@@ -578,20 +579,42 @@ __global__ __launch_bounds__(512) void k_kron3_wpp(CBatch x, MBatch y, int n, in
     }
   }
   __syncthreads();
-  if (!act1) return;
-  for (int idx = wave; idx < C3 * T2; idx += NWV) {
-    const int q = idx / T2, u = idx - q * T2;
-    const int i2 = i2a + u;
-    if (s3 + q >= e3 || i2 > i2b) continue;
-    const int b3 = lo3s[q] - P0;
-    double acc = 0.0;
+  double rr = 0.0;  // RES: this thread's part of |b - A x|^2
+  if (act1) {
+    const double *rb = RES ? rhs.at(ent) : nullptr;
+    for (int idx = wave; idx < C3 * T2; idx += NWV) {
+      const int q = idx / T2, u = idx - q * T2;
+      const int i2 = i2a + u;
+      if (s3 + q >= e3 || i2 > i2b) continue;
+      const int b3 = lo3s[q] - P0;
+      double acc = 0.0;
 #pragma unroll
-    for (int tt = 0; tt < WMAX; ++tt)
-      if (tt < w3) {
-        acc = fma(c3k[q][tt], As[b3 + tt][u][lane], acc);
-        acc = fma(c3m[q][tt], Cs[b3 + tt][u][lane], acc);
+      for (int tt = 0; tt < WMAX; ++tt)
+        if (tt < w3) {
+          acc = fma(c3k[q][tt], As[b3 + tt][u][lane], acc);
+          acc = fma(c3m[q][tt], Cs[b3 + tt][u][lane], acc);
+        }
+      const int64_t o = (int64_t)(s3 + q) * n2 + (int64_t)i2 * n + i1;
+      if (RES) {
+        const double r = rb[o] - acc;
+        yb[o] = r;
+        rr = fma(r, r, rr);
+      } else {
+        yb[o] = acc;
       }
-    yb[(int64_t)(s3 + q) * n2 + (int64_t)i2 * n + i1] = acc;
+    }
+  }
+  if (RES) {  // one partial per workgroup, waves in index order
+    __shared__ double red[NWV];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) rr += __shfl_xor(rr, off, 64);
+    if (lane == 0) red[wave] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = red[0];
+      for (int k = 1; k < NWV; ++k) sum += red[k];
+      part.at(ent)[t - ent * (int64_t)ntx * nty * nchunk] = sum;
+    }
   }
 }
 
@@ -615,21 +638,51 @@ bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bd) {
   return bd.rows16 <= kPlaneRowsMax && bd.step3 <= 1 && w <= 8 && (int64_t)n * nbatch <= 65535;
 }
 
+namespace {
+
+constexpr int kWppT2 = FDG_MV_T2, kWppC3 = FDG_MV_C3;
+
+int64_t wpp_tiles(int n) { return (int64_t)cdiv(n, 64) * cdiv(n, kWppT2) * cdiv(n, kWppC3); }
+
+template <bool RES>
+void launch_wpp(hipStream_t s, CBatch x, MBatch y, int n, int64_t nbatch, const KronBands &bd, CBatch rhs,
+                MBatch part) {
+  int w = 0;
+  for (int l = 0; l < 3; ++l) w = bd.w[l] > w ? bd.w[l] : w;
+  const int ntx = (int)cdiv(n, 64), nty = (int)cdiv(n, kWppT2), nchunk = (int)cdiv(n, kWppC3);
+  const dim3 grid((unsigned)((int64_t)ntx * nty * nchunk * nbatch));
+  if (w <= 4)
+    hipLaunchKernelGGL((k_kron3_wpp<4, kWppT2, kWppC3, RES>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd,
+                       rhs, part);
+  else if (w <= 6)
+    hipLaunchKernelGGL((k_kron3_wpp<6, kWppT2, kWppC3, RES>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd,
+                       rhs, part);
+  else
+    hipLaunchKernelGGL((k_kron3_wpp<8, kWppT2, kWppC3, RES>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd,
+                       rhs, part);
+}
+
+}  // namespace
+
+int kron_residual_partials(int d, int n, const KronBands &bd) {
+  if (d != 3 || !kron_fused_ok(n, 1, bd)) return 0;
+  return (int)wpp_tiles(n);
+}
+
+bool launch_kron_residual_f64(hipStream_t s, CBatch x, CBatch rhs, MBatch r, int d, int n, int64_t nbatch,
+                              const KronBands &bd, MBatch part) {
+  if (d != 3 || !kron_fused_ok(n, nbatch, bd)) return false;
+  launch_wpp<true>(s, x, r, n, nbatch, bd, rhs, part);
+  return true;
+}
+
 bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int64_t nbatch, const KronBands &bd,
                             MBatch tmp_a, MBatch tmp_c) {
   int w = 0;
   for (int l = 0; l < d; ++l) w = bd.w[l] > w ? bd.w[l] : w;
   const dim3 blk(kBlock);
   if (d == 3 && kron_fused_ok(n, nbatch, bd)) {
-    constexpr int T2 = FDG_MV_T2, C3 = FDG_MV_C3;
-    const int ntx = (int)cdiv(n, 64), nty = (int)cdiv(n, T2), nchunk = (int)cdiv(n, C3);
-    const dim3 grid((unsigned)((int64_t)ntx * nty * nchunk * nbatch));
-    if (w <= 4)
-      hipLaunchKernelGGL((k_kron3_wpp<4, T2, C3>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd);
-    else if (w <= 6)
-      hipLaunchKernelGGL((k_kron3_wpp<6, T2, C3>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd);
-    else
-      hipLaunchKernelGGL((k_kron3_wpp<8, T2, C3>), grid, dim3(512), 0, s, x, y, n, ntx, nty, nchunk, bd);
+    launch_wpp<false>(s, x, y, n, nbatch, bd, CBatch{}, MBatch{});
     return true;
   }
   if (d == 3) {

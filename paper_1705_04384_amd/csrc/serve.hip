@@ -266,7 +266,7 @@ extern "C" int fdg_server_create(fdg_server **out, int max_slots, int restart, i
 
 extern "C" size_t fdg_server_run_bytes(const fdg_ctx *c, int restart) {
   if (!c || restart < 1) return 0;
-  return run_bytes(c->N, restart, c->prec != FDG_PREC_FP64);
+  return run_bytes(c, restart);
 }
 
 extern "C" int fdg_server_admit(fdg_server *s, fdg_ctx *c, const double *b, double *x, double rtol, int maxit,
@@ -280,8 +280,7 @@ extern "C" int fdg_server_admit(fdg_server *s, fdg_ctx *c, const double *b, doub
   int st = ctx_ready(c);
   if (st != FDG_OK) return st;
   if (s->free_slots.empty()) return set_error(FDG_EFULL, "server_admit: all %d slots in use", s->max_slots);
-  const bool lowp = c->prec != FDG_PREC_FP64;
-  const size_t bytes = run_bytes(c->N, s->m, lowp);
+  const size_t bytes = run_bytes(c, s->m);
   size_t off = 0;
   if (!s->alloc.alloc(bytes, &off))
     return set_error(FDG_EFULL, "server_admit: %zu arena bytes not available", bytes);
@@ -293,7 +292,7 @@ extern "C" int fdg_server_admit(fdg_server *s, fdg_ctx *c, const double *b, doub
   sl.off = off;
   sl.bytes = bytes;
   sl.tag = tag;
-  RunBufs rb = carve_run(s->arena + off, c->N, s->m, lowp);
+  RunBufs rb = carve_run(s->arena + off, c, s->m);
   rb.hh = s->pin + (size_t)idx * host_doubles(s->m);
   rb.hh_dev = s->pin_dev + (size_t)idx * host_doubles(s->m);
   sl.run.init(c, rb, s->m, b, x, rtol, maxit, flags);

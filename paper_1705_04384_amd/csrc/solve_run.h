@@ -35,15 +35,15 @@ struct RunBufs {
 };
 
 // Host-mapped doubles of one solve: Hessenberg column [0, m+2), ||b|| at m+2, and from
-// m+4 the per-block partial sums of a squared norm (at most 256), which the host adds in
-// block order.
-constexpr int kHostPartials = 256;
+// m+4 the per-block partial sums of a squared norm (at most kHostPartials), which the
+// host adds in block order.
+constexpr int kHostPartials = 4096;
 inline int host_doubles(int m) { return m + 4 + kHostPartials; }
 
-// Device bytes of RunBufs for an N-vector solve with restart m (each piece 256-aligned).
-size_t run_bytes(int64_t N, int m, bool lowp);
+// Device bytes of RunBufs for a solve on c with restart m (each piece 256-aligned).
+size_t run_bytes(const fdg_ctx *c, int m);
 // Carves RunBufs out of [base, base + run_bytes(...)); hh / hh_dev are set by the caller.
-RunBufs carve_run(char *base, int64_t N, int m, bool lowp);
+RunBufs carve_run(char *base, const fdg_ctx *c, int m);
 
 // Steps of a phase, executed in this order.
 enum : unsigned {
@@ -51,7 +51,7 @@ enum : unsigned {
   kStepBNorm = 1u << 1,    // |b| -> scal[0], hh[m+2]
   kStepBScale = 1u << 2,   // V0 = b / |b|; |b| -> scal[0], hh[m+2]
   kStepLincomb = 1u << 3,  // x = (x or 0) + Z y
-  kStepRes = 1u << 4,      // Z0 = A x; V0 = b - Z0; partials of |V0|^2 -> hh[m+4 ..]
+  kStepRes = 1u << 4,      // V0 = b - A x (via Z0 unless fused); |V0|^2 partials -> hh[m+4 ..]
   kStepScaleV = 1u << 5,   // V_j /= div (the norm the host formed from the partials)
   kStepIter = 1u << 6,     // Z_j = P^-1 V_j; w = V_{j+1} = A Z_j; CGS2; column -> hh,
                            // partials of |w|^2 -> hh[m+4 ..] (w is scaled by the next phase)
@@ -87,12 +87,13 @@ class SolveRun {
   int m = 0;
   int64_t N = 0;
   int G = 0;
+  int res_parts = 0;  // partials of the fused residual matvec, 0 if it does not apply
   const double *b = nullptr;
   double *x = nullptr;
 
  private:
   double &Hij(int i, int jj) { return H_[(size_t)i * m + jj]; }
-  double host_norm() const;  // sqrt of the block-ordered sum of the G partials in hh
+  double host_norm(int count) const;  // sqrt of the block-ordered sum of count partials in hh
   void finish(bool converged);
   void zero_then_finish(bool converged);
 

@@ -16,7 +16,9 @@ inline bool al(const void *p, int bytes) { return (reinterpret_cast<uintptr_t>(p
 
 }  // namespace
 
-size_t run_bytes(int64_t N, int m, bool lowp) {
+size_t run_bytes(const fdg_ctx *c, int m) {
+  const int64_t N = c->N;
+  const bool lowp = c->prec != FDG_PREC_FP64;
   const size_t n8 = (size_t)N * 8;
   const int G = reduction_blocks(N);
   size_t s = up256(n8 * (m + 1)) + up256(n8 * m) + 2 * up256(n8);
@@ -26,7 +28,9 @@ size_t run_bytes(int64_t N, int m, bool lowp) {
   return s;
 }
 
-RunBufs carve_run(char *base, int64_t N, int m, bool lowp) {
+RunBufs carve_run(char *base, const fdg_ctx *c, int m) {
+  const int64_t N = c->N;
+  const bool lowp = c->prec != FDG_PREC_FP64;
   const size_t n8 = (size_t)N * 8;
   const int G = reduction_blocks(N);
   RunBufs r;
@@ -63,6 +67,8 @@ void SolveRun::init(fdg_ctx *c, const RunBufs &bufs, int restart, const double *
   m = restart;
   N = c->N;
   G = reduction_blocks(N);
+  res_parts = residual_partials(c);
+  if (res_parts > kHostPartials) res_parts = 0;
   b = bv;
   x = xv;
   rtol_ = rtol;
@@ -106,9 +112,9 @@ void SolveRun::finish(bool converged) {
   ph_ = Phase{};
 }
 
-double SolveRun::host_norm() const {
+double SolveRun::host_norm(int count) const {
   double sum = 0.0;
-  for (int g = 0; g < G; ++g) sum += buf.hh[m + 4 + g];
+  for (int g = 0; g < count; ++g) sum += buf.hh[m + 4 + g];
   return std::sqrt(sum);
 }
 
@@ -131,7 +137,7 @@ void SolveRun::consume() {
   };
   if (st & kStepRes) {  // true residual r = b - A x in V0, its norm from the partials
     if (bnorm_ < 0.0) learn_bnorm();
-    const double beta = host_norm();
+    const double beta = host_norm(res_parts > 0 ? res_parts : G);
     if (bnorm_ == 0.0) {  // b = 0: the solution is x = 0 exactly
       info_.rel_res_true = 0.0;
       last_est_ = 0.0;
@@ -173,7 +179,7 @@ void SolveRun::consume() {
   }
   const int nv = j + 1;
   for (int q = 0; q < nv; ++q) Hij(q, j) = buf.hh[q];
-  Hij(nv, j) = host_norm();
+  Hij(nv, j) = host_norm(G);
   double wn0 = 0.0;
   for (int q = 0; q <= nv; ++q) wn0 += Hij(q, j) * Hij(q, j);
   wn0 = std::sqrt(wn0);
@@ -398,9 +404,13 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
     launch_lincomb(s, X, Zb, N, K, r0.coeffs(), ytab, N, nrun, OW);
   }
   if (steps & kStepRes) {
-    if ((st = matvec_entries(c, ex, as_const(X), Z0, nrun, T1, T2)) != FDG_OK) return st;
-    TimedLaunch tl(c, 2, s, timed);
-    launch_residual(s, B, as_const(Z0), V0, N, nrun, G, Hp, b16);
+    if (r0.res_parts > 0) {  // r = b - A x fused into the matvec
+      if ((st = residual_entries(c, ex, as_const(X), B, V0, nrun, Hp)) != FDG_OK) return st;
+    } else {
+      if ((st = matvec_entries(c, ex, as_const(X), Z0, nrun, T1, T2)) != FDG_OK) return st;
+      TimedLaunch tl(c, 2, s, timed);
+      launch_residual(s, B, as_const(Z0), V0, N, nrun, G, Hp, b16);
+    }
   }
   if (steps & kStepScaleV) {  // v_j = w / ||w|| with the norm formed on the host
     TimedLaunch tl(c, 2, s, timed);
