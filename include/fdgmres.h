@@ -135,6 +135,25 @@ int fdg_set_operator_kron(fdg_ctx *ctx, int l, const double *M, const double *K)
 int fdg_set_operator_csr(fdg_ctx *ctx, int64_t nrows, int64_t nnz, const int64_t *rowptr,
                          const int32_t *col, const double *val);
 
+/* Operator A of a mapped 3D domain applied matrix-free (the collocation matrix of
+ * Sec. 2.2 on F([0,1]^3), K = I, never assembled):
+ *   (A x)_i = -sum_k C_kk (d_k^2 u)(tau_i) - sum_{k<l} 2 C_kl (d_k d_l u)(tau_i)
+ *             - sum_k g_k (d_k u)(tau_i),       u = sum_j x_j B_j,
+ * with C = J^{-1} J^{-T}, g = -J^{-1} sum_lm (d_l d_m F) C_lm at the collocation points.
+ * The derivatives come from the univariate factors by sum factorization:
+ * fdg_set_operator_mapped gives direction l's M_l (values), D_l (first derivatives) and
+ * K_l (minus second derivatives) at the collocation points (host n*n row-major, banded,
+ * band width <= 8); fdg_set_operator_fields gives the 9 coefficient fields, host
+ * coef[f*N + i], f = 0..8: C_11, C_22, C_33, 2 C_12, 2 C_13, 2 C_23, g_1, g_2, g_3.
+ * Both are copied to the device; the context then reads 9 N + 2 N doubles per matvec
+ * instead of an assembled matrix. */
+int fdg_set_operator_mapped(fdg_ctx *ctx, int l, const double *M, const double *D, const double *K);
+int fdg_set_operator_fields(fdg_ctx *ctx, const double *coef);
+
+/* The 9 coefficient fields above for the deformed cube of fdg_deformed_csr (degree p,
+ * n unknowns per direction, amplitude amp): host coef[9 * n^3]. */
+int fdg_deformed_coefficients(int p, int n, double amp, double *coef);
+
 /* s = P^{-1} b (eq. 4.7 / 4.9) for every batch entry.  b, s: device, batch*N FP64. */
 int fdg_apply_prec(fdg_ctx *ctx, const double *b, double *s);
 

@@ -36,9 +36,12 @@ struct fdg_ctx {
   float *lam32[3] = {nullptr, nullptr, nullptr};
   double lam_min[3] = {0, 0, 0};
   // operator
-  int op_kind = 0;  // 0 none, 1 Kronecker bands, 2 ELL
+  int op_kind = 0;  // 0 none, 1 Kronecker bands, 2 ELL, 3 mapped (matrix-free)
   bool have_op[3] = {false, false, false};
   double *bandM[3] = {nullptr, nullptr, nullptr}, *bandK[3] = {nullptr, nullptr, nullptr};
+  double *bandD[3] = {nullptr, nullptr, nullptr};  // first-derivative bands (mapped operator)
+  double *fields = nullptr;                        // 9 N coefficient fields (mapped operator)
+  bool have_fields = false;
   int32_t *bandlo[3] = {nullptr, nullptr, nullptr};
   int bandw[3] = {0, 0, 0};
   int bandrows4[3] = {0, 0, 0}, bandrows16[3] = {0, 0, 0}, bandstep[3] = {0, 0, 0};

@@ -12,6 +12,7 @@
 #include "common.h"
 #include "context.h"
 #include "fd_apply.h"
+#include "mapped.h"
 #include "kernels.h"
 #include "modeprod.h"
 #include "solve_run.h"
@@ -64,6 +65,12 @@ int check_ready_op(fdg_ctx *c) {
     return FDG_OK;
   }
   if (c->op_kind == 2) return FDG_OK;
+  if (c->op_kind == 3) {
+    for (int l = 0; l < 3; ++l)
+      if (!c->have_op[l]) return set_error(FDG_ENOTREADY, "mapped operator factors of direction %d not set", l);
+    if (!c->have_fields) return set_error(FDG_ENOTREADY, "mapped operator coefficient fields not set");
+    return FDG_OK;
+  }
   return set_error(FDG_ENOTREADY, "operator not set");
 }
 
@@ -97,9 +104,27 @@ KronBands ctx_bands(const fdg_ctx *c) {
 }
 }  // namespace
 
+namespace {
+MappedOp ctx_mapped(const fdg_ctx *c) {
+  MappedOp op;
+  for (int l = 0; l < 3; ++l) {
+    op.M[l] = c->bandM[l];
+    op.D[l] = c->bandD[l];
+    op.K[l] = c->bandK[l];
+    op.lo[l] = c->bandlo[l];
+    op.w[l] = c->bandw[l];
+    op.step[l] = c->bandstep[l];
+  }
+  op.coef = c->fields;
+  op.N = c->N;
+  return op;
+}
+}  // namespace
+
 bool groupable(const fdg_ctx *c) {
   if (c->prec != FDG_PREC_FP64 || !fd_fused_supported(c->n)) return false;
   if (c->op_kind == 2 || c->d == 2) return true;
+  if (c->op_kind == 3) return mapped_matvec_ok(c->n, kMaxGroupEntries, ctx_mapped(c));
   int w = 0;
   for (int l = 0; l < c->d; ++l) w = std::max(w, c->bandw[l]);
   KronBands bd = ctx_bands(c);
@@ -209,6 +234,11 @@ int matvec_entries(fdg_ctx *c, const Exec &ex, CBatch x, MBatch y, int64_t nent,
     launch_ell_matvec_f64(ex.stream, x, y, c->N, c->N, c->ell_width, c->ell_col, c->ell_val, nent);
     return hip_check(hipGetLastError(), "matvec launch");
   }
+  if (c->op_kind == 3) {
+    if (!launch_mapped_matvec_f64(ex.stream, x, y, c->n, nent, ctx_mapped(c)))
+      return set_error(FDG_EINVAL, "matvec: mapped operator bands wider than 8 or growing by more than 1 per row");
+    return hip_check(hipGetLastError(), "matvec launch");
+  }
   const KronBands bd = ctx_bands(c);
   if (!launch_kron_matvec_f64(ex.stream, x, y, c->d, c->n, nent, bd, t1, t2))
     return set_error(FDG_EINVAL, "matvec: this operator shape needs a contiguous batch");
@@ -302,8 +332,9 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
   for (int l = 0; l < 3; ++l) {
     dfree(c->Wv[l]); dfree(c->Wu[l]); dfree(c->lam[l]);
     dfree(c->Wv32[l]); dfree(c->Wu32[l]); dfree(c->Wv16[l]); dfree(c->Wu16[l]); dfree(c->lam32[l]);
-    dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandlo[l]);
+    dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandD[l]); dfree(c->bandlo[l]);
   }
+  dfree(c->fields);
   dfree(c->ell_col); dfree(c->ell_val);
   dfree(c->t1); dfree(c->t2);
   if (c->t32a) (void)hipFree(c->t32a);
@@ -387,46 +418,49 @@ extern "C" int fdg_set_precision(fdg_ctx *c, int prec) {
   return FDG_OK;
 }
 
-extern "C" int fdg_set_operator_kron(fdg_ctx *c, int l, const double *M, const double *K) {
-  clear_error();
-  if (!c || !M || !K) return set_error(FDG_EINVAL, "set_operator_kron: NULL argument");
-  if (l < 0 || l >= c->d) return set_error(FDG_EINVAL, "set_operator_kron: bad direction %d", l);
-  if (c->op_kind == 2) return set_error(FDG_EINVAL, "set_operator_kron: context already has a CSR operator");
+namespace {
+
+// Row bands of the univariate factors F[0..nf) of direction l (union of their non-zero
+// patterns, one window [lo_i, lo_i + w) per row, non-decreasing lo) uploaded to the
+// device as bandM, bandK (and bandD for three factors).
+int store_bands(fdg_ctx *c, int l, const double *const *F, int nf, const char *who) {
   const int n = c->n;
-  if (!finite_all(M, (size_t)n * n) || !finite_all(K, (size_t)n * n))
-    return set_error(FDG_EINVAL, "set_operator_kron: non-finite factor");
+  for (int f = 0; f < nf; ++f)
+    if (!finite_all(F[f], (size_t)n * n)) return set_error(FDG_EINVAL, "%s: non-finite factor", who);
   std::vector<int> lo(n), hi(n);
   int w = 1;
   for (int i = 0; i < n; ++i) {
     int a = n, b = -1;
-    for (int j = 0; j < n; ++j)
-      if (M[(size_t)i * n + j] != 0.0 || K[(size_t)i * n + j] != 0.0) { a = std::min(a, j); b = std::max(b, j); }
+    for (int j = 0; j < n; ++j) {
+      bool nz = false;
+      for (int f = 0; f < nf; ++f) nz = nz || F[f][(size_t)i * n + j] != 0.0;
+      if (nz) { a = std::min(a, j); b = std::max(b, j); }
+    }
     if (b < 0) { a = 0; b = 0; }
     lo[i] = a;
     hi[i] = b;
     w = std::max(w, b - a + 1);
   }
   for (int i = 1; i < n; ++i)
-    if (lo[i] < lo[i - 1])
-      return set_error(FDG_EINVAL, "set_operator_kron: band starts must not decrease (row %d)", i);
-  if (w > kron_window_max()) return set_error(FDG_EINVAL, "set_operator_kron: band wider than %d", kron_window_max());
-  std::vector<double> bm((size_t)n * w, 0.0), bk((size_t)n * w, 0.0);
+    if (lo[i] < lo[i - 1]) return set_error(FDG_EINVAL, "%s: band starts must not decrease (row %d)", who, i);
+  if (w > kron_window_max()) return set_error(FDG_EINVAL, "%s: band wider than %d", who, kron_window_max());
+  std::vector<double> band[3];
+  for (int f = 0; f < nf; ++f) band[f].assign((size_t)n * w, 0.0);
   std::vector<int32_t> blo(n);
   for (int i = 0; i < n; ++i) {
     const int s = std::min(lo[i], n - w);  // window [s, s+w) covers [lo, hi] and stays inside
     blo[i] = s;
-    for (int t = 0; t < w; ++t) {
-      bm[(size_t)i * w + t] = M[(size_t)i * n + s + t];
-      bk[(size_t)i * w + t] = K[(size_t)i * n + s + t];
-    }
+    for (int f = 0; f < nf; ++f)
+      for (int t = 0; t < w; ++t) band[f][(size_t)i * w + t] = F[f][(size_t)i * n + s + t];
   }
-  dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandlo[l]);
+  double **dst[3] = {&c->bandM[l], &c->bandK[l], &c->bandD[l]};
+  dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandD[l]); dfree(c->bandlo[l]);
   int st;
-  if ((st = dalloc(&c->bandM[l], bm.size())) != FDG_OK) return st;
-  if ((st = dalloc(&c->bandK[l], bk.size())) != FDG_OK) return st;
+  for (int f = 0; f < nf; ++f) {
+    if ((st = dalloc(dst[f], band[f].size())) != FDG_OK) return st;
+    HIPCHK(hipMemcpy(*dst[f], band[f].data(), band[f].size() * 8, hipMemcpyHostToDevice));
+  }
   if ((st = dalloc(&c->bandlo[l], blo.size())) != FDG_OK) return st;
-  HIPCHK(hipMemcpy(c->bandM[l], bm.data(), bm.size() * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->bandK[l], bk.data(), bk.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->bandlo[l], blo.data(), blo.size() * 4, hipMemcpyHostToDevice));
   c->bandw[l] = w;
   int rows4 = 0;
@@ -438,7 +472,51 @@ extern "C" int fdg_set_operator_kron(fdg_ctx *c, int l, const double *M, const d
   c->bandrows16[l] = rows16;
   c->bandstep[l] = step;
   c->have_op[l] = true;
+  return FDG_OK;
+}
+
+}  // namespace
+
+extern "C" int fdg_set_operator_kron(fdg_ctx *c, int l, const double *M, const double *K) {
+  clear_error();
+  if (!c || !M || !K) return set_error(FDG_EINVAL, "set_operator_kron: NULL argument");
+  if (l < 0 || l >= c->d) return set_error(FDG_EINVAL, "set_operator_kron: bad direction %d", l);
+  if (c->op_kind == 2 || c->op_kind == 3)
+    return set_error(FDG_EINVAL, "set_operator_kron: context already has another operator");
+  const double *F[2] = {M, K};
+  const int st = store_bands(c, l, F, 2, "set_operator_kron");
+  if (st != FDG_OK) return st;
   c->op_kind = 1;
+  return FDG_OK;
+}
+
+extern "C" int fdg_set_operator_mapped(fdg_ctx *c, int l, const double *M, const double *D, const double *K) {
+  clear_error();
+  if (!c || !M || !D || !K) return set_error(FDG_EINVAL, "set_operator_mapped: NULL argument");
+  if (c->d != 3) return set_error(FDG_EINVAL, "set_operator_mapped: 3D contexts only");
+  if (l < 0 || l >= 3) return set_error(FDG_EINVAL, "set_operator_mapped: bad direction %d", l);
+  if (c->op_kind == 1 || c->op_kind == 2)
+    return set_error(FDG_EINVAL, "set_operator_mapped: context already has another operator");
+  const double *F[3] = {M, K, D};
+  const int st = store_bands(c, l, F, 3, "set_operator_mapped");
+  if (st != FDG_OK) return st;
+  c->op_kind = 3;
+  return FDG_OK;
+}
+
+extern "C" int fdg_set_operator_fields(fdg_ctx *c, const double *coef) {
+  clear_error();
+  if (!c || !coef) return set_error(FDG_EINVAL, "set_operator_fields: NULL argument");
+  if (c->d != 3) return set_error(FDG_EINVAL, "set_operator_fields: 3D contexts only");
+  if (c->op_kind == 1 || c->op_kind == 2)
+    return set_error(FDG_EINVAL, "set_operator_fields: context already has another operator");
+  const size_t cnt = (size_t)9 * c->N;
+  if (!finite_all(coef, cnt)) return set_error(FDG_EINVAL, "set_operator_fields: non-finite coefficient");
+  int st;
+  if ((st = dalloc(&c->fields, cnt)) != FDG_OK) return st;
+  HIPCHK(hipMemcpy(c->fields, coef, cnt * 8, hipMemcpyHostToDevice));
+  c->have_fields = true;
+  c->op_kind = 3;
   return FDG_OK;
 }
 

@@ -303,3 +303,31 @@ extern "C" int fdg_deformed_csr(int p, int n, double amp, int band, int64_t *nnz
   (void)N;
   return FDG_OK;
 }
+
+extern "C" int fdg_deformed_coefficients(int p, int n, double amp, double *coef) {
+  clear_error();
+  if (!coef) return set_error(FDG_EINVAL, "deformed_coefficients: coef is NULL");
+  if (!std::isfinite(amp)) return set_error(FDG_EINVAL, "deformed_coefficients: amp not finite");
+  std::vector<double> M, K, D1, tau;
+  int st = colloc_factors_impl(p, n, M, K, D1, tau);
+  if (st != FDG_OK) return st;
+  const int64_t N = (int64_t)n * n * n;
+  for (int i3 = 0; i3 < n; ++i3)
+    for (int i2 = 0; i2 < n; ++i2)
+      for (int i1 = 0; i1 < n; ++i1) {
+        const double xi[3] = {tau[i1], tau[i2], tau[i3]};
+        Geo G;
+        geometry_at(xi, amp, G);
+        const int64_t o = i1 + (int64_t)n * i2 + (int64_t)n * n * i3;
+        coef[0 * N + o] = G.C[0][0];
+        coef[1 * N + o] = G.C[1][1];
+        coef[2 * N + o] = G.C[2][2];
+        coef[3 * N + o] = G.C[0][1] + G.C[1][0];
+        coef[4 * N + o] = G.C[0][2] + G.C[2][0];
+        coef[5 * N + o] = G.C[1][2] + G.C[2][1];
+        coef[6 * N + o] = G.g[0];
+        coef[7 * N + o] = G.g[1];
+        coef[8 * N + o] = G.g[2];
+      }
+  return FDG_OK;
+}

@@ -50,7 +50,8 @@ EXPORTS = [
     "fdg_set_operator_kron", "fdg_set_operator_csr", "fdg_apply_prec", "fdg_matvec", "fdg_solve",
     "fdg_footprint_bytes", "fdg_timer_enable", "fdg_timer_read", "fdg_status_str", "fdg_last_error",
     "fdg_server_create", "fdg_server_destroy", "fdg_server_run_bytes", "fdg_server_admit", "fdg_server_step",
-    "fdg_server_pending", "fdg_server_stats",
+    "fdg_server_pending", "fdg_server_stats", "fdg_set_operator_mapped", "fdg_set_operator_fields",
+    "fdg_deformed_coefficients",
 ]
 
 
@@ -92,6 +93,9 @@ def lib():
                                   ctypes.POINTER(ctypes.c_int)]
     L.fdg_server_pending.argtypes = [ctypes.c_void_p]
     L.fdg_server_stats.argtypes = [ctypes.c_void_p, _i64p, _i64p, _i64p, _i64p]
+    L.fdg_set_operator_mapped.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
+    L.fdg_set_operator_fields.argtypes = [ctypes.c_void_p, _dp]
+    L.fdg_deformed_coefficients.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
     L.fdg_status_str.argtypes = [ctypes.c_int]
     L.fdg_status_str.restype = ctypes.c_char_p
     L.fdg_last_error.argtypes = []
@@ -141,6 +145,14 @@ def deformed_csr(p, n, amp=0.1, band=False):
     _check(L.fdg_deformed_csr(p, n, amp, int(band), ctypes.byref(nnz), _ptr(rowptr, _i64p), _ptr(col, _i32p),
                               _ptr(val)))
     return rowptr, col, val
+
+
+def deformed_coefficients(p, n, amp=0.1):
+    """The 9 coefficient fields (9, n^3) of the deformed-cube operator at the collocation
+    points: C_11, C_22, C_33, 2 C_12, 2 C_13, 2 C_23, g_1, g_2, g_3."""
+    coef = np.zeros(9 * n ** 3)
+    _check(lib().fdg_deformed_coefficients(p, n, amp, _ptr(coef)))
+    return coef.reshape(9, n ** 3)
 
 
 def manufactured_rhs(d, n, tau):
@@ -208,6 +220,14 @@ class Context:
         val = np.ascontiguousarray(val, dtype=np.float64)
         _check(lib().fdg_set_operator_csr(self._h, len(rowptr) - 1, len(col), _ptr(rowptr, _i64p),
                                           _ptr(col, _i32p), _ptr(val)))
+
+    def set_operator_mapped(self, l, M, D, K):
+        M, D, K = (np.ascontiguousarray(a, dtype=np.float64) for a in (M, D, K))
+        _check(lib().fdg_set_operator_mapped(self._h, l, _ptr(M), _ptr(D), _ptr(K)))
+
+    def set_operator_fields(self, coef):
+        coef = np.ascontiguousarray(coef, dtype=np.float64).ravel()
+        _check(lib().fdg_set_operator_fields(self._h, _ptr(coef)))
 
     def apply_prec(self, b, s):
         _check(lib().fdg_apply_prec(self._h, _dev_ptr(b), _dev_ptr(s)))
@@ -318,4 +338,20 @@ def deformed_problem(p, n, amp=0.1, band=False, stream=None, prec=PREC_FP64):
     ctx.set_precision(prec)
     ctx.tau = tau
     ctx.nnz = len(col)
+    return ctx
+
+
+def mapped_problem(p, n, amp=0.1, stream=None, prec=PREC_FP64):
+    """Context for the deformed-cube collocation problem with the operator applied
+    matrix-free (1D factors and coefficient fields), preconditioned by the unit-cube FD
+    solve."""
+    M, K, D1, tau = colloc_factors(p, n)
+    U, V, lam, _ = factor_pencil(K, M)
+    ctx = Context(3, n, stream=stream)
+    for l in range(3):
+        ctx.set_prec_factors(l, U, V, lam)
+        ctx.set_operator_mapped(l, M, D1, K)
+    ctx.set_operator_fields(deformed_coefficients(p, n, amp))
+    ctx.set_precision(prec)
+    ctx.tau = tau
     return ctx

@@ -115,3 +115,17 @@ def test_footprint_grows_with_restart():
     a = fdg.footprint_bytes(3, 128, 1, 0, 30)
     b = fdg.footprint_bytes(3, 128, 1, 0, 50)
     assert b > a > 61 * 8 * 128 ** 3
+
+
+@pytest.mark.parametrize("p,n", [(3, 8), (4, 7), (2, 9)])
+def test_deformed_coefficient_fields_match_oracle(p, n):
+    _lib()
+    coef = fdg.deformed_coefficients(p, n, 0.1)
+    _, _, _, tau = colloc.colloc_factors(p, n)
+    g1, g2, g3 = np.meshgrid(tau, tau, tau, indexing="ij")
+    # i_1 fastest: point (i3, i2, i1) has xi = (tau[i1], tau[i2], tau[i3])
+    xi = np.stack([g3.ravel(), g2.ravel(), g1.ravel()], axis=-1)
+    C, g = colloc.deformed_coefficients(xi, 0.1)
+    want = np.stack([C[:, 0, 0], C[:, 1, 1], C[:, 2, 2], 2 * C[:, 0, 1], 2 * C[:, 0, 2], 2 * C[:, 1, 2],
+                     g[:, 0], g[:, 1], g[:, 2]])
+    assert np.allclose(coef, want, rtol=1e-12, atol=1e-12)
