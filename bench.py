@@ -159,6 +159,13 @@ def deformed_96():
            "spmv": {"avg_us": spmv_s * 1e6, "algorithmic_bytes": spmv_bytes,
                     "gbps": spmv_bytes / spmv_s / 1e9, "frac_hbm": spmv_bytes / spmv_s / 8e12}}
     ctx.close()
+    # the same solve with the FD preconditioner in FP32 (fused FP32 MFMA passes)
+    ctx32 = fdgmres.deformed_problem(p, n, 0.1, prec=fdgmres.PREC_FP32)
+    dt32, info32, split32 = timed_solves(ctx32, b, x, 5, rtol=1e-8, restart=30)
+    out["fp32_preconditioner"] = {"solves_per_s": 1.0 / dt32, "ms_per_solve": dt32 * 1e3,
+                                  "iterations": info32["iterations"], "rel_res_true": info32["rel_res_true"],
+                                  "speedup_vs_fp64": dt / dt32, "kernel_ms_per_solve": split32}
+    ctx32.close()
     # the same operator applied matrix-free: 1D factors + 9 coefficient fields per point
     t = time.perf_counter()
     mctx = fdgmres.mapped_problem(p, n, 0.1)

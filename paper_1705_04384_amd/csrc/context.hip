@@ -136,6 +136,13 @@ int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nen
   const int n = c->n;
   const int64_t N = c->N;
   const bool gathered = in.ptrs || out.ptrs || t1.ptrs || t2.ptrs;
+  if (c->prec == FDG_PREC_FP32 && fd_fused_supported(n)) {  // fused FP32 passes
+    if (gathered) return set_error(FDG_EINVAL, "apply: gathered batches need the FP64 preconditioner");
+    TimedLaunch tl(c, 0, ex.stream, ex.timed);
+    launch_fd_apply_f32(ex.stream, c->d, n, nent, in.base, out.base, (float *)t32a, (float *)t32b, c->Wv32, c->Wu32,
+                        c->lam32, c->ldw);
+    return hip_check(hipGetLastError(), "apply_prec launch");
+  }
   if (c->prec != FDG_PREC_FP64) {
     if (gathered) return set_error(FDG_EINVAL, "apply: gathered batches need the FP64 preconditioner");
     TimedLaunch tl(c, 0, ex.stream, ex.timed);

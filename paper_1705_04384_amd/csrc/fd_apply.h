@@ -25,4 +25,10 @@ void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const 
 void launch_fibre_f64(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const double *Wb, int ldw,
                       int n, int64_t batch, const double *lam1, const double *lam2, const double *lam3);
 
+// Fused FP32 solve of batch contiguous entries (FP64 b in, FP64 out): FP32 factors
+// Wv[l] = V_l^T, Wu[l] = U_l (ldw x ldw, zero-padded) and eigenvalues lam[l] (padded
+// with 1), FP32 intermediates t1, t2 of batch * N floats.  n <= 256.
+void launch_fd_apply_f32(hipStream_t s, int d, int n, int64_t batch, const double *b, double *out, float *t1,
+                         float *t2, const float *const *Wv, const float *const *Wu, const float *const *lam, int ldw);
+
 }  // namespace fdg

@@ -1,0 +1,313 @@
+// Fused FP32 fast-diagonalization solve (eq. 4.9 / 4.7) on FP32 MFMA: the three passes of
+// the FP64 solve (slab: modes 1 and 2; fibre: mode 3, divide, mode 3; slab: modes 1 and 2)
+// with the factors rounded once to FP32, FP32 products and accumulation, FP32
+// intermediates between the passes, an FP64 input to the first pass and an FP64 output
+// from the last.  The preconditioner is then inexact at the FP32 level, which flexible
+// GMRES absorbs.
+//
+// v_mfma_f32_16x16x4_f32 lane layout (li = lane % 16, lg = lane / 16):
+//   A[m = li][k = lg], B[k = lg][n = li], D[m = 4 lg + r][n = li] in register r.
+// As in the FP64 passes, lane group lg supplies contraction index j0 + 4 lg + t to both
+// operands of the t-th MFMA of a 16-wide k-block, so each lane reads four consecutive
+// elements.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fd_apply.h"
+
+namespace fdg {
+
+namespace {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+constexpr int kNT = 2;         // 16-column MFMA tiles per wave
+constexpr int kNB = 16 * kNT;  // columns per workgroup
+constexpr int kPad = 4;        // LDS row padding (floats)
+
+__device__ inline flt4 mfma32(float a, float b, flt4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// Four consecutive elements p[0..3] as floats, zero where j + t >= jmax or !ok.
+template <typename T>
+__device__ inline void load4f(const T *p, int j, int jmax, bool ok, float (&v)[4]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = (ok && j + t < jmax) ? (float)p[t] : 0.0f;
+}
+
+template <int MT>
+struct Frag32 {
+  float a[MT][4];
+  float b[kNT][4];
+};
+
+template <int MT>
+__device__ inline void mma_block32(const Frag32<MT> &f, flt4 (&acc)[MT][kNT]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int b = 0; b < kNT; ++b) acc[a][b] = mfma32(f.a[a][t], f.b[b][t], acc[a][b]);
+}
+
+template <int MT, typename Load>
+__device__ inline void gemm32(int kpad, Load load, flt4 (&acc)[MT][kNT]) {
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
+  Frag32<MT> f0, f1;
+  load(0, f0);
+  for (int j0 = 0; j0 < kpad; j0 += 32) {
+    const bool has1 = j0 + 16 < kpad;
+    if (has1) load(j0 + 16, f1);
+    mma_block32<MT>(f0, acc);
+    if (has1) {
+      if (j0 + 32 < kpad) load(j0 + 32, f0);
+      mma_block32<MT>(f1, acc);
+    }
+  }
+}
+
+// Pass A / C: workgroup = (slab s, block of kNB columns); wave w owns rows
+// [w*MT*16, (w+1)*MT*16) of both contractions.
+//   GEMM1: Y1[i2][c] = sum_i1 X[s][i2][i1] W1[c][i1]   (W1 column tile in LDS)
+//   GEMM2: Y2[k2][c] = sum_i2 W2[k2][i2] Y1[i2][c]     (Y1 in LDS, transposed)
+//   2D: Y2[k2][c] /= lam2[k2] + lam1[c].
+template <int WAVES, int MT, typename TI, typename TO, bool DIV>
+__global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X, TO *__restrict__ Y,
+                                                       const float *__restrict__ W1, const float *__restrict__ W2,
+                                                       int ldw, int n, int64_t nslab, int ncb, int xcd_remap,
+                                                       const float *__restrict__ lam1, const float *__restrict__ lam2) {
+  constexpr int MPAD = WAVES * MT * 16;
+  constexpr int LDP = MPAD + kPad;
+  constexpr int NTHR = 64 * WAVES;
+  __shared__ float buf[kNB * LDP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  int64_t s;
+  int cb;
+  {
+    const int64_t bid = blockIdx.x;
+    if (xcd_remap) {  // the ncb workgroups of one slab share an XCD
+      const int64_t xcd = bid & 7, local = bid >> 3;
+      s = (local / ncb) * 8 + xcd;
+      cb = (int)(local % ncb);
+    } else {
+      s = bid / ncb;
+      cb = (int)(bid % ncb);
+    }
+  }
+  if (s >= nslab) return;
+  const int64_t n2 = (int64_t)n * n;
+  const TI *__restrict__ Xs = X + s * n2;
+  TO *__restrict__ Ys = Y + s * n2;
+  const int c0 = cb * kNB;
+  const int m0 = wave * MT * 16;
+  const int kpad = (n + 15) & ~15;
+  for (int e = threadIdx.x; e < kNB * kpad; e += NTHR) {
+    const int c = e / kpad, j = e - c * kpad;
+    buf[c * LDP + j] = W1[(size_t)(c0 + c) * ldw + j];
+  }
+  __syncthreads();
+  flt4 acc[MT][kNT];
+  gemm32<MT>(kpad, [&](int j0, Frag32<MT> &f) {
+    const int j = j0 + 4 * lg;
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      const int row = m0 + 16 * a + li;
+      load4f(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
+    }
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) {
+      const float *p = buf + (16 * b + li) * LDP + j;
+      f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
+    }
+  }, acc);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < kNT; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + 4 * lg + r] = acc[a][b][r];
+  __syncthreads();
+  gemm32<MT>(kpad, [&](int j0, Frag32<MT> &f) {
+    const int j = j0 + 4 * lg;
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      const float *w = W2 + (size_t)(m0 + 16 * a + li) * ldw + j;
+      f.a[a][0] = w[0]; f.a[a][1] = w[1]; f.a[a][2] = w[2]; f.a[a][3] = w[3];
+    }
+#pragma unroll
+    for (int b = 0; b < kNT; ++b) {
+      const float *p = buf + (16 * b + li) * LDP + j;
+      f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
+    }
+  }, acc);
+#pragma unroll
+  for (int b = 0; b < kNT; ++b) {
+    const int c = c0 + 16 * b + li;
+    if (c >= n) continue;
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k2 = m0 + 16 * a + 4 * lg + r;
+        if (k2 < n) {
+          float v = acc[a][b][r];
+          if (DIV) v = v / (lam2[k2] + lam1[c]);
+          Ys[(int64_t)k2 * n + c] = (TO)v;
+        }
+      }
+  }
+}
+
+// Pass B: workgroup = (entry, block of kNB columns c of X[i3][c]); the block is staged
+// transposed in LDS, then T = Wa X, T /= lam3 + lam2 + lam1, S = Wb T.
+template <int WAVES, int MT>
+__global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict__ X, float *__restrict__ Y,
+                                                        const float *__restrict__ Wa, const float *__restrict__ Wb,
+                                                        int ldw, int n, int ncb, const float *__restrict__ lam1,
+                                                        const float *__restrict__ lam2, const float *__restrict__ lam3) {
+  constexpr int MPAD = WAVES * MT * 16;
+  constexpr int LDP = MPAD + kPad;
+  constexpr int NTHR = 64 * WAVES;
+  __shared__ float xt[kNB * LDP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t bidx = blockIdx.x / ncb;
+  const int cb = (int)(blockIdx.x % ncb);
+  const int64_t n2 = (int64_t)n * n;
+  const float *__restrict__ Xb = X + bidx * n2 * n;
+  float *__restrict__ Yb = Y + bidx * n2 * n;
+  const int64_t c0 = (int64_t)cb * kNB;
+  const int m0 = wave * MT * 16;
+  const int kpad = (n + 15) & ~15;
+  for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
+    const int i3 = e / kNB, c = e % kNB;
+    const int64_t cg = c0 + c;
+    xt[c * LDP + i3] = (i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0f;
+  }
+  __syncthreads();
+  flt4 acc[MT][kNT];
+  auto lds_gemm = [&](const float *W) {
+    gemm32<MT>(kpad, [&](int j0, Frag32<MT> &f) {
+      const int j = j0 + 4 * lg;
+#pragma unroll
+      for (int a = 0; a < MT; ++a) {
+        const float *w = W + (size_t)(m0 + 16 * a + li) * ldw + j;
+        f.a[a][0] = w[0]; f.a[a][1] = w[1]; f.a[a][2] = w[2]; f.a[a][3] = w[3];
+      }
+#pragma unroll
+      for (int b = 0; b < kNT; ++b) {
+        const float *p = xt + (16 * b + li) * LDP + j;
+        f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
+      }
+    }, acc);
+  };
+  lds_gemm(Wa);
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < kNT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    const bool cok = cg < n2;
+    const int i2 = cok ? (int)(cg / n) : 0, i1 = cok ? (int)(cg % n) : 0;
+    const float l12 = lam2[i2] + lam1[i1];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k3 = m0 + 16 * a + 4 * lg + r;
+        xt[(16 * b + li) * LDP + k3] = acc[a][b][r] / (lam3[k3] + l12);  // lam3 padded with 1
+      }
+  }
+  __syncthreads();
+  lds_gemm(Wb);
+#pragma unroll
+  for (int b = 0; b < kNT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    if (cg >= n2) continue;
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k3 = m0 + 16 * a + 4 * lg + r;
+        if (k3 < n) Yb[(int64_t)k3 * n2 + cg] = acc[a][b][r];
+      }
+  }
+}
+
+struct Shape32 {
+  int waves, mt;
+};
+
+Shape32 pick_shape32(int n) {
+  const int k = (n + 15) / 16;
+  if (k <= 4) return {4, 1};
+  if (k <= 8) return {k, 1};
+  if (k <= 12) return {12, 1};
+  return {8, 2};
+}
+
+#define FDG_SHAPES32(X) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(12, 1) X(8, 2)
+
+template <int W, int M, typename TI, typename TO>
+void slab32(hipStream_t s, const TI *X, TO *Y, const float *W1, const float *W2, int ldw, int n, int64_t nslab,
+            bool div, const float *lam1, const float *lam2) {
+  const int ncb = (n + kNB - 1) / kNB;
+  const int remap = (nslab % 8 == 0) ? 1 : 0;
+  const dim3 grid((unsigned)(nslab * ncb)), blk(64 * W);
+  if (div)
+    hipLaunchKernelGGL((k_slab32<W, M, TI, TO, true>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1,
+                       lam2);
+  else
+    hipLaunchKernelGGL((k_slab32<W, M, TI, TO, false>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap,
+                       lam1, lam2);
+}
+
+template <typename TI, typename TO>
+void slab32_dispatch(hipStream_t s, const TI *X, TO *Y, const float *W1, const float *W2, int ldw, int n,
+                     int64_t nslab, bool div, const float *lam1, const float *lam2) {
+  const Shape32 sh = pick_shape32(n);
+#define FDG_CASE(W, M)                                                        \
+  if (sh.waves == W && sh.mt == M) {                                         \
+    slab32<W, M, TI, TO>(s, X, Y, W1, W2, ldw, n, nslab, div, lam1, lam2); \
+    return;                                                                  \
+  }
+  FDG_SHAPES32(FDG_CASE)
+#undef FDG_CASE
+}
+
+void fibre32_dispatch(hipStream_t s, const float *X, float *Y, const float *Wa, const float *Wb, int ldw, int n,
+                      int64_t batch, const float *lam1, const float *lam2, const float *lam3) {
+  const Shape32 sh = pick_shape32(n);
+  const int64_t n2 = (int64_t)n * n;
+  const int ncb = (int)((n2 + kNB - 1) / kNB);
+  const dim3 grid((unsigned)(batch * ncb));
+#define FDG_CASE(W, M)                                                                                            \
+  if (sh.waves == W && sh.mt == M) {                                                                             \
+    hipLaunchKernelGGL((k_fibre32<W, M>), grid, dim3(64 * W), 0, s, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3); \
+    return;                                                                                                       \
+  }
+  FDG_SHAPES32(FDG_CASE)
+#undef FDG_CASE
+}
+
+}  // namespace
+
+void launch_fd_apply_f32(hipStream_t s, int d, int n, int64_t batch, const double *b, double *out, float *t1,
+                         float *t2, const float *const *Wv, const float *const *Wu, const float *const *lam, int ldw) {
+  if (d == 3) {
+    const int64_t nslab = batch * n;
+    slab32_dispatch<double, float>(s, b, t1, Wv[0], Wv[1], ldw, n, nslab, false, nullptr, nullptr);
+    fibre32_dispatch(s, t1, t2, Wv[2], Wu[2], ldw, n, batch, lam[0], lam[1], lam[2]);
+    slab32_dispatch<float, double>(s, t2, out, Wu[0], Wu[1], ldw, n, nslab, false, nullptr, nullptr);
+  } else {
+    slab32_dispatch<double, float>(s, b, t1, Wv[0], Wv[1], ldw, n, batch, true, lam[0], lam[1]);
+    slab32_dispatch<float, double>(s, t1, out, Wu[0], Wu[1], ldw, n, batch, false, nullptr, nullptr);
+  }
+}
+
+}  // namespace fdg

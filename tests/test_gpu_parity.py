@@ -208,3 +208,45 @@ def test_errors_through_the_abi():
     with pytest.raises(fdg.FdgError):
         ctx.set_precision(7)
     ctx.close()
+
+
+@pytest.mark.parametrize("d,p,n", [(3, 4, 40), (3, 3, 33), (3, 6, 65), (2, 4, 130), (2, 3, 47), (3, 5, 96),
+                                   (3, 4, 129), (2, 2, 260)])
+def test_fp32_apply_fused_passes(d, p, n):
+    """FP32 factors and MFMA (fused passes for n <= 256, mode products beyond): the
+    contraction |b - P P~^{-1} b| / |b| and the distance to the FP64 oracle stay at the
+    FP32 rounding level."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.unit_problem(d, p, n, prec=fdg.PREC_FP32)
+    b = inputs.rhs_normal(7, n ** d)
+    s = torch.empty(n ** d, dtype=torch.float64, device="cuda")
+    ctx.apply_prec(to_dev(b), s)
+    torch.cuda.synchronize()
+    P, prec64 = oracle_unit(p, n, d)
+    sg = s.cpu().numpy()
+    assert relerr(P @ sg, b) <= 5e-5
+    assert relerr(sg, prec64(b)) <= 5e-4
+    ctx.close()
+
+
+def test_fp32_preconditioned_deformed_solve():
+    """P != A: the FP32 preconditioner inside FGMRES reaches the FP64 true residual and
+    the oracle's FP64 solution."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    p, n = 3, 12
+    ctx = fdg.deformed_problem(p, n, 0.1, prec=fdg.PREC_FP32)
+    b = inputs.rhs_uniform(inputs.SEED_DEFORMED_96, n ** 3)
+    A = colloc.deformed_operator(p, n, 0.1)
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    U, V, lam = fd.factor_pencil(K, M)
+    prec = lambda v: fd.fd_apply([U] * 3, [V] * 3, [lam] * 3, v)
+    x_ref, _ = fgmres.fgmres(lambda v: A @ v, prec, b, rtol=1e-13, restart=30)
+    _, io = fgmres.fgmres(lambda v: A @ v, prec, b, rtol=1e-10, restart=30)
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.solve(to_dev(b), x, rtol=1e-10, restart=30)
+    assert info["converged"] and info["rel_res_true"] <= 1e-10
+    assert abs(info["iterations"] - io["iterations"]) <= 2, (info["iterations"], io["iterations"])
+    assert relerr(x.cpu().numpy(), x_ref) <= 1e-8
+    ctx.close()
