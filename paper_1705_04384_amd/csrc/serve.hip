@@ -296,15 +296,15 @@ extern "C" int fdg_server_admit(fdg_server *s, fdg_ctx *c, const double *b, doub
   rb.hh = s->pin + (size_t)idx * host_doubles(s->m);
   rb.hh_dev = s->pin_dev + (size_t)idx * host_doubles(s->m);
   sl.run.init(c, rb, s->m, b, x, rtol, maxit, flags);
-  // lane: one already serving this context (shared launches), else the least loaded
+  // lane: one already serving this context with room in its group (shared launches),
+  // else the least loaded
   int lane = -1;
   if (groupable(c))
-    for (size_t li = 0; li < s->lanes.size() && lane < 0; ++li)
-      for (int j : s->lanes[li].slots)
-        if (s->slots[j].run.ctx == c) {
-          lane = (int)li;
-          break;
-        }
+    for (size_t li = 0; li < s->lanes.size() && lane < 0; ++li) {
+      int same = 0;
+      for (int j : s->lanes[li].slots) same += s->slots[j].run.ctx == c ? 1 : 0;
+      if (same > 0 && same < kMaxGroupEntries) lane = (int)li;
+    }
   if (lane < 0) {
     lane = 0;
     for (size_t li = 1; li < s->lanes.size(); ++li)
