@@ -73,10 +73,11 @@ void lu_solve(const Mat &LU, const std::vector<int> &piv, std::vector<double> &B
   }
 }
 
-// Householder reduction to upper Hessenberg form, H = Z^T A Z, Z accumulated.
-void hessenberg(Mat &H, Mat &Z) {
+// Householder reduction to upper Hessenberg form, H = Z^T A Z, Z accumulated (stored
+// transposed in Zt, so its updates run along contiguous rows).
+void hessenberg(Mat &H, Mat &Zt) {
   const int n = H.n;
-  std::vector<double> v(n);
+  std::vector<double> v(n), w(n);
   for (int k = 0; k + 2 < n; ++k) {
     double alpha = 0.0;
     for (int i = k + 1; i < n; ++i) alpha += H(i, k) * H(i, k);
@@ -91,12 +92,18 @@ void hessenberg(Mat &H, Mat &Z) {
     for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
     if (vv == 0.0) continue;
     const double beta = 2.0 / vv;
-    // left: H = (I - beta v v^T) H on rows k+1.., columns k..
-    for (int j = k; j < n; ++j) {
-      double s = 0.0;
-      for (int i = k + 1; i < n; ++i) s += v[i] * H(i, j);
-      s *= beta;
-      for (int i = k + 1; i < n; ++i) H(i, j) -= s * v[i];
+    // left: H = (I - beta v v^T) H on rows k+1.., columns k.. (row-major sweeps:
+    // w = H^T v accumulated row by row, then the rank-one update row by row)
+    std::fill(w.begin(), w.end(), 0.0);
+    for (int i = k + 1; i < n; ++i) {
+      const double vi = v[i];
+      const double *h = &H(i, 0);
+      for (int j = k; j < n; ++j) w[j] += vi * h[j];
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double bv = beta * v[i];
+      double *h = &H(i, 0);
+      for (int j = k; j < n; ++j) h[j] -= bv * w[j];
     }
     // right: H = H (I - beta v v^T) on all rows, columns k+1..
     for (int i = 0; i < n; ++i) {
@@ -105,20 +112,27 @@ void hessenberg(Mat &H, Mat &Z) {
       s *= beta;
       for (int j = k + 1; j < n; ++j) H(i, j) -= s * v[j];
     }
-    for (int i = 0; i < n; ++i) {
-      double s = 0.0;
-      for (int j = k + 1; j < n; ++j) s += Z(i, j) * v[j];
-      s *= beta;
-      for (int j = k + 1; j < n; ++j) Z(i, j) -= s * v[j];
+    // Z = Z (I - beta v v^T), Z stored transposed (Zt(j, i) = Z(i, j))
+    std::fill(w.begin(), w.end(), 0.0);
+    for (int j = k + 1; j < n; ++j) {
+      const double vj = v[j];
+      const double *z = &Zt(j, 0);
+      for (int i = 0; i < n; ++i) w[i] += vj * z[i];
+    }
+    for (int j = k + 1; j < n; ++j) {
+      const double bv = beta * v[j];
+      double *z = &Zt(j, 0);
+      for (int i = 0; i < n; ++i) z[i] -= bv * w[i];
     }
     H(k + 1, k) = alpha;
     for (int i = k + 2; i < n; ++i) H(i, k) = 0.0;
   }
 }
 
-// Applies the reflector I - beta v v^T (v of length m at rows/cols r0..r0+m-1) to H
-// from both sides within the given ranges, and to Z from the right.
-void apply_reflector(Mat &H, Mat &Z, int r0, int m, const double *v, double beta, int col_lo,
+// Applies the reflector I - beta v v^T (v of length m = 2 or 3 at rows/cols
+// r0..r0+m-1) to H from both sides within the given ranges, and to Z from the right
+// (Z stored transposed in Zt).
+void apply_reflector(Mat &H, Mat &Zt, int r0, int m, const double *v, double beta, int col_lo,
                      int row_hi) {
   const int n = H.n;
   for (int j = col_lo; j < n; ++j) {
@@ -133,11 +147,23 @@ void apply_reflector(Mat &H, Mat &Z, int r0, int m, const double *v, double beta
     s *= beta;
     for (int t = 0; t < m; ++t) H(i, r0 + t) -= s * v[t];
   }
-  for (int i = 0; i < n; ++i) {
-    double s = 0.0;
-    for (int t = 0; t < m; ++t) s += Z(i, r0 + t) * v[t];
-    s *= beta;
-    for (int t = 0; t < m; ++t) Z(i, r0 + t) -= s * v[t];
+  // Z = Z (I - beta v v^T) with Z stored transposed: rows r0..r0+m-1 of Zt
+  double *z0 = &Zt(r0, 0);
+  double *z1 = m > 1 ? &Zt(r0 + 1, 0) : nullptr;
+  double *z2 = m > 2 ? &Zt(r0 + 2, 0) : nullptr;
+  if (m == 3) {
+    for (int i = 0; i < n; ++i) {
+      const double s = beta * (v[0] * z0[i] + v[1] * z1[i] + v[2] * z2[i]);
+      z0[i] -= s * v[0];
+      z1[i] -= s * v[1];
+      z2[i] -= s * v[2];
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      const double s = beta * (v[0] * z0[i] + v[1] * z1[i]);
+      z0[i] -= s * v[0];
+      z1[i] -= s * v[1];
+    }
   }
 }
 
@@ -160,7 +186,7 @@ double make_reflector(const double *x, int m, double *v) {
 
 // Rotates the 2x2 diagonal block at (p, p+1), whose eigenvalues are real, to upper
 // triangular form.  Returns false if the block's eigenvalues are genuinely complex.
-bool split_block(Mat &H, Mat &Z, int p, double *ev0, double *ev1) {
+bool split_block(Mat &H, Mat &Zt, int p, double *ev0, double *ev1) {
   const int n = H.n, q = p + 1;
   const double a = H(p, p), b = H(p, q), c = H(q, p), d = H(q, q);
   const double half = 0.5 * (a - d);
@@ -192,10 +218,11 @@ bool split_block(Mat &H, Mat &Z, int p, double *ev0, double *ev1) {
     H(i, p) = cs * h0 + sn * h1;
     H(i, q) = -sn * h0 + cs * h1;
   }
+  double *zp = &Zt(p, 0), *zq = &Zt(q, 0);  // columns p, q of Z
   for (int i = 0; i < n; ++i) {
-    const double z0 = Z(i, p), z1 = Z(i, q);
-    Z(i, p) = cs * z0 + sn * z1;
-    Z(i, q) = -sn * z0 + cs * z1;
+    const double z0 = zp[i], z1 = zq[i];
+    zp[i] = cs * z0 + sn * z1;
+    zq[i] = -sn * z0 + cs * z1;
   }
   H(q, p) = 0.0;
   *ev0 = H(p, p);
@@ -204,7 +231,7 @@ bool split_block(Mat &H, Mat &Z, int p, double *ev0, double *ev1) {
 }
 
 // Francis double-shift QR on the Hessenberg H to upper-triangular form (real spectrum).
-int schur_real(Mat &H, Mat &Z, std::vector<double> &ev) {
+int schur_real(Mat &H, Mat &Zt, std::vector<double> &ev) {
   const int n = H.n;
   const double eps = 2.220446049250313e-16;
   double anorm = 0.0;
@@ -233,7 +260,7 @@ int schur_real(Mat &H, Mat &Z, std::vector<double> &ev) {
     }
     if (l == hi - 1) {
       double e0, e1;
-      if (!split_block(H, Z, hi - 1, &e0, &e1))
+      if (!split_block(H, Zt, hi - 1, &e0, &e1))
         return set_error(FDG_ECOMPLEX, "factor_pencil: complex eigenvalue pair");
       ev[hi - 1] = e0;
       ev[hi] = e1;
@@ -259,7 +286,7 @@ int schur_real(Mat &H, Mat &Z, std::vector<double> &ev) {
       const double xv[3] = {x, y, z};
       const double beta = make_reflector(xv, 3, v);
       if (beta != 0.0) {
-        apply_reflector(H, Z, k, 3, v, beta, std::max(l, k - 1), std::min(k + 3, hi));
+        apply_reflector(H, Zt, k, 3, v, beta, std::max(l, k - 1), std::min(k + 3, hi));
         if (k > l) {
           H(k + 1, k - 1) = 0.0;
           H(k + 2, k - 1) = 0.0;
@@ -272,7 +299,7 @@ int schur_real(Mat &H, Mat &Z, std::vector<double> &ev) {
     const double xv[2] = {x, y};
     const double beta = make_reflector(xv, 2, v);
     if (beta != 0.0) {
-      apply_reflector(H, Z, hi - 1, 2, v, beta, std::max(l, hi - 2), hi);
+      apply_reflector(H, Zt, hi - 1, 2, v, beta, std::max(l, hi - 2), hi);
       if (hi - 2 >= l) H(hi, hi - 2) = 0.0;
     }
   }
@@ -300,81 +327,89 @@ extern "C" int fdg_factor_pencil(int n, const double *K, const double *M, double
   if (!lu_factor(LU, piv)) return set_error(FDG_EINVAL, "factor_pencil: M is singular");
   std::vector<double> A(K, K + nn);
   lu_solve(LU, piv, A, n);
-  Mat H(n), Z(n);
+  Mat H(n), Zt(n);  // Zt = Z^T, the Schur vectors as rows
   H.a = A;
-  for (int i = 0; i < n; ++i) Z(i, i) = 1.0;
-  hessenberg(H, Z);
+  for (int i = 0; i < n; ++i) Zt(i, i) = 1.0;
+  hessenberg(H, Zt);
   std::vector<double> ev;
-  int st = schur_real(H, Z, ev);
+  int st = schur_real(H, Zt, ev);
   if (st != FDG_OK) return st;
   double emax = 0.0;
   for (double e : ev) emax = std::max(emax, std::fabs(e));
   for (double e : ev)
     if (!(e > 0.0)) return set_error(FDG_ECOMPLEX, "factor_pencil: non-positive eigenvalue %g", e);
-  // eigenvectors of the upper-triangular T = H by back-substitution
+  // eigenvectors of the upper-triangular T = H by back-substitution; column k of Y is
+  // kept as row k of Yt so every inner product runs over contiguous memory
   const double ulp = 2.220446049250313e-16;
-  Mat Y(n);
+  Mat Yt(n);
   for (int k = n - 1; k >= 0; --k) {
     const double lk = H(k, k);
     const double smin = std::max(ulp * std::fabs(lk), 1e-300);
-    Y(k, k) = 1.0;
+    double *y = &Yt(k, 0);
+    y[k] = 1.0;
     for (int i = k - 1; i >= 0; --i) {
+      const double *h = &H(i, 0);
       double s = 0.0;
-      for (int j = i + 1; j <= k; ++j) s += H(i, j) * Y(j, k);
+      for (int j = i + 1; j <= k; ++j) s += h[j] * y[j];
       double den = H(i, i) - lk;
-      double y;
+      double yi;
       if (std::fabs(den) < smin) {
         // equal eigenvalues (the double outlier of Remark 1): when the coupling is at
         // rounding level the Schur vector itself is an eigenvector of the cluster;
         // otherwise perturb the divisor as for nearby eigenvalues.
         double ymax = 0.0;
-        for (int j = i + 1; j <= k; ++j) ymax = std::max(ymax, std::fabs(Y(j, k)));
+        for (int j = i + 1; j <= k; ++j) ymax = std::max(ymax, std::fabs(y[j]));
         if (std::fabs(s) <= 1e-10 * std::fabs(lk) * ymax) {
-          y = 0.0;
+          yi = 0.0;
         } else {
           den = den >= 0 ? smin : -smin;
-          y = -s / den;
+          yi = -s / den;
         }
       } else {
-        y = -s / den;
+        yi = -s / den;
       }
-      Y(i, k) = y;
-      if (std::fabs(y) > 1e150) {  // rescale the partial vector
-        for (int j = i; j <= k; ++j) Y(j, k) *= 1e-150;
+      y[i] = yi;
+      if (std::fabs(yi) > 1e150) {  // rescale the partial vector
+        for (int j = i; j <= k; ++j) y[j] *= 1e-150;
       }
     }
   }
-  // U = Z Y, unit columns, eigenvalues ascending
-  Mat Uz(n);
-  for (int i = 0; i < n; ++i)
-    for (int k = 0; k < n; ++k) {
-      double s = 0.0;
-      for (int j = 0; j <= k; ++j) s += Z(i, j) * Y(j, k);
-      Uz(i, k) = s;
+  // U = Z Y (column k of U = sum_j Y(j, k) Z(:, j), accumulated as row k of Ut),
+  // unit columns, eigenvalues ascending
+  Mat Ut(n);
+  for (int k = 0; k < n; ++k) {
+    const double *y = &Yt(k, 0);
+    double *u = &Ut(k, 0);
+    for (int j = 0; j <= k; ++j) {
+      const double yj = y[j];
+      if (yj == 0.0) continue;
+      const double *z = &Zt(j, 0);
+      for (int i = 0; i < n; ++i) u[i] += yj * z[i];
     }
+  }
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ev[a] < ev[b]; });
   for (int c = 0; c < n; ++c) {
     const int k = order[c];
     double nrm = 0.0;
-    for (int i = 0; i < n; ++i) nrm += Uz(i, k) * Uz(i, k);
+    for (int i = 0; i < n; ++i) nrm += Ut(k, i) * Ut(k, i);
     nrm = std::sqrt(nrm);
     if (!(nrm > 0.0) || !std::isfinite(nrm)) return set_error(FDG_ENOCONV, "factor_pencil: degenerate eigenvector");
-    for (int i = 0; i < n; ++i) U[(size_t)i * n + c] = Uz(i, k) / nrm;
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + c] = Ut(k, i) / nrm;
     lambda[c] = ev[k];
   }
   // V = (M U)^{-T}
   Mat MU(n);
-  for (int i = 0; i < n; ++i)
-    for (int k = 0; k < n; ++k) {
-      double s = 0.0;
-      for (int j = 0; j < n; ++j) {
-        const double m = M[(size_t)i * n + j];
-        if (m != 0.0) s += m * U[(size_t)j * n + k];
-      }
-      MU(i, k) = s;
+  for (int i = 0; i < n; ++i) {
+    double *mu = &MU(i, 0);
+    for (int j = 0; j < n; ++j) {
+      const double m = M[(size_t)i * n + j];
+      if (m == 0.0) continue;
+      const double *u = U + (size_t)j * n;
+      for (int k = 0; k < n; ++k) mu[k] += m * u[k];
     }
+  }
   std::vector<int> piv2;
   if (!lu_factor(MU, piv2)) return set_error(FDG_EINVAL, "factor_pencil: M U is singular");
   std::vector<double> inv(nn, 0.0);

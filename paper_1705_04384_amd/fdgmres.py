@@ -124,14 +124,16 @@ def colloc_factors(p, n):
     return M, K, D1, tau
 
 
-def factor_pencil(K, M):
-    """(U, V, lam, cond1(U)) with K U = M U diag(lam), V = (M U)^{-T} (eq. 4.6)."""
+def factor_pencil(K, M, want_cond=True):
+    """(U, V, lam, cond1(U)) with K U = M U diag(lam), V = (M U)^{-T} (eq. 4.6); the
+    condition number (an extra factorisation) is None unless want_cond."""
     K = np.ascontiguousarray(K, dtype=np.float64)
     M = np.ascontiguousarray(M, dtype=np.float64)
     n = K.shape[0]
     U = np.zeros((n, n)); V = np.zeros((n, n)); lam = np.zeros(n); c = ctypes.c_double()
-    _check(lib().fdg_factor_pencil(n, _ptr(K), _ptr(M), _ptr(U), _ptr(V), _ptr(lam), ctypes.byref(c)))
-    return U, V, lam, c.value
+    _check(lib().fdg_factor_pencil(n, _ptr(K), _ptr(M), _ptr(U), _ptr(V), _ptr(lam),
+                                   ctypes.byref(c) if want_cond else None))
+    return U, V, lam, (c.value if want_cond else None)
 
 
 def deformed_csr(p, n, amp=0.1, band=False):
@@ -315,7 +317,7 @@ def unit_problem(d, p, n, batch=1, stream=None, prec=PREC_FP64):
     """Context for the unit-domain collocation problem: operator (eq. 2.7 / 2.9) and its FD
     preconditioner, all factors built by the library's host setup."""
     M, K, D1, tau = colloc_factors(p, n)
-    U, V, lam, _ = factor_pencil(K, M)
+    U, V, lam, _ = factor_pencil(K, M, want_cond=False)
     ctx = Context(d, n, batch=batch, stream=stream)
     for l in range(d):
         ctx.set_prec_factors(l, U, V, lam)
@@ -329,7 +331,7 @@ def deformed_problem(p, n, amp=0.1, band=False, stream=None, prec=PREC_FP64):
     """Context for the deformed-cube collocation problem (CSR operator) preconditioned by the
     unit-cube FD solve."""
     M, K, D1, tau = colloc_factors(p, n)
-    U, V, lam, _ = factor_pencil(K, M)
+    U, V, lam, _ = factor_pencil(K, M, want_cond=False)
     ctx = Context(3, n, stream=stream)
     for l in range(3):
         ctx.set_prec_factors(l, U, V, lam)
@@ -346,7 +348,7 @@ def mapped_problem(p, n, amp=0.1, stream=None, prec=PREC_FP64):
     matrix-free (1D factors and coefficient fields), preconditioned by the unit-cube FD
     solve."""
     M, K, D1, tau = colloc_factors(p, n)
-    U, V, lam, _ = factor_pencil(K, M)
+    U, V, lam, _ = factor_pencil(K, M, want_cond=False)
     ctx = Context(3, n, stream=stream)
     for l in range(3):
         ctx.set_prec_factors(l, U, V, lam)

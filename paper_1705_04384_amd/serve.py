@@ -25,7 +25,7 @@ from . import fdgmres, inputs
 
 def _factors(p, n):
     M, K, _, _ = fdgmres.colloc_factors(p, n)
-    U, V, lam, _ = fdgmres.factor_pencil(K, M)
+    U, V, lam, _ = fdgmres.factor_pencil(K, M, want_cond=False)
     return M, K, U, V, lam
 
 
