@@ -393,7 +393,9 @@ unsigned stream_blocks(int64_t N, int per_thread) {
 }  // namespace
 
 int reduction_blocks(int64_t N) {
-  int64_t g = (N + 8191) / 8192;
+  // one 1024-thread workgroup per 2048 elements (its minimum chunk), up to 256: the
+  // device has 256 compute units
+  int64_t g = (N + 2047) / 2048;
   if (g < 1) g = 1;
   if (g > kMaxG) g = kMaxG;
   return (int)g;
