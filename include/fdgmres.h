@@ -174,8 +174,9 @@ int fdg_solve(fdg_ctx *ctx, const double *b, double *x, double rtol, int restart
  * (factors, operator excluded for CSR, Krylov bases, scratch). */
 size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart);
 
-/* Per-kernel timing with HIP events recorded on the context stream around every launch
- * of the named kernel class while enabled.  kernel: 0 = FD slab passes (modes 1 and 2 of
+/* Per-kernel timing with HIP events on the context stream for every launch of the named
+ * kernel class while enabled (FD passes: events recorded by the kernel dispatch itself;
+ * other classes: events around the launch).  kernel: 0 = FD slab passes (modes 1 and 2 of
  * eq. 4.9, or the whole 2D solve in two passes; for n > 256 every unfused mode product),
  * 1 = operator matvec, 2 = Krylov vector kernels, 3 = FD fibre pass (mode 3 with V_3^T,
  * the eigenvalue divide and mode 3 with U_3).  fdg_timer_read returns the number of timed

@@ -101,8 +101,12 @@ struct TimedLaunch {
       a = t.pool.back(); t.pool.pop_back();
       b = t.pool.back(); t.pool.pop_back();
     } else {
-      if (hipEventCreate(&a) != hipSuccess) return;
-      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+      // timing-only events: no system-scope fence (no cache write-back) when recorded
+      if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return;
+      if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
     }
     (void)hipEventRecord(a, s);
     t.pending.push_back(a);
@@ -112,6 +116,32 @@ struct TimedLaunch {
     if (!stop) return;
     (void)hipEventRecord(stop, s);
     ctx->timers[c].pending.push_back(stop);
+  }
+};
+
+// Event pair for one kernel of timer class c, recorded by the kernel's own dispatch
+// (hipExtLaunchKernel: no extra queue packets between kernels), when that timer is on
+// and the caller asks for timing; start == nullptr otherwise.
+struct DispatchTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+  DispatchTimer(fdg_ctx *ctx, int c, bool want) {
+    TimerState &t = ctx->timers[c];
+    if (!want || !t.on) return;
+    hipEvent_t a, b;
+    if (t.pool.size() >= 2) {
+      a = t.pool.back(); t.pool.pop_back();
+      b = t.pool.back(); t.pool.pop_back();
+    } else {
+      if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return;
+      if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+    }
+    t.pending.push_back(a);
+    t.pending.push_back(b);
+    start = a;
+    stop = b;
   }
 };
 

@@ -159,28 +159,30 @@ int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nen
                                (nent == 1 || (in.stride % 4 == 0 && out.stride % 4 == 0));
     if (c->d == 3) {
       {
-        TimedLaunch tl(c, 0, ex.stream, ex.timed);
-        launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, n, false, nullptr, nullptr, a32);
+        DispatchTimer tm(c, 0, ex.timed);
+        launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, n, false, nullptr, nullptr, a32,
+                        tm.start, tm.stop);
       }
       {
-        TimedLaunch tl(c, 3, ex.stream, ex.timed);
+        DispatchTimer tm(c, 3, ex.timed);
         launch_fibre_f64(ex.stream, as_const(t1), t2, c->Wv[2], c->Wu[2], c->ldw, n, nent, c->lam[0], c->lam[1],
-                         c->lam[2]);
+                         c->lam[2], tm.start, tm.stop);
       }
       {
-        TimedLaunch tl(c, 0, ex.stream, ex.timed);
+        DispatchTimer tm(c, 0, ex.timed);
         launch_slab_f64(ex.stream, as_const(t2), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, n, false, nullptr,
-                        nullptr, a32);
+                        nullptr, a32, tm.start, tm.stop);
       }
     } else {
       {
-        TimedLaunch tl(c, 0, ex.stream, ex.timed);
-        launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, 1, true, c->lam[0], c->lam[1], a32);
+        DispatchTimer tm(c, 0, ex.timed);
+        launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, 1, true, c->lam[0], c->lam[1], a32,
+                        tm.start, tm.stop);
       }
       {
-        TimedLaunch tl(c, 0, ex.stream, ex.timed);
-        launch_slab_f64(ex.stream, as_const(t1), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, 1, false, nullptr, nullptr,
-                        a32);
+        DispatchTimer tm(c, 0, ex.timed);
+        launch_slab_f64(ex.stream, as_const(t1), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, 1, false, nullptr,
+                        nullptr, a32, tm.start, tm.stop);
       }
     }
     return hip_check(hipGetLastError(), "apply_prec launch");

@@ -14,6 +14,7 @@
 // The contraction index is permuted so that each lane reads four consecutive elements:
 // over the four MFMAs t = 0..3 of a 16-wide k-block starting at j0, lane group lg
 // supplies contraction index j0 + 4 lg + t to both operands.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -329,9 +330,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   }
 }
 
+// Launch on stream s, with dispatch-recorded events when ev0 is given.
+template <typename K, typename... Args>
+void launch_timed(K kernel, dim3 grid, dim3 blk, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, Args... args) {
+  if (ev0)
+    hipExtLaunchKernelGGL(kernel, grid, blk, 0, s, ev0, ev1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, blk, 0, s, args...);
+}
+
 template <int WAVES, int MT>
 void slab_launch(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
-                 int64_t nslab, int spe, bool div, const double *lam1, const double *lam2, bool aligned32) {
+                 int64_t nslab, int spe, bool div, const double *lam1, const double *lam2, bool aligned32,
+                 hipEvent_t ev0, hipEvent_t ev1) {
   const int ncb = (n + kNB - 1) / kNB;
   const int64_t nwg = nslab * ncb;
   const int remap = (nslab % 8 == 0) ? 1 : 0;
@@ -340,28 +351,29 @@ void slab_launch(hipStream_t s, CBatch X, MBatch Y, const double *W1, const doub
   constexpr bool PRE = false;  // preloading the X strip measured slower at n = 128
   if (div) {
     if (vec)
-      hipLaunchKernelGGL((k_slab<WAVES, MT, true, true, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, spe, ncb,
-                         remap, lam1, lam2);
+      launch_timed(k_slab<WAVES, MT, true, true, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe, ncb,
+                   remap, lam1, lam2);
     else
-      hipLaunchKernelGGL((k_slab<WAVES, MT, false, true, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, spe,
-                         ncb, remap, lam1, lam2);
+      launch_timed(k_slab<WAVES, MT, false, true, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+                   ncb, remap, lam1, lam2);
   } else {
     if (vec)
-      hipLaunchKernelGGL((k_slab<WAVES, MT, true, false, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, spe,
-                         ncb, remap, lam1, lam2);
+      launch_timed(k_slab<WAVES, MT, true, false, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+                   ncb, remap, lam1, lam2);
     else
-      hipLaunchKernelGGL((k_slab<WAVES, MT, false, false, PRE>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, spe,
-                         ncb, remap, lam1, lam2);
+      launch_timed(k_slab<WAVES, MT, false, false, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+                   ncb, remap, lam1, lam2);
   }
 }
 
 template <int WAVES, int MT>
 void fibre_launch(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const double *Wb, int ldw, int n,
-                  int64_t batch, const double *lam1, const double *lam2, const double *lam3) {
+                  int64_t batch, const double *lam1, const double *lam2, const double *lam3, hipEvent_t ev0,
+                  hipEvent_t ev1) {
   const int64_t n2 = (int64_t)n * n;
   const int ncb = (int)((n2 + kNB - 1) / kNB);
   const dim3 grid((unsigned)(batch * ncb)), blk(64 * WAVES);
-  hipLaunchKernelGGL((k_fibre<WAVES, MT>), grid, blk, 0, s, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
+  launch_timed(k_fibre<WAVES, MT>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
 }
 
 }  // namespace
@@ -390,13 +402,13 @@ static Shape pick_shape(int n) {
 #define FDG_SHAPES(X) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(4, 2) X(6, 2) X(8, 2) X(4, 3) X(12, 1)
 
 void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
-                     int64_t nentries, int spe, bool divide, const double *lam1, const double *lam2,
-                     bool aligned32) {
+                     int64_t nentries, int spe, bool divide, const double *lam1, const double *lam2, bool aligned32,
+                     hipEvent_t ev0, hipEvent_t ev1) {
   const Shape sh = pick_shape(n);
   const int64_t nslab = nentries * spe;
 #define FDG_CASE(W, M)                                                                    \
   if (sh.waves == W && sh.mt == M) {                                                     \
-    slab_launch<W, M>(s, X, Y, W1, W2, ldw, n, nslab, spe, divide, lam1, lam2, aligned32); \
+    slab_launch<W, M>(s, X, Y, W1, W2, ldw, n, nslab, spe, divide, lam1, lam2, aligned32, ev0, ev1); \
     return;                                                                              \
   }
   FDG_SHAPES(FDG_CASE)
@@ -404,11 +416,12 @@ void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const 
 }
 
 void launch_fibre_f64(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const double *Wb, int ldw, int n,
-                      int64_t batch, const double *lam1, const double *lam2, const double *lam3) {
+                      int64_t batch, const double *lam1, const double *lam2, const double *lam3, hipEvent_t ev0,
+                      hipEvent_t ev1) {
   const Shape sh = pick_shape(n);
 #define FDG_CASE(W, M)                                                                  \
   if (sh.waves == W && sh.mt == M) {                                                   \
-    fibre_launch<W, M>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3);             \
+    fibre_launch<W, M>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3, ev0, ev1);   \
     return;                                                                            \
   }
   FDG_SHAPES(FDG_CASE)

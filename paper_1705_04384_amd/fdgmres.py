@@ -169,11 +169,17 @@ def footprint_bytes(d, n, batch=1, prec=PREC_FP64, restart=30):
 
 # ---- device context -------------------------------------------------------------------------
 
+_torch = None
+
+
 def _dev_ptr(t):
-    import torch
-    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+    global _torch
+    if _torch is None:
+        import torch
+        _torch = torch
+    if not isinstance(t, _torch.Tensor) or not t.is_cuda or t.dtype != _torch.float64 or not t.is_contiguous():
         raise ValueError("expected a contiguous float64 CUDA tensor")
-    return ctypes.c_void_p(t.data_ptr())
+    return t.data_ptr()
 
 
 class Context:
@@ -239,9 +245,12 @@ class Context:
 
     def solve(self, b, x, rtol=1e-8, restart=30, maxit=1000, flags=0):
         info = fdg_info()
-        st = lib().fdg_solve(self._h, _dev_ptr(b), _dev_ptr(x), rtol, restart, maxit, flags, ctypes.byref(info))
-        _check(st, allow=(FDG_OK, FDG_NOT_CONVERGED))
-        return {k: getattr(info, k) for k, _ in fdg_info._fields_}
+        st = _lib.fdg_solve(self._h, _dev_ptr(b), _dev_ptr(x), rtol, restart, maxit, flags, ctypes.byref(info))
+        if st != FDG_OK and st != FDG_NOT_CONVERGED:
+            _check(st)
+        return {"iterations": info.iterations, "restarts": info.restarts, "converged": info.converged,
+                "breakdown": info.breakdown, "rel_res_est": info.rel_res_est, "rel_res_true": info.rel_res_true,
+                "ms_total": info.ms_total}
 
     def timer_enable(self, kernel, on=True):
         _check(lib().fdg_timer_enable(self._h, kernel, int(on)))
