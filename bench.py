@@ -193,6 +193,40 @@ def deformed_96():
     return out
 
 
+def galerkin_convection_48():
+    """Galerkin convection-diffusion on the deformed cube, p = 3, n = 48 (Sec. 3.2): the
+    unit-cube Galerkin preconditioner without the wind (eq. 3.7, symmetric FD, V = U)
+    against the one with univariate winds (eq. 3.9, nonsymmetric FD of K_l + H_l)."""
+    import torch
+    from paper_1705_04384_amd import fdgmres, inputs
+    p, n, amp, wind, beta = 3, 48, 0.1, (10.0, 10.0, 10.0), 0.5
+    N = n ** 3
+    b = torch.from_numpy(inputs.rhs_uniform(inputs.SEED_DEFORMED_96, N)).cuda()
+    x = torch.empty_like(b)
+    out = {"workload": f"Galerkin -Lap u + w.grad u on the deformed cube (amplitude {amp}), "
+                       f"w_a = {wind[0]:g} (1 + x_a)(1 + {beta} cos cos), p={p}, n={n} (N={N}), "
+                       "CSR (2p+1)^3 stencil as ELL, U[-1,1] RHS, FGMRES(30) to rtol 1e-8, FP64"}
+    for key, wp, prec in (("P_wind_nonsymmetric_fd", True, fdgmres.PREC_FP64),
+                          ("P_no_wind_symmetric_fd", False, fdgmres.PREC_FP64),
+                          ("P_wind_fp32", True, fdgmres.PREC_FP32)):
+        t = time.perf_counter()
+        ctx = fdgmres.galerkin_problem(p, n, amp, wind, beta, wind_prec=wp, prec=prec)
+        setup = time.perf_counter() - t
+        dt, info, split = timed_solves(ctx, b, x, 5, rtol=1e-8, restart=30)
+        mv = split["matvec"]
+        spmv_bytes = ctx.nnz * 12 + 2 * N * 8
+        spmv_s = mv["ms_per_solve"] / 1e3 / max(mv["launches_per_solve"], 1)
+        out[key] = {"solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": info["iterations"],
+                    "rel_res_true": info["rel_res_true"], "setup_s": setup, "nnz": ctx.nnz,
+                    "kernel_ms_per_solve": split,
+                    "spmv": {"avg_us": spmv_s * 1e6, "algorithmic_bytes": spmv_bytes,
+                             "gbps": spmv_bytes / spmv_s / 1e9, "frac_hbm": spmv_bytes / spmv_s / 8e12}}
+        ctx.close()
+    out["iteration_ratio_no_wind_over_wind"] = (out["P_no_wind_symmetric_fd"]["iterations"]
+                                                / out["P_wind_nonsymmetric_fd"]["iterations"])
+    return out
+
+
 def batched_2d(count):
     """Many solves of the 2D p = 3, n = 33 problem (manufactured RHS scaled per request):
     through the server, where requests of one shape share every launch, and one by one."""
@@ -406,6 +440,7 @@ def main():
         out["deformed_96"] = deformed_96()
         out["precision_sweep_192"] = precision_sweep_192()
         out["batched_2d_p3_n33"] = batched_2d(1000)
+        out["galerkin_convection_p3_n48"] = galerkin_convection_48()
     if not args.no_serve:
         out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:

@@ -86,6 +86,35 @@ int fdg_colloc_factors(int p, int n, double *M, double *K, double *D1, double *t
 int fdg_factor_pencil(int n, const double *K, const double *M,
                       double *U, double *V, double *lambda, double *cond_u);
 
+/* Symmetric FD factors (Sec. 4, after eq. 4.6) of a pencil with K symmetric and M
+ * symmetric positive definite (e.g. the Galerkin factors of eq. 3.8): K U = M U
+ * diag(lambda) with U^T M U = I, so that V = (M U)^{-T} = U.  Eigenvalues ascending.
+ * K, M: host n*n input (symmetric to 1e-12 relative); U: host n*n output; lambda: host n.
+ * Errors: FDG_EINVAL (bad n, not symmetric, M not positive definite), FDG_ECOMPLEX (an
+ * eigenvalue <= 0), FDG_ENOCONV. */
+int fdg_factor_pencil_sym(int n, const double *K, const double *M, double *U, double *lambda);
+
+/* Univariate Galerkin factors of Sec. 3.2 (eq. 3.8 and the convection factor after
+ * eq. 3.9) for degree p and n interior functions on the open uniform knot vector with
+ * E = n + 2 - p spans, by (p+1)-point Gauss quadrature on every span:
+ *   M[i*n+j] = int B_i B_j,  K[i*n+j] = int B_i' B_j',  H[i*n+j] = int w(z) B_i B_j'
+ * with the affine univariate wind w(z) = w0 + w1 z (exact for this rule).  Host n*n
+ * outputs, any may be NULL.  Errors: FDG_EINVAL. */
+int fdg_galerkin_factors(int p, int n, double w0, double w1, double *M, double *K, double *H);
+
+/* Galerkin matrix (Sec. 3.2) of -Lap u + w . grad u, homogeneous Dirichlet, on the
+ * deformed cube of fdg_deformed_csr (amp = 0: the unit cube), pulled back to the
+ * parametric cube and integrated with the tensor (p+1)^3-point Gauss rule of every
+ * element:  A_ij = sum_q omega_q [grad B_i^T Q grad B_j + B_i b^T grad B_j](xi_q),
+ * Q = det(J) J^{-1} J^{-T} (eq. 2.10, K = I), b = det(J) J^{-1} w(F(xi)), with
+ *   w_a(x) = c_a (1 + x_a) (1 + beta cos(2 pi x_{a+1}) cos(2 pi x_{a+2}))  (cyclic a),
+ * c = wind[0..2] (NULL: no convection).  Rows = test functions, i_1 fastest; the pattern
+ * is every column with |j_l - i_l| <= p (the (2p+1)^3 stencil, clipped at the boundary),
+ * columns ascending.  Call with rowptr/col/val NULL to get *nnz; then pass arrays of
+ * n^3+1, *nnz, *nnz.  Uses up to 16 host threads. */
+int fdg_galerkin_csr(int p, int n, double amp, const double *wind, double beta, int64_t *nnz,
+                     int64_t *rowptr, int32_t *col, double *val);
+
 /* Collocation matrix of -Laplace on the deformed cube F([0,1]^3) with
  * F_a(xi) = xi_a + amp sin(2 pi xi_{a+1}) sin(2 pi xi_{a+2}) (cyclic a), degree p,
  * n unknowns per direction, in CSR (rows = collocation points, i_1 fastest).
@@ -121,6 +150,9 @@ int fdg_destroy(fdg_ctx *ctx);
  * over the directions could be <= 0 -- checked once all directions are set). */
 int fdg_set_prec_factors(fdg_ctx *ctx, int l, const double *U, const double *V,
                          const double *lambda);
+
+/* Symmetric FD factors of direction l (U from fdg_factor_pencil_sym): V = U. */
+int fdg_set_prec_factors_sym(fdg_ctx *ctx, int l, const double *U, const double *lambda);
 
 /* Arithmetic of the P^{-1} mode products (default FDG_PREC_FP64). */
 int fdg_set_precision(fdg_ctx *ctx, int prec);

@@ -21,6 +21,9 @@ Modules (each function cites the passage it follows):
   rule).
 * ``fd``       -- generalized eigendecomposition of the pencils (eq. 4.6),
   V = (M U)^{-T}, and the fast-diagonalization solve (eq. 4.7 / 4.9).
+* ``galerkin`` -- Gauss-quadrature Galerkin factors M, K (eq. 3.8) and the
+  convection factor H (after eq. 3.9), symmetric FD factors (V = U), and the
+  Galerkin convection-diffusion matrix on the deformed cube (Sec. 3.2).
 * ``fgmres``   -- flexible GMRES(m) with classical Gram-Schmidt and one
   reorthogonalisation, Givens least squares, true-residual restarts (the paper
   names GMRES as the Krylov method for the nonsymmetric system, Sec. 3).

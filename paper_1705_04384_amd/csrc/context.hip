@@ -418,6 +418,13 @@ extern "C" int fdg_set_prec_factors(fdg_ctx *c, int l, const double *U, const do
   return FDG_OK;
 }
 
+// Symmetric FD (Sec. 4, after eq. 4.6): U M-orthonormal, so V = U.  The first pass
+// reads V^T row by row and the last reads U row by row, so the device keeps U in both
+// layouts, as for a general pencil.
+extern "C" int fdg_set_prec_factors_sym(fdg_ctx *c, int l, const double *U, const double *lambda) {
+  return fdg_set_prec_factors(c, l, U, U, lambda);
+}
+
 extern "C" int fdg_set_precision(fdg_ctx *c, int prec) {
   clear_error();
   if (!c) return set_error(FDG_EINVAL, "set_precision: NULL context");

@@ -430,19 +430,32 @@ __global__ __launch_bounds__(kBlock) void k_kron2_window(CBatch x, MBatch y, int
   }
 }
 
+// ELL (slot-major: slot t of row r at t * ld + r).  S lanes share a row: a wave covers
+// R = 64 / S consecutive rows, lane group g (lanes g R .. g R + R - 1) takes slots
+// g, g + S, ..., so every group reads R consecutive entries of a slot; the S partial
+// sums of a row are then added by a butterfly over the groups.  Wide rows (the Galerkin
+// (2p+1)^3 stencil) need S > 1 to keep enough loads in flight; the order of the sum is
+// fixed for a given width and S.
+template <int S>
 __global__ __launch_bounds__(kBlock) void k_ell_f64(CBatch x, MBatch y, int64_t nrows, int64_t ld, int width,
                                                     const int32_t *__restrict__ col,
                                                     const double *__restrict__ val) {
-  const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (row >= nrows) return;
+  constexpr int R = 64 / S;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / R;
+  const int64_t row = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) / S + (lane % R);
+  const bool ok = row < nrows;
   const int64_t b = blockIdx.y;
   const double *__restrict__ xb = x.at(b);
   double acc = 0.0;
-  for (int t = 0; t < width; ++t) {
-    const int64_t e = (int64_t)t * ld + row;
-    acc = fma(val[e], xb[col[e]], acc);
-  }
-  y.at(b)[row] = acc;
+  if (ok)
+    for (int t = g; t < width; t += S) {
+      const int64_t e = (int64_t)t * ld + row;
+      acc = fma(val[e], xb[col[e]], acc);
+    }
+#pragma unroll
+  for (int m = R; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
+  if (ok && g == 0) y.at(b)[row] = acc;
 }
 
 // One-pass 3D form, one wave per plane.  A workgroup of 8 waves owns a tile of 64
@@ -730,10 +743,30 @@ bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int
   return true;
 }
 
+// Lanes per row: doubled (up to 4) while the launch has fewer than ~400K lanes and each
+// lane keeps at least 16 slots.  Measured on MI355X: the 27-wide collocation rows at
+// N = 96^3 run best with 1 lane per row (4.8 TB/s); the 343-wide Galerkin rows with 4 at
+// N = 48^3 (4.4 TB/s against 1.7 with 1) and 2 at N = 64^3 (4.8 TB/s).
+#ifndef FDG_ELL_SPLIT
+#define FDG_ELL_SPLIT 0
+#endif
+int ell_split(int64_t nrows, int width) {
+  if (FDG_ELL_SPLIT > 0) return FDG_ELL_SPLIT;
+  int S = 1;
+  while (S < 4 && nrows * S < 400000 && width >= 32 * S) S *= 2;
+  return S;
+}
+
 void launch_ell_matvec_f64(hipStream_t s, CBatch x, MBatch y, int64_t nrows, int64_t ld, int width,
                            const int32_t *col, const double *val, int64_t nbatch) {
-  hipLaunchKernelGGL(k_ell_f64, dim3(cdiv(nrows, kBlock), (unsigned)nbatch), dim3(kBlock), 0, s, x, y, nrows, ld,
-                     width, col, val);
+  const int S = ell_split(nrows, width);
+  const dim3 grid(cdiv(nrows * S, kBlock), (unsigned)nbatch), blk(kBlock);
+  switch (S) {
+    case 1: hipLaunchKernelGGL(k_ell_f64<1>, grid, blk, 0, s, x, y, nrows, ld, width, col, val); break;
+    case 2: hipLaunchKernelGGL(k_ell_f64<2>, grid, blk, 0, s, x, y, nrows, ld, width, col, val); break;
+    case 4: hipLaunchKernelGGL(k_ell_f64<4>, grid, blk, 0, s, x, y, nrows, ld, width, col, val); break;
+    default: hipLaunchKernelGGL(k_ell_f64<8>, grid, blk, 0, s, x, y, nrows, ld, width, col, val); break;
+  }
 }
 
 }  // namespace fdg

@@ -10,12 +10,10 @@
 #include <vector>
 
 #include "common.h"
+#include "spline_eval.h"
 
 namespace fdg {
-namespace {
 
-// Open uniform knot vector with E spans, kept as integer numerators over E:
-// p+1 zeros, 1..E-1, p+1 copies of E.  Returns the numerators (E + 2p + 1 entries).
 std::vector<int64_t> open_knots(int p, int E) {
   std::vector<int64_t> k;
   k.reserve(E + 2 * p + 1);
@@ -24,15 +22,6 @@ std::vector<int64_t> open_knots(int p, int E) {
   for (int i = 0; i <= p; ++i) k.push_back(E);
   return k;
 }
-
-// Local evaluation of the p+1 B-splines that can be non-zero at x, with their first
-// and second derivatives.  span is the index s with xi_s <= x < xi_{s+1} (the last
-// non-empty span when x is the right end); on return f[r][t] holds the r-th
-// derivative of B_{s-p+t}.
-struct LocalBasis {
-  int span;
-  double f[3][16];
-};
 
 void eval_local(const std::vector<double> &xi, int p, double x, LocalBasis &out) {
   const int nk = (int)xi.size();
@@ -94,7 +83,6 @@ void eval_local(const std::vector<double> &xi, int p, double x, LocalBasis &out)
   }
 }
 
-}  // namespace
 
 // Dense univariate factors; shared by the C entry point and the CSR assembly.
 int colloc_factors_impl(int p, int n, std::vector<double> &M, std::vector<double> &K,

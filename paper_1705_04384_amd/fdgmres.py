@@ -51,7 +51,8 @@ EXPORTS = [
     "fdg_footprint_bytes", "fdg_timer_enable", "fdg_timer_read", "fdg_status_str", "fdg_last_error",
     "fdg_server_create", "fdg_server_destroy", "fdg_server_run_bytes", "fdg_server_admit", "fdg_server_step",
     "fdg_server_pending", "fdg_server_stats", "fdg_set_operator_mapped", "fdg_set_operator_fields",
-    "fdg_deformed_coefficients",
+    "fdg_deformed_coefficients", "fdg_factor_pencil_sym", "fdg_galerkin_factors", "fdg_galerkin_csr",
+    "fdg_set_prec_factors_sym",
 ]
 
 
@@ -96,6 +97,11 @@ def lib():
     L.fdg_set_operator_mapped.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
     L.fdg_set_operator_fields.argtypes = [ctypes.c_void_p, _dp]
     L.fdg_deformed_coefficients.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+    L.fdg_factor_pencil_sym.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.fdg_galerkin_factors.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+    L.fdg_galerkin_csr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double, _i64p,
+                                   _i64p, _i32p, _dp]
+    L.fdg_set_prec_factors_sym.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     L.fdg_status_str.argtypes = [ctypes.c_int]
     L.fdg_status_str.restype = ctypes.c_char_p
     L.fdg_last_error.argtypes = []
@@ -134,6 +140,40 @@ def factor_pencil(K, M, want_cond=True):
     _check(lib().fdg_factor_pencil(n, _ptr(K), _ptr(M), _ptr(U), _ptr(V), _ptr(lam),
                                    ctypes.byref(c) if want_cond else None))
     return U, V, lam, (c.value if want_cond else None)
+
+
+def factor_pencil_sym(K, M):
+    """(U, lam) with K U = M U diag(lam), U^T M U = I: the symmetric FD factors (V = U)."""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    n = K.shape[0]
+    U = np.zeros((n, n)); lam = np.zeros(n)
+    _check(lib().fdg_factor_pencil_sym(n, _ptr(K), _ptr(M), _ptr(U), _ptr(lam)))
+    return U, lam
+
+
+def galerkin_factors(p, n, w0=0.0, w1=0.0):
+    """(M, K, H): univariate Galerkin factors of eq. 3.8 and the convection factor of the
+    affine wind w0 + w1 z (after eq. 3.9)."""
+    M = np.zeros((n, n)); K = np.zeros((n, n)); H = np.zeros((n, n))
+    _check(lib().fdg_galerkin_factors(p, n, w0, w1, _ptr(M), _ptr(K), _ptr(H)))
+    return M, K, H
+
+
+def galerkin_csr(p, n, amp=0.0, wind=None, beta=0.0):
+    """CSR (rowptr, col, val) of the Galerkin matrix of -Lap u + w . grad u on the
+    deformed cube (wind = (c_1, c_2, c_3) or None)."""
+    L = lib()
+    w = None if wind is None else np.ascontiguousarray(wind, dtype=np.float64)
+    wp = None if w is None else _ptr(w)
+    nnz = ctypes.c_int64()
+    _check(L.fdg_galerkin_csr(p, n, amp, wp, beta, ctypes.byref(nnz), None, None, None))
+    rowptr = np.zeros(n ** 3 + 1, dtype=np.int64)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value, dtype=np.float64)
+    _check(L.fdg_galerkin_csr(p, n, amp, wp, beta, ctypes.byref(nnz), _ptr(rowptr, _i64p), _ptr(col, _i32p),
+                              _ptr(val)))
+    return rowptr, col, val
 
 
 def deformed_csr(p, n, amp=0.1, band=False):
@@ -213,6 +253,11 @@ class Context:
         V = np.ascontiguousarray(V, dtype=np.float64)
         lam = np.ascontiguousarray(lam, dtype=np.float64)
         _check(lib().fdg_set_prec_factors(self._h, l, _ptr(U), _ptr(V), _ptr(lam)))
+
+    def set_prec_factors_sym(self, l, U, lam):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        _check(lib().fdg_set_prec_factors_sym(self._h, l, _ptr(U), _ptr(lam)))
 
     def set_precision(self, prec):
         _check(lib().fdg_set_precision(self._h, prec))
@@ -365,4 +410,27 @@ def mapped_problem(p, n, amp=0.1, stream=None, prec=PREC_FP64):
     ctx.set_operator_fields(deformed_coefficients(p, n, amp))
     ctx.set_precision(prec)
     ctx.tau = tau
+    return ctx
+
+
+def galerkin_problem(p, n, amp=0.0, wind=None, beta=0.0, wind_prec=True, stream=None, prec=PREC_FP64):
+    """Context for the Galerkin convection-diffusion problem on the deformed cube (CSR
+    operator, Sec. 3.2).  The preconditioner is the unit-cube Galerkin discretization: with
+    wind_prec and a wind (c_1, c_2, c_3), direction l uses K_l + H_l for the univariate
+    wind c_l (1 + z) (eq. 3.9, nonsymmetric FD); otherwise the wind is dropped (eq. 3.7,
+    symmetric FD with V = U)."""
+    ctx = Context(3, n, stream=stream)
+    for l in range(3):
+        cl = 0.0 if wind is None else float(wind[l])
+        M, K, H = galerkin_factors(p, n, cl, cl)
+        if wind_prec and cl != 0.0:
+            U, V, lam, _ = factor_pencil(K + H, M, want_cond=False)
+            ctx.set_prec_factors(l, U, V, lam)
+        else:
+            U, lam = factor_pencil_sym(K, M)
+            ctx.set_prec_factors_sym(l, U, lam)
+    rowptr, col, val = galerkin_csr(p, n, amp, wind, beta)
+    ctx.set_operator_csr(rowptr, col, val)
+    ctx.set_precision(prec)
+    ctx.nnz = len(col)
     return ctx

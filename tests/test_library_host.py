@@ -129,3 +129,65 @@ def test_deformed_coefficient_fields_match_oracle(p, n):
     want = np.stack([C[:, 0, 0], C[:, 1, 1], C[:, 2, 2], 2 * C[:, 0, 1], 2 * C[:, 0, 2], 2 * C[:, 1, 2],
                      g[:, 0], g[:, 1], g[:, 2]])
     assert np.allclose(coef, want, rtol=1e-12, atol=1e-12)
+
+
+# ---- Galerkin setup (Sec. 3.2) and the symmetric FD factors -----------------------------
+
+from oracle import galerkin  # noqa: E402
+
+
+@pytest.mark.parametrize("p,n,w0,w1", [(1, 5, 0.0, 0.0), (2, 16, 2.0, 3.0), (3, 48, 10.0, 10.0),
+                                       (4, 33, -1.0, 0.5), (6, 24, 5.0, 5.0)])
+def test_galerkin_factors_match_oracle(p, n, w0, w1):
+    _lib()
+    M, K, H = fdg.galerkin_factors(p, n, w0, w1)
+    Mo, Ko, Ho = galerkin.galerkin_factors(p, n, lambda z: w0 + w1 * z)
+    for a, b in ((M, Mo), (K, Ko), (H, Ho)):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max() + 1e-300
+
+
+@pytest.mark.parametrize("p,n", [(2, 16), (3, 48), (4, 128), (6, 64)])
+def test_factor_pencil_sym_is_m_orthonormal(p, n):
+    _lib()
+    M, K, _ = fdg.galerkin_factors(p, n)
+    U, lam = fdg.factor_pencil_sym(K, M)
+    _, lo = galerkin.factor_pencil_sym(K, M)
+    assert np.abs(lam - lo).max() <= 1e-12 * lo.max()
+    assert np.abs(U.T @ M @ U - np.eye(n)).max() <= 1e-12
+    assert np.abs(K @ U - M @ U * lam).max() <= 1e-10 * lam.max()
+    assert np.all(np.diff(lam) >= 0)
+
+
+def test_factor_pencil_sym_rejects_bad_pencils():
+    _lib()
+    M, K, H = fdg.galerkin_factors(3, 10, 1.0, 1.0)
+    with pytest.raises(fdg.FdgError):          # K + H is not symmetric
+        fdg.factor_pencil_sym(K + H, M)
+    with pytest.raises(fdg.FdgError):          # -M is not positive definite
+        fdg.factor_pencil_sym(K, -M)
+
+
+def test_coarse_wind_pencil_is_complex():
+    # the nonsymmetric FD needs real eigenvalues; a strong wind on a coarse mesh breaks that
+    _lib()
+    M, K, H = fdg.galerkin_factors(3, 8, 10.0, 10.0)
+    with pytest.raises(fdg.FdgError) as e:
+        fdg.factor_pencil(K + H, M)
+    assert e.value.status == -4
+
+
+@pytest.mark.parametrize("p,n,amp,wind,beta", [(2, 5, 0.0, None, 0.0), (3, 6, 0.1, (3.0, 4.0, 5.0), 0.5),
+                                                (2, 7, 0.1, (1.0, -2.0, 3.0), 0.3), (1, 4, 0.05, (1.0, 1.0, 1.0), 1.0)])
+def test_galerkin_csr_matches_oracle(p, n, amp, wind, beta):
+    _lib()
+    rowptr, col, val = fdg.galerkin_csr(p, n, amp, wind, beta)
+    A = sp.csr_matrix((val, col, rowptr), shape=(n ** 3, n ** 3))
+    Ao = galerkin.galerkin_operator(p, n, amp, wind if wind else (0.0, 0.0, 0.0), beta)
+    assert abs(A - Ao).max() <= 1e-13 * abs(Ao).max()
+    # pattern: the clipped (2p+1)^3 stencil, columns ascending in every row
+    i = np.arange(n)
+    w = np.minimum(n - 1, i + p) - np.maximum(0, i - p) + 1
+    want = (w[None, None, :] * w[None, :, None] * w[:, None, None]).ravel()
+    assert np.array_equal(np.diff(rowptr), want)
+    for r in range(0, n ** 3, 7):
+        assert np.all(np.diff(col[rowptr[r]:rowptr[r + 1]]) > 0)
