@@ -63,6 +63,9 @@ typedef struct {
   double rel_res_est;    /* |g_{j+1}| / ||b|| after the last iteration                      */
   double rel_res_true;   /* ||b - A x||_2 / ||b||_2, recomputed in FP64 at the end          */
   double ms_total;       /* wall time of the call, host clock                               */
+  int half_steps;        /* BiCGStab: half steps done (the paper's count is half_steps / 2,
+                            "k + 0.5" when the last iteration stopped after its BiCG half);
+                            0 for flexible GMRES                                           */
 } fdg_info;
 
 /* ------------------------------------------------------------------------------------
@@ -201,6 +204,20 @@ int fdg_matvec(fdg_ctx *ctx, const double *x, double *y);
  * info may be NULL. */
 int fdg_solve(fdg_ctx *ctx, const double *b, double *x, double rtol, int restart,
               int maxit, int flags, fdg_info *info);
+
+/* Right-preconditioned BiCGStab for A x = b (Sec. 5: the Krylov method of the paper's
+ * experiments; van der Vorst's method: per iteration one BiCG half step with
+ * p^ = P^{-1} p, then one GMRES(1) half step with s^ = P^{-1} s), batch must be 1.
+ * b, x: device, N FP64.  x0 = 0 unless flags has FDG_SOLVE_USE_X0; shadow residual
+ * r~ = r_0.  After each half step the recursively updated residual is compared with
+ * rtol ||b||, and a pass is confirmed by the true FP64 residual ||b - A x||; converged
+ * iff that holds.  info->iterations counts full iterations, info->half_steps half steps.
+ * maxit bounds full iterations; with FDG_SOLVE_FIXED_ITERS exactly maxit run (no
+ * convergence test).  A breakdown (r~.r = 0, r~.v = 0 or omega = 0) stops with the
+ * current iterate, info->breakdown = 1 and FDG_NOT_CONVERGED.  Device memory: 8 N
+ * doubles per context, allocated on first use.  Blocks until done. */
+int fdg_bicgstab(fdg_ctx *ctx, const double *b, double *x, double rtol, int maxit, int flags,
+                 fdg_info *info);
 
 /* Device bytes a context of this shape needs for a solve with the given restart
  * (factors, operator excluded for CSR, Krylov bases, scratch). */

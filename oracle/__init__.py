@@ -24,6 +24,8 @@ Modules (each function cites the passage it follows):
 * ``galerkin`` -- Gauss-quadrature Galerkin factors M, K (eq. 3.8) and the
   convection factor H (after eq. 3.9), symmetric FD factors (V = U), and the
   Galerkin convection-diffusion matrix on the deformed cube (Sec. 3.2).
+* ``bicgstab`` -- right-preconditioned BiCGStab (the Krylov method of the
+  experiments, Sec. 5) with the k + 0.5 half-step count.
 * ``fgmres``   -- flexible GMRES(m) with classical Gram-Schmidt and one
   reorthogonalisation, Givens least squares, true-residual restarts (the paper
   names GMRES as the Krylov method for the nonsymmetric system, Sec. 3).

@@ -57,6 +57,9 @@ struct fdg_ctx {
   double *hpin = nullptr;      // pinned, device-mapped host memory for the scalars the host needs
   double *hpin_dev = nullptr;  // its device address
   hipEvent_t phase_ev = nullptr;  // end of a solve phase, polled by the host
+  double *bicg = nullptr;          // BiCGStab vectors and partials (allocated on first use)
+  double *bicg_host = nullptr;     // BiCGStab host-mapped scalars and its device address
+  double *bicg_host_dev = nullptr;
   fdg::TimerState timers[fdg::kTimerClasses];
 };
 
@@ -169,6 +172,8 @@ int residual_entries(fdg_ctx *c, const Exec &ex, CBatch x, CBatch b, MBatch r, i
 int residual_partials(const fdg_ctx *c);
 // FDG_OK when the preconditioner factors and the operator are set, else FDG_ENOTREADY.
 int ctx_ready(fdg_ctx *c);
+// Apply/matvec scratch t1, t2 (and t32a, t32b for a reduced-precision context).
+int ensure_solve_workspace(fdg_ctx *c);
 // The context's apply and matvec accept gathered batches (FP64 fused FD passes and a
 // matvec form with per-entry scratch).
 bool groupable(const fdg_ctx *c);

@@ -86,6 +86,12 @@ int ctx_ready(fdg_ctx *c) {
   return st;
 }
 
+int ensure_solve_workspace(fdg_ctx *c) {
+  int st = ensure_workspace(c);
+  if (st == FDG_OK && c->prec != FDG_PREC_FP64) st = ensure_lowp_workspace(c);
+  return st;
+}
+
 namespace {
 KronBands ctx_bands(const fdg_ctx *c) {
   KronBands bd;
@@ -351,6 +357,8 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
   dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol);
   dfree(c->hbuf); dfree(c->scal);
   if (c->hpin) (void)hipHostFree(c->hpin);
+  dfree(c->bicg);
+  if (c->bicg_host) (void)hipHostFree(c->bicg_host);
   if (c->phase_ev) (void)hipEventDestroy(c->phase_ev);
   for (auto &t : c->timers) {
     for (auto e : t.pool) (void)hipEventDestroy(e);

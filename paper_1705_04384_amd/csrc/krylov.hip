@@ -18,48 +18,14 @@
 
 #include "batch_addr.h"
 #include "kernels.h"
+#include "reduce.h"
 
 namespace fdg {
 
 namespace {
 
-constexpr int kRed = 1024;  // threads of the reduction-producing kernels
-constexpr int kRedWaves = kRed / 64;
 constexpr int kBlock = 256;  // threads of the streaming kernels
 constexpr int kQB = 8;       // basis vectors per register batch
-constexpr int kMaxG = 256;
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Contiguous chunk of block g; chunks are multiples of 2 * kRed elements.
-__device__ inline void chunk_of(int64_t N, int G, int g, int64_t &beg, int64_t &end) {
-  int64_t chunk = (N + G - 1) / G;
-  chunk = (chunk + 2 * kRed - 1) / (2 * kRed) * (2 * kRed);
-  beg = (int64_t)g * chunk;
-  if (beg > N) beg = N;
-  end = beg + chunk < N ? beg + chunk : N;
-}
-
-// Fixed-order sum of the G <= 256 partials of component q (partial g of component q at
-// P[g * ldp + q]), valid in every lane: lane l adds g = l, l + 64, l + 128, l + 192 in
-// order, then an xor butterfly.
-__device__ inline double sum_partials(const double *P, int G, int ldp, int q) {
-  const int lane = threadIdx.x & 63;
-  double v[kMaxG / 64];
-#pragma unroll
-  for (int k = 0; k < kMaxG / 64; ++k) {
-    const int g = lane + 64 * k;
-    v[k] = g < G ? P[(int64_t)g * ldp + q] : 0.0;
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < kMaxG / 64; ++k) s += v[k];
-  return wave_sum(s);
-}
 
 // hs[q] = sum of the partials of component q, q < ncomp (all waves of the block help).
 __device__ inline void reduce_into(const double *P, int G, int ldp, int ncomp, double *hs, int nwaves) {

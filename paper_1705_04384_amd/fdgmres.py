@@ -35,7 +35,7 @@ class FdgError(RuntimeError):
 class fdg_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("breakdown", ctypes.c_int), ("rel_res_est", ctypes.c_double),
-                ("rel_res_true", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("rel_res_true", ctypes.c_double), ("ms_total", ctypes.c_double), ("half_steps", ctypes.c_int)]
 
 
 class fdg_done(ctypes.Structure):
@@ -52,7 +52,7 @@ EXPORTS = [
     "fdg_server_create", "fdg_server_destroy", "fdg_server_run_bytes", "fdg_server_admit", "fdg_server_step",
     "fdg_server_pending", "fdg_server_stats", "fdg_set_operator_mapped", "fdg_set_operator_fields",
     "fdg_deformed_coefficients", "fdg_factor_pencil_sym", "fdg_galerkin_factors", "fdg_galerkin_csr",
-    "fdg_set_prec_factors_sym",
+    "fdg_set_prec_factors_sym", "fdg_bicgstab",
 ]
 
 
@@ -102,6 +102,8 @@ def lib():
     L.fdg_galerkin_csr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double, _i64p,
                                    _i64p, _i32p, _dp]
     L.fdg_set_prec_factors_sym.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
+    L.fdg_bicgstab.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                               ctypes.c_int, ctypes.POINTER(fdg_info)]
     L.fdg_status_str.argtypes = [ctypes.c_int]
     L.fdg_status_str.restype = ctypes.c_char_p
     L.fdg_last_error.argtypes = []
@@ -296,6 +298,16 @@ class Context:
         return {"iterations": info.iterations, "restarts": info.restarts, "converged": info.converged,
                 "breakdown": info.breakdown, "rel_res_est": info.rel_res_est, "rel_res_true": info.rel_res_true,
                 "ms_total": info.ms_total}
+
+    def bicgstab(self, b, x, rtol=1e-8, maxit=1000, flags=0):
+        """Preconditioned BiCGStab; "iterations" is the paper's count (k or k + 0.5)."""
+        info = fdg_info()
+        st = _lib.fdg_bicgstab(self._h, _dev_ptr(b), _dev_ptr(x), rtol, maxit, flags, ctypes.byref(info))
+        if st != FDG_OK and st != FDG_NOT_CONVERGED:
+            _check(st)
+        return {"iterations": info.half_steps / 2.0, "full_iterations": info.iterations,
+                "half_steps": info.half_steps, "converged": info.converged, "breakdown": info.breakdown,
+                "rel_res_est": info.rel_res_est, "rel_res_true": info.rel_res_true, "ms_total": info.ms_total}
 
     def timer_enable(self, kernel, on=True):
         _check(lib().fdg_timer_enable(self._h, kernel, int(on)))
