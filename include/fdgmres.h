@@ -219,6 +219,13 @@ int fdg_solve(fdg_ctx *ctx, const double *b, double *x, double rtol, int restart
 int fdg_bicgstab(fdg_ctx *ctx, const double *b, double *x, double rtol, int maxit, int flags,
                  fdg_info *info);
 
+/* Bytes of operator data one matvec of the context reads (stored matrix slots, implicit
+ * or explicit column indices, coefficient fields or factor bands; not x and y), 0 when
+ * no operator is set.  An assembled operator whose pattern is the product of
+ * per-direction windows on the tensor grid is stored without column indices (8 bytes
+ * per slot); any other pattern as ELL (12 bytes per slot). */
+size_t fdg_operator_bytes(const fdg_ctx *ctx);
+
 /* Device bytes a context of this shape needs for a solve with the given restart
  * (factors, operator excluded for CSR, Krylov bases, scratch). */
 size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart);

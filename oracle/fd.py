@@ -22,16 +22,27 @@ class ComplexPencilError(ValueError):
     """The pencil has non-real or non-positive eigenvalues (outside Remark 1's assumption)."""
 
 
-def factor_pencil(K, M):
-    """U, V, lam for the pencil (K, M): K U = M U diag(lam), V = (M U)^{-T} (eq. 4.6 and the line after it)."""
+def factor_pencil(K, M, allow_complex=False):
+    """U, V, lam for the pencil (K, M): K U = M U diag(lam), V = (M U)^{-T} (eq. 4.6 and the line after it).
+
+    With allow_complex, a pencil with complex-conjugate eigenvalue pairs is accepted
+    (Sec. 4 after eq. 4.7: the decomposition then needs complex arithmetic, or 2 x 2
+    real blocks in D); U, V and lam are returned complex, ordered by real part, and every
+    real part must be positive."""
     lam, U = sla.eig(K, M)
     scale = np.max(np.abs(lam))
-    if np.max(np.abs(lam.imag)) > 1e-10 * scale:
+    is_complex = np.max(np.abs(lam.imag)) > 1e-10 * scale
+    if is_complex and not allow_complex:
         raise ComplexPencilError("pencil has complex eigenvalues")
+    if np.min(lam.real) <= 0.0:
+        raise ComplexPencilError("pencil has eigenvalues with non-positive real part")
+    if is_complex:
+        order = np.lexsort((lam.imag, lam.real))
+        U = U[:, order]
+        U = U / np.linalg.norm(U, axis=0)
+        return U, np.linalg.inv(M @ U).T, lam[order]
     lam = lam.real
     U = U.real
-    if np.min(lam) <= 0.0:
-        raise ComplexPencilError("pencil has non-positive eigenvalues")
     order = np.argsort(lam, kind="stable")
     lam = lam[order]
     U = U[:, order]
@@ -104,7 +115,9 @@ def eig_sum(lams):
 
 
 def fd_apply(Us, Vs, lams, b):
-    """s = P^{-1} b by eq. 4.7 / 4.9.  Us, Vs, lams are per direction l = 1..d; b is i_1-fastest."""
+    """s = P^{-1} b by eq. 4.7 / 4.9.  Us, Vs, lams are per direction l = 1..d; b is i_1-fastest.
+    With complex factors (conjugate-closed spectra) the arithmetic is complex and the
+    result, real up to rounding, is returned as its real part."""
     d = len(Us)
     shape = [len(lams[l]) for l in reversed(range(d))]
     X = np.asarray(b, dtype=np.float64).reshape(shape)
@@ -113,6 +126,8 @@ def fd_apply(Us, Vs, lams, b):
     X = X / eig_sum(lams)                           # diagonal solve
     for l in range(d):                              # (U_d x ... x U_1) s~
         X = mode_product(X, Us[l], l + 1)
+    if np.iscomplexobj(X):
+        X = X.real
     return X.ravel()
 
 

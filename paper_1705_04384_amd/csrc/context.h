@@ -48,6 +48,9 @@ struct fdg_ctx {
   int32_t *ell_col = nullptr;
   double *ell_val = nullptr;
   int ell_width = 0;
+  bool ell_tensor = false;       // implicit columns: windows lo_l, widths ell_tw (see set_operator_csr)
+  int32_t *ell_lo = nullptr;     // 3 n window starts (direction-major)
+  int ell_tw[3] = {1, 1, 1};
   // workspace
   double *t1 = nullptr, *t2 = nullptr;
   void *t32a = nullptr, *t32b = nullptr;

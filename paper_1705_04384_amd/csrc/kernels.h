@@ -62,6 +62,13 @@ bool kron_fused_ok(int n, int64_t nbatch, const KronBands &bands);
 void launch_ell_matvec_f64(hipStream_t s, CBatch x, MBatch y, int64_t nrows, int64_t ld, int width,
                            const int32_t *col, const double *val, int64_t nbatch);
 
+// Slot-major ELL with implicit columns, for a matrix on the n^d tensor grid whose row
+// (i1, i2, i3) couples exactly the columns (lo1[i1] + t1, lo2[i2] + t2, lo3[i3] + t3),
+// t_l < w[l] (lo_l[i] + w[l] <= n): slot t = (t3 w2 + t2) w1 + t1 of row r at
+// val[t * nrows + r].  For d = 2, w[2] = 1 and lo3 is all zero.
+void launch_ell_tensor_f64(hipStream_t s, CBatch x, MBatch y, int n, int d, const int w[3],
+                           const int32_t *lo, const double *val, int64_t nbatch);
+
 // ---- Krylov vector kernels --------------------------------------------------------------
 // Vectors of a basis are stored q-major: element (q, b, i) at V[q*ldv + b*N + i].
 // Partial sums of batch entry b, block g, component q at P[(b*G + g)*nv + q]

@@ -743,6 +743,38 @@ bool launch_kron_matvec_f64(hipStream_t s, CBatch x, MBatch y, int d, int n, int
   return true;
 }
 
+// The same with implicit columns: row r = (i1, i2, i3) reads x along the rows of its
+// window, w1 consecutive elements at a time; lane group g takes window rows
+// q = t3 w2 + t2 = g, g + S, ...  lo holds lo1 (n), lo2 (n), lo3 (n) back to back.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_ell_tensor_f64(CBatch x, MBatch y, int n, int64_t nrows, int w1,
+                                                           int w2, int w3, const int32_t *__restrict__ lo,
+                                                           const double *__restrict__ val) {
+  constexpr int R = 64 / S;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / R;
+  const int64_t row = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) / S + (lane % R);
+  const bool ok = row < nrows;
+  const int64_t b = blockIdx.y;
+  const double *__restrict__ xb = x.at(b);
+  const int64_t n2 = (int64_t)n * n;
+  double acc = 0.0;
+  if (ok) {
+    const int i1 = (int)(row % n), i2 = (int)((row / n) % n), i3 = (int)(row / n2);
+    const double *__restrict__ x0 = xb + lo[i1] + (int64_t)n * lo[n + i2] + n2 * lo[2 * n + i3];
+    const int nq = w2 * w3;
+    for (int q = g; q < nq; q += S) {
+      const int t3 = q / w2, t2 = q - t3 * w2;
+      const double *__restrict__ xr = x0 + (int64_t)n * t2 + n2 * t3;
+      const double *__restrict__ vr = val + (int64_t)q * w1 * nrows + row;
+      for (int t1 = 0; t1 < w1; ++t1) acc = fma(vr[(int64_t)t1 * nrows], xr[t1], acc);
+    }
+  }
+#pragma unroll
+  for (int m = R; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
+  if (ok && g == 0) y.at(b)[row] = acc;
+}
+
 // Lanes per row: doubled (up to 4) while the launch has fewer than ~400K lanes and each
 // lane keeps at least 16 slots.  Measured on MI355X: the 27-wide collocation rows at
 // N = 96^3 run best with 1 lane per row (4.8 TB/s); the 343-wide Galerkin rows with 4 at
@@ -766,6 +798,20 @@ void launch_ell_matvec_f64(hipStream_t s, CBatch x, MBatch y, int64_t nrows, int
     case 2: hipLaunchKernelGGL(k_ell_f64<2>, grid, blk, 0, s, x, y, nrows, ld, width, col, val); break;
     case 4: hipLaunchKernelGGL(k_ell_f64<4>, grid, blk, 0, s, x, y, nrows, ld, width, col, val); break;
     default: hipLaunchKernelGGL(k_ell_f64<8>, grid, blk, 0, s, x, y, nrows, ld, width, col, val); break;
+  }
+}
+
+void launch_ell_tensor_f64(hipStream_t s, CBatch x, MBatch y, int n, int d, const int w[3], const int32_t *lo,
+                           const double *val, int64_t nbatch) {
+  const int64_t nrows = d == 3 ? (int64_t)n * n * n : (int64_t)n * n;
+  const int width = w[0] * w[1] * w[2];
+  const int S = ell_split(nrows, width);
+  const dim3 grid(cdiv(nrows * S, kBlock), (unsigned)nbatch), blk(kBlock);
+  switch (S) {
+    case 1: hipLaunchKernelGGL(k_ell_tensor_f64<1>, grid, blk, 0, s, x, y, n, nrows, w[0], w[1], w[2], lo, val); break;
+    case 2: hipLaunchKernelGGL(k_ell_tensor_f64<2>, grid, blk, 0, s, x, y, n, nrows, w[0], w[1], w[2], lo, val); break;
+    case 4: hipLaunchKernelGGL(k_ell_tensor_f64<4>, grid, blk, 0, s, x, y, n, nrows, w[0], w[1], w[2], lo, val); break;
+    default: hipLaunchKernelGGL(k_ell_tensor_f64<8>, grid, blk, 0, s, x, y, n, nrows, w[0], w[1], w[2], lo, val); break;
   }
 }
 

@@ -52,7 +52,7 @@ EXPORTS = [
     "fdg_server_create", "fdg_server_destroy", "fdg_server_run_bytes", "fdg_server_admit", "fdg_server_step",
     "fdg_server_pending", "fdg_server_stats", "fdg_set_operator_mapped", "fdg_set_operator_fields",
     "fdg_deformed_coefficients", "fdg_factor_pencil_sym", "fdg_galerkin_factors", "fdg_galerkin_csr",
-    "fdg_set_prec_factors_sym", "fdg_bicgstab",
+    "fdg_set_prec_factors_sym", "fdg_bicgstab", "fdg_operator_bytes",
 ]
 
 
@@ -102,6 +102,8 @@ def lib():
     L.fdg_galerkin_csr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double, _i64p,
                                    _i64p, _i32p, _dp]
     L.fdg_set_prec_factors_sym.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
+    L.fdg_operator_bytes.argtypes = [ctypes.c_void_p]
+    L.fdg_operator_bytes.restype = ctypes.c_size_t
     L.fdg_bicgstab.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                                ctypes.c_int, ctypes.POINTER(fdg_info)]
     L.fdg_status_str.argtypes = [ctypes.c_int]
@@ -298,6 +300,10 @@ class Context:
         return {"iterations": info.iterations, "restarts": info.restarts, "converged": info.converged,
                 "breakdown": info.breakdown, "rel_res_est": info.rel_res_est, "rel_res_true": info.rel_res_true,
                 "ms_total": info.ms_total}
+
+    def operator_bytes(self):
+        """Bytes of operator data one matvec reads (x and y excluded)."""
+        return int(lib().fdg_operator_bytes(self._h))
 
     def bicgstab(self, b, x, rtol=1e-8, maxit=1000, flags=0):
         """Preconditioned BiCGStab; "iterations" is the paper's count (k or k + 0.5)."""

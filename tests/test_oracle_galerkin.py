@@ -211,3 +211,26 @@ def test_manufactured_solution_converges():
     rate = np.log(errs[0] / errs[1]) / np.log(Es[1] / Es[0])
     assert errs[1] < 1e-3
     assert rate >= p + 0.5, (errs, rate)
+
+
+@pytest.mark.parametrize("d,p,n,c", [(2, 3, 8, 10.0), (3, 3, 6, 12.0), (3, 2, 7, 20.0)])
+def test_complex_pencil_fd_brute_force(d, p, n, c):
+    # Sec. 4 after eq. 4.7: a pencil with complex eigenvalues (strong wind on a coarse
+    # mesh) is still diagonalized, in complex arithmetic; the FD then equals a dense solve
+    # of the Kronecker sum of eq. 3.9 and the result is real
+    M, K, H = G.galerkin_factors(p, n, G.affine_wind(c))
+    U, V, lam = fd.factor_pencil(K + H, M, allow_complex=True)
+    assert np.abs(lam.imag).max() > 1e-3 * np.abs(lam).max()        # genuinely complex
+    assert np.abs((K + H) @ U - M @ U * lam).max() <= 1e-10 * np.abs(lam).max()
+    P = colloc.unit_operator([M] * d, [K + H] * d).toarray()
+    b = np.random.default_rng(7).standard_normal(n ** d)
+    shape = [n] * d
+    X = b.reshape(shape).astype(complex)
+    for l in range(d):
+        X = fd.mode_product(X, V.T, l + 1)
+    X = X / fd.eig_sum([lam] * d)
+    for l in range(d):
+        X = fd.mode_product(X, U, l + 1)
+    assert np.abs(X.imag).max() <= 1e-12 * np.abs(X.real).max()
+    s = fd.fd_apply([U] * d, [V] * d, [lam] * d, b)
+    assert np.abs(s - np.linalg.solve(P, b)).max() <= 1e-11 * np.abs(s).max()
