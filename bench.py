@@ -298,6 +298,45 @@ def batched_2d(count):
     return out
 
 
+def complex_pairs_apply_128(reps=20):
+    """P^{-1} at n = 128 (3D) with real eigenvalues (three fused passes) against the same
+    shape with complex eigenvalue pairs in every direction (2 x 2 blocks of D: fused
+    passes for modes 1-2, mode-3 products around a separate block solve).  The factors
+    are synthetic (orthogonal U = V, every 4th index starting a pair): the cost does not
+    depend on their values."""
+    import numpy as np
+    import torch
+    from paper_1705_04384_amd import fdgmres, inputs
+    n = 128
+    rng = np.random.default_rng(5)
+    b = torch.from_numpy(inputs.rhs_normal(1, n ** 3)).cuda()
+    s = torch.empty_like(b)
+    out = {"workload": "P^-1 apply, 3D n=128, FP64, synthetic factors (orthogonal U = V)"}
+    for key, pairs in (("real_eigenvalues", False), ("complex_pairs", True)):
+        ctx = fdgmres.Context(3, n)
+        for l in range(3):
+            Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+            lam = np.sort(rng.uniform(1.0, 50.0, n))
+            mu = np.zeros(n)
+            if pairs:
+                for c in range(0, n - 1, 4):
+                    lam[c + 1] = lam[c]
+                    mu[c], mu[c + 1] = 2.0, -2.0
+            ctx.set_prec_factors_blocks(l, Q, Q, lam, mu)
+        for _ in range(3):
+            ctx.apply_prec(b, s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.apply_prec(b, s)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) / reps * 1e6
+        out[key] = {"us_per_apply": us, "tflops": 4 * 3 * n ** 4 / (us * 1e-6) / 1e12}
+        ctx.close()
+    out["slowdown"] = out["complex_pairs"]["us_per_apply"] / out["real_eigenvalues"]["us_per_apply"]
+    return out
+
+
 def precision_sweep_192():
     """Unit cube, p = 6, n = 192, FGMRES(50): P^-1 in FP64, FP32 and BF16 (FP32 accumulate).
     k* = the fixed iteration count at which the solution is within 1e-8 of the FP64 solve
@@ -475,6 +514,7 @@ def main():
         out["precision_sweep_192"] = precision_sweep_192()
         out["batched_2d_p3_n33"] = batched_2d(1000)
         out["galerkin_convection_p3_n48"] = galerkin_convection_48()
+        out["complex_pairs_apply_128"] = complex_pairs_apply_128()
     if not args.no_serve:
         out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:

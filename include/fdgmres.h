@@ -89,6 +89,18 @@ int fdg_colloc_factors(int p, int n, double *M, double *K, double *D1, double *t
 int fdg_factor_pencil(int n, const double *K, const double *M,
                       double *U, double *V, double *lambda, double *cond_u);
 
+/* The same factorization for a pencil whose eigenvalues may include complex-conjugate
+ * pairs (Sec. 4, the remark after eq. 4.7: D then has 2 x 2 real blocks).  A pair
+ * a +- ib occupies two adjacent columns c, c+1 of U, holding the real and imaginary parts
+ * of the eigenvector of a + ib (z = u + i v, phase chosen so u and v are orthogonal,
+ * |u|^2 + |v|^2 = 1); lambda[c] = lambda[c+1] = a, mu[c] = b > 0, mu[c+1] = -b, so that
+ * K U = M U D with D's block [[a, b], [-b, a]] at (c, c+1).  Real eigenvalues have
+ * mu = 0.  Units (a real eigenvalue or a pair) in ascending order of real part.  V, U,
+ * lambda, mu: host n*n, n*n, n, n outputs.  Errors as fdg_factor_pencil, with FDG_ECOMPLEX
+ * only for a non-positive real part. */
+int fdg_factor_pencil_blocks(int n, const double *K, const double *M, double *U, double *V,
+                             double *lambda, double *mu, double *cond_u);
+
 /* Symmetric FD factors (Sec. 4, after eq. 4.6) of a pencil with K symmetric and M
  * symmetric positive definite (e.g. the Galerkin factors of eq. 3.8): K U = M U
  * diag(lambda) with U^T M U = I, so that V = (M U)^{-T} = U.  Eigenvalues ascending.
@@ -153,6 +165,15 @@ int fdg_destroy(fdg_ctx *ctx);
  * over the directions could be <= 0 -- checked once all directions are set). */
 int fdg_set_prec_factors(fdg_ctx *ctx, int l, const double *U, const double *V,
                          const double *lambda);
+
+/* FD factors of direction l from fdg_factor_pencil_blocks: as fdg_set_prec_factors, plus
+ * mu (host n; NULL or all zero: real eigenvalues) marking complex pairs: mu[c] = b > 0,
+ * mu[c+1] = -b, lambda[c] = lambda[c+1] = a for the block [[a, b], [-b, a]] of a +- ib.
+ * The middle solve of eq. 4.9 then couples the two indices of every pair (a block solve
+ * instead of a divide); such a context needs FDG_PREC_FP64 and is not batched by the
+ * server.  Errors: FDG_EINVAL (malformed pairs), as fdg_set_prec_factors otherwise. */
+int fdg_set_prec_factors_blocks(fdg_ctx *ctx, int l, const double *U, const double *V,
+                                const double *lambda, const double *mu);
 
 /* Symmetric FD factors of direction l (U from fdg_factor_pencil_sym): V = U. */
 int fdg_set_prec_factors_sym(fdg_ctx *ctx, int l, const double *U, const double *lambda);

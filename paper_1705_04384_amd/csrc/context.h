@@ -35,6 +35,10 @@ struct fdg_ctx {
   uint16_t *Wv16[3] = {nullptr, nullptr, nullptr}, *Wu16[3] = {nullptr, nullptr, nullptr};
   float *lam32[3] = {nullptr, nullptr, nullptr};
   double lam_min[3] = {0, 0, 0};
+  // complex eigenvalue pairs (2 x 2 blocks of D_l): imaginary parts and index roles
+  bool pairs[3] = {false, false, false};
+  double *mu[3] = {nullptr, nullptr, nullptr};
+  int8_t *role[3] = {nullptr, nullptr, nullptr};
   // operator
   int op_kind = 0;  // 0 none, 1 Kronecker bands, 2 ELL, 3 mapped (matrix-free)
   bool have_op[3] = {false, false, false};
@@ -175,6 +179,8 @@ int residual_entries(fdg_ctx *c, const Exec &ex, CBatch x, CBatch b, MBatch r, i
 int residual_partials(const fdg_ctx *c);
 // FDG_OK when the preconditioner factors and the operator are set, else FDG_ENOTREADY.
 int ctx_ready(fdg_ctx *c);
+// Some direction's pencil has complex eigenvalue pairs (block-diagonal D).
+bool ctx_has_pairs(const fdg_ctx *c);
 // Apply/matvec scratch t1, t2 (and t32a, t32b for a reduced-precision context).
 int ensure_solve_workspace(fdg_ctx *c);
 // The context's apply and matvec accept gathered batches (FP64 fused FD passes and a

@@ -127,8 +127,14 @@ MappedOp ctx_mapped(const fdg_ctx *c) {
 }
 }  // namespace
 
+bool ctx_has_pairs(const fdg_ctx *c) {
+  for (int l = 0; l < c->d; ++l)
+    if (c->pairs[l]) return true;
+  return false;
+}
+
 bool groupable(const fdg_ctx *c) {
-  if (c->prec != FDG_PREC_FP64 || !fd_fused_supported(c->n)) return false;
+  if (c->prec != FDG_PREC_FP64 || !fd_fused_supported(c->n) || ctx_has_pairs(c)) return false;
   if (c->op_kind == 2 || c->d == 2) return true;
   if (c->op_kind == 3) return mapped_matvec_ok(c->n, kMaxGroupEntries, ctx_mapped(c));
   int w = 0;
@@ -137,11 +143,76 @@ bool groupable(const fdg_ctx *c) {
   return kron_fused_ok(c->n, kMaxGroupEntries, bd) || kron_two_pass_ok(c->d, c->n, kMaxGroupEntries, bd);
 }
 
+namespace {
+
+// P^{-1} when some D_l has 2 x 2 blocks (complex pairs, Sec. 4 after eq. 4.7): the mode
+// products are those of the real case; the middle solve couples the two indices of a
+// pair, across slabs and columns, so it runs as its own pass between the V^T and the U
+// products (3D: fused slab pass for modes 1-2, mode-3 product, block solve, mode-3
+// product, fused slab pass; 2D: slab pass, block solve, slab pass; n > 256: unfused).
+int apply_blocks(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nent, MBatch t1, MBatch t2,
+                 bool gathered) {
+  if (c->prec != FDG_PREC_FP64)
+    return set_error(FDG_EINVAL, "apply: pencils with complex eigenvalue pairs need the FP64 preconditioner");
+  if (gathered) return set_error(FDG_EINVAL, "apply: gathered batches need pencils with real eigenvalues");
+  const int n = c->n;
+  const int64_t n2 = (int64_t)n * n, B = nent;
+  const double *b = in.base;
+  double *s = out.base, *T1 = t1.base, *T2 = t2.base;
+  BlockEig e[3];
+  for (int l = 0; l < c->d; ++l) e[l] = BlockEig{c->lam[l], c->mu[l], c->role[l]};
+  TimedLaunch tl(c, 0, ex.stream, ex.timed);
+  auto mode = [&](const double *X, double *Y, const double *W, int l) {
+    if (l == 0)
+      launch_modeprod_f64(ex.stream, X, Y, W, c->ldw, n, B * (c->d == 3 ? n2 : n), 0, 1, n, 1);
+    else if (l == 1)
+      launch_modeprod_f64(ex.stream, X, Y, W, c->ldw, n, n, n2, n, 1, B * (c->d == 3 ? n : 1));
+    else
+      launch_modeprod_f64(ex.stream, X, Y, W, c->ldw, n, n2, n2 * n, n2, 1, B);
+  };
+  const bool a32 = al(b, 32) && al(s, 32) && (nent == 1 || (in.stride % 4 == 0 && out.stride % 4 == 0));
+  if (fd_fused_supported(n)) {
+    if (c->d == 3) {
+      launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, n, false, nullptr, nullptr, a32,
+                      nullptr, nullptr);
+      mode(T1, T2, c->Wv[2], 2);
+      launch_blockdiv_f64(ex.stream, T2, 3, n, B, e[0], e[1], e[2]);
+      mode(T2, T1, c->Wu[2], 2);
+      launch_slab_f64(ex.stream, as_const(t1), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, n, false, nullptr,
+                      nullptr, a32, nullptr, nullptr);
+    } else {
+      launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, 1, false, nullptr, nullptr, a32,
+                      nullptr, nullptr);
+      launch_blockdiv_f64(ex.stream, T1, 2, n, B, e[0], e[1], e[1]);
+      launch_slab_f64(ex.stream, as_const(t1), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, 1, false, nullptr,
+                      nullptr, a32, nullptr, nullptr);
+    }
+  } else if (c->d == 3) {
+    mode(b, T1, c->Wv[0], 0);
+    mode(T1, T2, c->Wv[1], 1);
+    mode(T2, T1, c->Wv[2], 2);
+    launch_blockdiv_f64(ex.stream, T1, 3, n, B, e[0], e[1], e[2]);
+    mode(T1, T2, c->Wu[0], 0);
+    mode(T2, T1, c->Wu[1], 1);
+    mode(T1, s, c->Wu[2], 2);
+  } else {
+    mode(b, T1, c->Wv[0], 0);
+    mode(T1, T2, c->Wv[1], 1);
+    launch_blockdiv_f64(ex.stream, T2, 2, n, B, e[0], e[1], e[1]);
+    mode(T2, T1, c->Wu[0], 0);
+    mode(T1, s, c->Wu[1], 1);
+  }
+  return hip_check(hipGetLastError(), "apply_prec launch");
+}
+
+}  // namespace
+
 int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nent, MBatch t1, MBatch t2,
                   void *t32a, void *t32b, bool gathered_aligned32) {
   const int n = c->n;
   const int64_t N = c->N;
   const bool gathered = in.ptrs || out.ptrs || t1.ptrs || t2.ptrs;
+  if (ctx_has_pairs(c)) return apply_blocks(c, ex, in, out, nent, t1, t2, gathered);
   if (c->prec == FDG_PREC_FP32 && fd_fused_supported(n)) {  // fused FP32 passes
     if (gathered) return set_error(FDG_EINVAL, "apply: gathered batches need the FP64 preconditioner");
     TimedLaunch tl(c, 0, ex.stream, ex.timed);
@@ -351,6 +422,7 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
     dfree(c->Wv[l]); dfree(c->Wu[l]); dfree(c->lam[l]);
     dfree(c->Wv32[l]); dfree(c->Wu32[l]); dfree(c->Wv16[l]); dfree(c->Wu16[l]); dfree(c->lam32[l]);
     dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandD[l]); dfree(c->bandlo[l]);
+    dfree(c->mu[l]); dfree(c->role[l]);
   }
   dfree(c->fields);
   dfree(c->ell_col); dfree(c->ell_val); dfree(c->ell_lo);
@@ -415,6 +487,7 @@ extern "C" int fdg_set_prec_factors(fdg_ctx *c, int l, const double *U, const do
   HIPCHK(hipMemcpy(c->Wu16[l], bu.data(), bu.size() * 2, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->lam32[l], fl.data(), fl.size() * 4, hipMemcpyHostToDevice));
   c->have_factor[l] = true;
+  c->pairs[l] = false;
   c->lam_min[l] = lmin;
   bool all = true;
   double sum = 0.0;
@@ -434,6 +507,44 @@ extern "C" int fdg_set_prec_factors(fdg_ctx *c, int l, const double *U, const do
 // layouts, as for a general pencil.
 extern "C" int fdg_set_prec_factors_sym(fdg_ctx *c, int l, const double *U, const double *lambda) {
   return fdg_set_prec_factors(c, l, U, U, lambda);
+}
+
+// Nonsymmetric FD factors with complex eigenvalue pairs (Sec. 4, the remark after
+// eq. 4.7): D_l block diagonal, 2 x 2 block [[lambda_c, mu_c], [mu_{c+1}, lambda_{c+1}]]
+// = [[a, b], [-b, a]] for a pair.
+extern "C" int fdg_set_prec_factors_blocks(fdg_ctx *c, int l, const double *U, const double *V,
+                                           const double *lambda, const double *mu) {
+  clear_error();
+  if (!c || !U || !V || !lambda) return set_error(FDG_EINVAL, "set_prec_factors_blocks: NULL argument");
+  if (l < 0 || l >= c->d) return set_error(FDG_EINVAL, "set_prec_factors_blocks: bad direction %d", l);
+  const int n = c->n;
+  std::vector<int8_t> role(c->ldw, 0);
+  std::vector<double> m(c->ldw, 0.0);
+  bool any = false;
+  if (mu) {
+    for (int i = 0; i < n; ++i) {
+      if (!std::isfinite(mu[i])) return set_error(FDG_EINVAL, "set_prec_factors_blocks: non-finite mu");
+      if (mu[i] == 0.0) continue;
+      if (!(mu[i] > 0.0) || i + 1 >= n || mu[i + 1] != -mu[i] || lambda[i + 1] != lambda[i])
+        return set_error(FDG_EINVAL, "set_prec_factors_blocks: index %d does not start a pair "
+                                     "(mu[c] > 0, mu[c+1] = -mu[c], lambda[c+1] = lambda[c])", i);
+      role[i] = 1;
+      role[i + 1] = 2;
+      m[i] = mu[i];
+      m[i + 1] = mu[i + 1];
+      any = true;
+      ++i;
+    }
+  }
+  int st = fdg_set_prec_factors(c, l, U, V, lambda);
+  if (st != FDG_OK) return st;
+  c->pairs[l] = any;
+  if (!any) return FDG_OK;
+  if ((st = dalloc(&c->mu[l], m.size())) != FDG_OK) return st;
+  if ((st = dalloc(&c->role[l], role.size())) != FDG_OK) return st;
+  HIPCHK(hipMemcpy(c->mu[l], m.data(), m.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->role[l], role.data(), role.size(), hipMemcpyHostToDevice));
+  return FDG_OK;
 }
 
 extern "C" int fdg_set_precision(fdg_ctx *c, int prec) {

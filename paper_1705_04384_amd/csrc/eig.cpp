@@ -7,8 +7,13 @@
 // reduction to upper Hessenberg form, Francis implicit double-shift QR iterations to
 // a real Schur form T = Z^T A Z (accumulating Z), 2x2 blocks with real eigenvalues split
 // by a rotation; eigenvectors of the triangular T by back-substitution; U = Z Y.
+// A pencil with complex eigenvalues (Sec. 4, the remark after eq. 4.7) keeps each pair's
+// 2x2 block in T; its eigenvector z = u + i v (complex back-substitution through the
+// quasi-triangular T) gives the two real columns u, v of U, and D gets the real 2x2
+// block [[a, b], [-b, a]] for the pair a +- ib (fdg_factor_pencil_blocks).
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -230,14 +235,18 @@ bool split_block(Mat &H, Mat &Zt, int p, double *ev0, double *ev1) {
   return true;
 }
 
-// Francis double-shift QR on the Hessenberg H to upper-triangular form (real spectrum).
-int schur_real(Mat &H, Mat &Zt, std::vector<double> &ev) {
+// Francis double-shift QR on the Hessenberg H to real Schur form.  Real eigenvalues end on
+// the diagonal (2x2 blocks with real eigenvalues are split by a rotation); a 2x2 block with
+// a complex-conjugate pair a +- ib is kept when allow_complex (ev = a, evi = +b on its
+// first row and -b on its second), and is an error otherwise.
+int schur_real(Mat &H, Mat &Zt, std::vector<double> &ev, std::vector<double> &evi, bool allow_complex) {
   const int n = H.n;
   const double eps = 2.220446049250313e-16;
   double anorm = 0.0;
   for (double x : H.a) anorm = std::max(anorm, std::fabs(x));
   if (anorm == 0.0) anorm = 1.0;
   ev.assign(n, 0.0);
+  evi.assign(n, 0.0);
   int hi = n - 1;
   int iter = 0, total = 0;
   const int max_total = 60 * std::max(n, 10);
@@ -260,10 +269,18 @@ int schur_real(Mat &H, Mat &Zt, std::vector<double> &ev) {
     }
     if (l == hi - 1) {
       double e0, e1;
-      if (!split_block(H, Zt, hi - 1, &e0, &e1))
-        return set_error(FDG_ECOMPLEX, "factor_pencil: complex eigenvalue pair");
-      ev[hi - 1] = e0;
-      ev[hi] = e1;
+      if (!split_block(H, Zt, hi - 1, &e0, &e1)) {
+        if (!allow_complex) return set_error(FDG_ECOMPLEX, "factor_pencil: complex eigenvalue pair");
+        const double a = H(hi - 1, hi - 1), b = H(hi - 1, hi), c = H(hi, hi - 1), d = H(hi, hi);
+        const double half = 0.5 * (a - d);
+        const double im = std::sqrt(-(half * half + b * c));
+        ev[hi - 1] = ev[hi] = 0.5 * (a + d);
+        evi[hi - 1] = im;
+        evi[hi] = -im;
+      } else {
+        ev[hi - 1] = e0;
+        ev[hi] = e1;
+      }
       hi -= 2;
       iter = 0;
       continue;
@@ -311,9 +328,26 @@ int schur_real(Mat &H, Mat &Zt, std::vector<double> &ev) {
 
 using namespace fdg;
 
-extern "C" int fdg_factor_pencil(int n, const double *K, const double *M, double *U, double *V,
-                                 double *lambda, double *cond_u) {
-  clear_error();
+
+namespace {
+
+typedef std::complex<double> cplx;
+
+// Solution of the 2x2 system [[a, b], [c, d]] [x0, x1] = [r0, r1] by Cramer's rule, the
+// determinant moved away from zero by smin (nearly equal eigenvalues).
+template <typename T>
+void solve2(T a, T b, T c, T d, T r0, T r1, double smin, T &x0, T &x1) {
+  T det = a * d - b * c;
+  if (std::abs(det) < smin) det = det == T(0) ? T(smin) : det * (smin / std::abs(det));
+  x0 = (r0 * d - b * r1) / det;
+  x1 = (a * r1 - c * r0) / det;
+}
+
+// Eigenvalues, Schur vectors and quasi-triangular T -> U (eigenvectors, real; a complex
+// pair z = u + i v is stored as the columns u, v), V = (M U)^{-T}, lambda (real parts),
+// mu (0, or +b and -b on the two columns of a pair a +- ib), ordered by real part.
+int factor_impl(int n, const double *K, const double *M, bool allow_complex, double *U, double *V, double *lambda,
+                double *mu, double *cond_u) {
   if (n < 1 || n > 4096 || !K || !M || !U || !V || !lambda)
     return set_error(FDG_EINVAL, "factor_pencil: bad arguments (n=%d)", n);
   const size_t nn = (size_t)n * n;
@@ -331,23 +365,73 @@ extern "C" int fdg_factor_pencil(int n, const double *K, const double *M, double
   H.a = A;
   for (int i = 0; i < n; ++i) Zt(i, i) = 1.0;
   hessenberg(H, Zt);
-  std::vector<double> ev;
-  int st = schur_real(H, Zt, ev);
+  std::vector<double> ev, evi;
+  int st = schur_real(H, Zt, ev, evi, allow_complex);
   if (st != FDG_OK) return st;
-  double emax = 0.0;
-  for (double e : ev) emax = std::max(emax, std::fabs(e));
   for (double e : ev)
-    if (!(e > 0.0)) return set_error(FDG_ECOMPLEX, "factor_pencil: non-positive eigenvalue %g", e);
-  // eigenvectors of the upper-triangular T = H by back-substitution; column k of Y is
-  // kept as row k of Yt so every inner product runs over contiguous memory
+    if (!(e > 0.0)) return set_error(FDG_ECOMPLEX, "factor_pencil: eigenvalue with non-positive real part %g", e);
+  // first[i]: rows i, i+1 of T form a 2x2 block (a complex pair)
+  std::vector<char> first(n, 0);
+  for (int i = 0; i + 1 < n; ++i)
+    if (evi[i] > 0.0) first[i] = 1;
+  auto in_block_second = [&](int i) { return i >= 1 && first[i - 1]; };
+  // Eigenvectors of the quasi-triangular T = H by back-substitution, kept as rows of Yt
+  // (row k: eigenvector of a real eigenvalue; rows k, k+1: real and imaginary parts of
+  // the eigenvector of the pair's eigenvalue a + ib) so inner products run over rows.
   const double ulp = 2.220446049250313e-16;
   Mat Yt(n);
+  std::vector<cplx> yc(n);
   for (int k = n - 1; k >= 0; --k) {
+    if (in_block_second(k)) continue;  // handled with the pair's first row
+    if (first[k]) {                    // complex pair at rows k, k+1
+      const cplx lk(ev[k], evi[k]);
+      const double smin = std::max(ulp * std::abs(lk), 1e-300);
+      std::fill(yc.begin(), yc.end(), cplx(0.0));
+      yc[k] = H(k, k + 1);
+      yc[k + 1] = lk - H(k, k);
+      int i = k - 1;
+      while (i >= 0) {
+        if (in_block_second(i)) {  // rows i-1, i: a 2x2 block
+          cplx s0 = 0.0, s1 = 0.0;
+          for (int j = i + 1; j <= k + 1; ++j) {
+            s0 += H(i - 1, j) * yc[j];
+            s1 += H(i, j) * yc[j];
+          }
+          solve2<cplx>(H(i - 1, i - 1) - lk, H(i - 1, i), H(i, i - 1), H(i, i) - lk, -s0, -s1, smin, yc[i - 1],
+                       yc[i]);
+          i -= 2;
+        } else {
+          cplx s = 0.0;
+          for (int j = i + 1; j <= k + 1; ++j) s += H(i, j) * yc[j];
+          cplx den = H(i, i) - lk;
+          if (std::abs(den) < smin) den = smin;
+          yc[i] = -s / den;
+          i -= 1;
+        }
+      }
+      double *yr = &Yt(k, 0), *yi = &Yt(k + 1, 0);
+      for (int j = 0; j <= k + 1; ++j) {
+        yr[j] = yc[j].real();
+        yi[j] = yc[j].imag();
+      }
+      continue;
+    }
     const double lk = H(k, k);
     const double smin = std::max(ulp * std::fabs(lk), 1e-300);
     double *y = &Yt(k, 0);
     y[k] = 1.0;
-    for (int i = k - 1; i >= 0; --i) {
+    int i = k - 1;
+    while (i >= 0) {
+      if (in_block_second(i)) {  // rows i-1, i: a 2x2 block of a complex pair
+        double s0 = 0.0, s1 = 0.0;
+        for (int j = i + 1; j <= k; ++j) {
+          s0 += H(i - 1, j) * y[j];
+          s1 += H(i, j) * y[j];
+        }
+        solve2<double>(H(i - 1, i - 1) - lk, H(i - 1, i), H(i, i - 1), H(i, i) - lk, -s0, -s1, smin, y[i - 1], y[i]);
+        i -= 2;
+        continue;
+      }
       const double *h = &H(i, 0);
       double s = 0.0;
       for (int j = i + 1; j <= k; ++j) s += h[j] * y[j];
@@ -372,42 +456,72 @@ extern "C" int fdg_factor_pencil(int n, const double *K, const double *M, double
       if (std::fabs(yi) > 1e150) {  // rescale the partial vector
         for (int j = i; j <= k; ++j) y[j] *= 1e-150;
       }
+      i -= 1;
     }
   }
-  // U = Z Y (column k of U = sum_j Y(j, k) Z(:, j), accumulated as row k of Ut),
-  // unit columns, eigenvalues ascending
+  // U = Z Y (column k of U = sum_j Y(j, k) Z(:, j), accumulated as row k of Ut)
   Mat Ut(n);
   for (int k = 0; k < n; ++k) {
     const double *y = &Yt(k, 0);
     double *u = &Ut(k, 0);
-    for (int j = 0; j <= k; ++j) {
+    const int jmax = (first[k] || in_block_second(k)) ? std::min(n - 1, k + 1) : k;
+    for (int j = 0; j <= jmax; ++j) {
       const double yj = y[j];
       if (yj == 0.0) continue;
       const double *z = &Zt(j, 0);
       for (int i = 0; i < n; ++i) u[i] += yj * z[i];
     }
   }
-  std::vector<int> order(n);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ev[a] < ev[b]; });
-  for (int c = 0; c < n; ++c) {
-    const int k = order[c];
-    double nrm = 0.0;
-    for (int i = 0; i < n; ++i) nrm += Ut(k, i) * Ut(k, i);
-    nrm = std::sqrt(nrm);
-    if (!(nrm > 0.0) || !std::isfinite(nrm)) return set_error(FDG_ENOCONV, "factor_pencil: degenerate eigenvector");
-    for (int i = 0; i < n; ++i) U[(size_t)i * n + c] = Ut(k, i) / nrm;
-    lambda[c] = ev[k];
+  // units (a real eigenvalue or a pair) in ascending order of the real part
+  std::vector<int> units;
+  for (int k = 0; k < n; ++k)
+    if (!in_block_second(k)) units.push_back(k);
+  std::stable_sort(units.begin(), units.end(), [&](int a, int b) { return ev[a] < ev[b]; });
+  int c = 0;
+  for (int k : units) {
+    if (first[k]) {
+      // z = u + i v: rotate the phase so that u and v are orthogonal, unit 2-norm of z
+      double *u = &Ut(k, 0), *v = &Ut(k + 1, 0);
+      double uu = 0.0, vv = 0.0, uv = 0.0;
+      for (int i = 0; i < n; ++i) {
+        uu += u[i] * u[i];
+        vv += v[i] * v[i];
+        uv += u[i] * v[i];
+      }
+      const double th = 0.5 * std::atan2(-2.0 * uv, uu - vv);
+      const double cs = std::cos(th), sn = std::sin(th);
+      const double nrm = std::sqrt(uu + vv);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) return set_error(FDG_ENOCONV, "factor_pencil: degenerate eigenvector");
+      for (int i = 0; i < n; ++i) {
+        U[(size_t)i * n + c] = (cs * u[i] - sn * v[i]) / nrm;
+        U[(size_t)i * n + c + 1] = (sn * u[i] + cs * v[i]) / nrm;
+      }
+      lambda[c] = lambda[c + 1] = ev[k];
+      if (mu) {
+        mu[c] = evi[k];
+        mu[c + 1] = -evi[k];
+      }
+      c += 2;
+    } else {
+      double nrm = 0.0;
+      for (int i = 0; i < n; ++i) nrm += Ut(k, i) * Ut(k, i);
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) return set_error(FDG_ENOCONV, "factor_pencil: degenerate eigenvector");
+      for (int i = 0; i < n; ++i) U[(size_t)i * n + c] = Ut(k, i) / nrm;
+      lambda[c] = ev[k];
+      if (mu) mu[c] = 0.0;
+      c += 1;
+    }
   }
   // V = (M U)^{-T}
   Mat MU(n);
   for (int i = 0; i < n; ++i) {
-    double *mu = &MU(i, 0);
+    double *mrow = &MU(i, 0);
     for (int j = 0; j < n; ++j) {
       const double m = M[(size_t)i * n + j];
       if (m == 0.0) continue;
       const double *u = U + (size_t)j * n;
-      for (int k = 0; k < n; ++k) mu[k] += m * u[k];
+      for (int k = 0; k < n; ++k) mrow[k] += m * u[k];
     }
   }
   std::vector<int> piv2;
@@ -442,6 +556,20 @@ extern "C" int fdg_factor_pencil(int n, const double *K, const double *M, double
       *cond_u = c1 * c2;
     }
   }
-  (void)emax;
   return FDG_OK;
+}
+
+}  // namespace
+
+extern "C" int fdg_factor_pencil(int n, const double *K, const double *M, double *U, double *V,
+                                 double *lambda, double *cond_u) {
+  clear_error();
+  return factor_impl(n, K, M, false, U, V, lambda, nullptr, cond_u);
+}
+
+extern "C" int fdg_factor_pencil_blocks(int n, const double *K, const double *M, double *U, double *V,
+                                        double *lambda, double *mu, double *cond_u) {
+  clear_error();
+  if (!mu) return set_error(FDG_EINVAL, "factor_pencil_blocks: mu is NULL");
+  return factor_impl(n, K, M, true, U, V, lambda, mu, cond_u);
 }

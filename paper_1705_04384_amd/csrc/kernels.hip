@@ -3,7 +3,8 @@
 //  * FD mode products (eq. 4.7 / 4.9): every mode product of the fast-diagonalization
 //    solve is a small dense contraction Y = W x_l X with a zero-padded n x n factor W,
 //    run on the FP64 matrix cores (v_mfma_f64_16x16x4_f64).
-//  * The diagonal solve of eq. 4.9 (divide by the sum of univariate eigenvalues).
+//  * The diagonal solve of eq. 4.9 (divide by the sum of univariate eigenvalues), and its
+//    block form when some pencils have complex eigenvalue pairs (2 x 2 real blocks in D).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -90,6 +91,100 @@ __global__ __launch_bounds__(kBlock) void k_divide_f64(double *__restrict__ t, i
   double den = l1[i1] + l2[i2];
   if (d == 3) den += l3[(idx / ((int64_t)n * n)) % n];
   t[idx] = t[idx] / den;
+}
+
+// Solve of sum_l I x D_l x I for block-diagonal D_l (1 x 1 blocks lam, 2 x 2 blocks
+// [[a, b], [-b, a]] of a pair a +- ib, role 1 / 2 on its first / second index).  The
+// operator decouples into cells: the product of one block per direction (at most
+// 2 x 2 x 2 entries).  The thread of a cell's first entry solves it: in every paired
+// direction the pair (x0, x1) goes to the eigen-coordinates ((x0 - i x1) / 2,
+// (x0 + i x1) / 2) of a + ib and a - ib, each entry is divided by the complex sum of its
+// eigenvalues, and the transform is undone (x0 = z+ + z-, x1 = i (z+ - z-)).
+struct Cplx {
+  double re, im;
+};
+
+__device__ inline void pair_fwd(Cplx &z0, Cplx &z1) {  // (z0 - i z1) / 2, (z0 + i z1) / 2
+  const Cplx p{0.5 * (z0.re + z1.im), 0.5 * (z0.im - z1.re)};
+  const Cplx q{0.5 * (z0.re - z1.im), 0.5 * (z0.im + z1.re)};
+  z0 = p;
+  z1 = q;
+}
+
+__device__ inline void pair_inv(Cplx &z0, Cplx &z1) {  // z0 + z1, i (z0 - z1)
+  const Cplx p{z0.re + z1.re, z0.im + z1.im};
+  const Cplx q{-(z0.im - z1.im), z0.re - z1.re};
+  z0 = p;
+  z1 = q;
+}
+
+// Block of index i in one direction: false when i is the second index of a pair.
+__device__ inline bool cell_dir(const BlockEig &e, int i, int &sz, double &a, double &b) {
+  const int r = e.role[i];
+  if (r == 2) return false;
+  sz = r == 1 ? 2 : 1;
+  a = e.lam[i];
+  b = r == 1 ? e.mu[i] : 0.0;
+  return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_blockdiv_f64(double *__restrict__ t, int d, int n, int64_t total,
+                                                         BlockEig e1, BlockEig e2, BlockEig e3) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t n2 = (int64_t)n * n;
+  const int i1 = (int)(idx % n), i2 = (int)((idx / n) % n), i3 = d == 3 ? (int)((idx / n2) % n) : 0;
+  int sz[3] = {1, 1, 1};
+  double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+  if (!cell_dir(e1, i1, sz[0], a[0], b[0]) || !cell_dir(e2, i2, sz[1], a[1], b[1])) return;
+  if (d == 3 && !cell_dir(e3, i3, sz[2], a[2], b[2])) return;
+  const int64_t st[3] = {1, n, n2};
+  Cplx z[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int t1 = c & 1, t2 = (c >> 1) & 1, t3 = c >> 2;
+    const bool in = t1 < sz[0] && t2 < sz[1] && t3 < sz[2];
+    z[c] = Cplx{in ? t[idx + t1 * st[0] + t2 * st[1] + t3 * st[2]] : 0.0, 0.0};
+  }
+  // eigen-coordinates in every paired direction (entries c and c + 2^l form a pair)
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (sz[l] != 2) continue;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (!((c >> l) & 1)) pair_fwd(z[c], z[c | (1 << l)]);
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    double lr = 0.0, li = 0.0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      lr += a[l];
+      li += ((c >> l) & 1) ? -b[l] : b[l];
+    }
+    const double den = lr * lr + li * li;  // z / (lr + i li)
+    const Cplx q{(z[c].re * lr + z[c].im * li) / den, (z[c].im * lr - z[c].re * li) / den};
+    z[c] = q;
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (sz[l] != 2) continue;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (!((c >> l) & 1)) pair_inv(z[c], z[c | (1 << l)]);
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int t1 = c & 1, t2 = (c >> 1) & 1, t3 = c >> 2;
+    if (t1 < sz[0] && t2 < sz[1] && t3 < sz[2]) t[idx + t1 * st[0] + t2 * st[1] + t3 * st[2]] = z[c].re;
+  }
+}
+
+void launch_blockdiv_f64(hipStream_t s, double *t, int d, int n, int64_t nbatch, const BlockEig &e1,
+                         const BlockEig &e2, const BlockEig &e3) {
+  const int64_t N = (int64_t)n * n * (d == 3 ? n : 1);
+  const int64_t total = N * nbatch;
+  hipLaunchKernelGGL(k_blockdiv_f64, dim3(grid1(total, kBlock)), dim3(kBlock), 0, s, t, d, n, total, e1, e2, e3);
 }
 
 void launch_divide_f64(hipStream_t s, double *t, int d, int n, int64_t nbatch, const double *lam1,

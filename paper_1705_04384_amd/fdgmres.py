@@ -52,7 +52,8 @@ EXPORTS = [
     "fdg_server_create", "fdg_server_destroy", "fdg_server_run_bytes", "fdg_server_admit", "fdg_server_step",
     "fdg_server_pending", "fdg_server_stats", "fdg_set_operator_mapped", "fdg_set_operator_fields",
     "fdg_deformed_coefficients", "fdg_factor_pencil_sym", "fdg_galerkin_factors", "fdg_galerkin_csr",
-    "fdg_set_prec_factors_sym", "fdg_bicgstab", "fdg_operator_bytes",
+    "fdg_set_prec_factors_sym", "fdg_bicgstab", "fdg_operator_bytes", "fdg_factor_pencil_blocks",
+    "fdg_set_prec_factors_blocks",
 ]
 
 
@@ -97,6 +98,8 @@ def lib():
     L.fdg_set_operator_mapped.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp]
     L.fdg_set_operator_fields.argtypes = [ctypes.c_void_p, _dp]
     L.fdg_deformed_coefficients.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+    L.fdg_factor_pencil_blocks.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.fdg_set_prec_factors_blocks.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, _dp, _dp]
     L.fdg_factor_pencil_sym.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
     L.fdg_galerkin_factors.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
     L.fdg_galerkin_csr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_double, _i64p,
@@ -144,6 +147,18 @@ def factor_pencil(K, M, want_cond=True):
     _check(lib().fdg_factor_pencil(n, _ptr(K), _ptr(M), _ptr(U), _ptr(V), _ptr(lam),
                                    ctypes.byref(c) if want_cond else None))
     return U, V, lam, (c.value if want_cond else None)
+
+
+def factor_pencil_blocks(K, M, want_cond=False):
+    """(U, V, lam, mu, cond1(U)): K U = M U D with D block diagonal (2x2 blocks
+    [[lam_c, mu_c], [mu_{c+1}, lam_{c+1}]] for complex pairs), V = (M U)^{-T}."""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    n = K.shape[0]
+    U = np.zeros((n, n)); V = np.zeros((n, n)); lam = np.zeros(n); mu = np.zeros(n); c = ctypes.c_double()
+    _check(lib().fdg_factor_pencil_blocks(n, _ptr(K), _ptr(M), _ptr(U), _ptr(V), _ptr(lam), _ptr(mu),
+                                          ctypes.byref(c) if want_cond else None))
+    return U, V, lam, mu, (c.value if want_cond else None)
 
 
 def factor_pencil_sym(K, M):
@@ -257,6 +272,10 @@ class Context:
         V = np.ascontiguousarray(V, dtype=np.float64)
         lam = np.ascontiguousarray(lam, dtype=np.float64)
         _check(lib().fdg_set_prec_factors(self._h, l, _ptr(U), _ptr(V), _ptr(lam)))
+
+    def set_prec_factors_blocks(self, l, U, V, lam, mu):
+        U, V, lam, mu = (np.ascontiguousarray(a, dtype=np.float64) for a in (U, V, lam, mu))
+        _check(lib().fdg_set_prec_factors_blocks(self._h, l, _ptr(U), _ptr(V), _ptr(lam), _ptr(mu)))
 
     def set_prec_factors_sym(self, l, U, lam):
         U = np.ascontiguousarray(U, dtype=np.float64)
@@ -436,14 +455,16 @@ def galerkin_problem(p, n, amp=0.0, wind=None, beta=0.0, wind_prec=True, stream=
     operator, Sec. 3.2).  The preconditioner is the unit-cube Galerkin discretization: with
     wind_prec and a wind (c_1, c_2, c_3), direction l uses K_l + H_l for the univariate
     wind c_l (1 + z) (eq. 3.9, nonsymmetric FD); otherwise the wind is dropped (eq. 3.7,
-    symmetric FD with V = U)."""
+    symmetric FD with V = U).  Pencils with complex eigenvalues use the block form of D
+    (FP64 preconditioner only)."""
     ctx = Context(3, n, stream=stream)
     for l in range(3):
         cl = 0.0 if wind is None else float(wind[l])
         M, K, H = galerkin_factors(p, n, cl, cl)
         if wind_prec and cl != 0.0:
-            U, V, lam, _ = factor_pencil(K + H, M, want_cond=False)
-            ctx.set_prec_factors(l, U, V, lam)
+            # complex eigenvalue pairs (strong wind, coarse mesh) take the 2 x 2 block form
+            U, V, lam, mu, _ = factor_pencil_blocks(K + H, M)
+            ctx.set_prec_factors_blocks(l, U, V, lam, mu)
         else:
             U, lam = factor_pencil_sym(K, M)
             ctx.set_prec_factors_sym(l, U, lam)

@@ -200,3 +200,121 @@ def test_galerkin_bench_size_properties():
     assert info["converged"]
     assert relerr(A @ x.cpu().numpy(), b) <= 1e-8
     ctx.close()
+
+
+# ---- pencils with complex eigenvalue pairs (Sec. 4, the remark after eq. 4.7) -----------
+
+def _blocks_context(fdg, d, p, n, winds):
+    ctx = fdg.Context(d, n)
+    Ms, KHs = [], []
+    npairs, cond = 0, 1.0
+    for l in range(d):
+        M, K, H = fdg.galerkin_factors(p, n, winds[l], winds[l])
+        U, V, lam, mu, cu = fdg.factor_pencil_blocks(K + H, M, want_cond=True)
+        npairs += int((mu > 0).sum())
+        cond = max(cond, cu)
+        ctx.set_prec_factors_blocks(l, U, V, lam, mu)
+        ctx.set_operator_kron(l, M, K + H)
+        Ms.append(M)
+        KHs.append(K + H)
+    return ctx, Ms, KHs, npairs, cond
+
+
+# winds past the point where the pencils turn complex, with eigenvector bases of moderate
+# condition (right after the transition they are nearly defective)
+@pytest.mark.parametrize("d,p,n,winds", [(3, 3, 8, (10.0, 20.0, 15.0)), (3, 3, 20, (100.0, 150.0, 80.0)),
+                                         (2, 3, 33, (150.0, 150.0)), (2, 2, 17, (150.0, 80.0)),
+                                         (3, 4, 24, (150.0, 100.0, 80.0)), (3, 2, 17, (80.0, 100.0, 150.0))])
+def test_complex_pencil_fd_apply_matches_oracle(d, p, n, winds):
+    # the device keeps D in real 2 x 2 blocks; the oracle runs the FD in complex arithmetic.
+    # Tolerance: rounding amplified by the condition of the eigenvector basis
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx, Ms, KHs, npairs, cond = _blocks_context(fdg, d, p, n, winds)
+    assert npairs > 0
+    tol = 1e-13 * cond + 1e-10
+    b = inputs.rhs_normal(31, n ** d)
+    s = torch.empty(n ** d, dtype=torch.float64, device="cuda")
+    ctx.apply_prec(to_dev(b), s)
+    torch.cuda.synchronize()
+    fac = [fd.factor_pencil(KH, M, allow_complex=True) for KH, M in zip(KHs, Ms)]
+    so = fd.fd_apply([f[0] for f in fac], [f[1] for f in fac], [f[2] for f in fac], b)
+    assert relerr(s.cpu().numpy(), so) <= tol
+    y = torch.empty_like(s)
+    ctx.matvec(s, y)
+    torch.cuda.synchronize()
+    assert relerr(y.cpu().numpy(), b) <= tol
+    ctx.close()
+
+
+def test_complex_blocks_unfused_beyond_256():
+    # n > 256 runs unfused mode products around the block solve.  Synthetic factors: U
+    # orthogonal, V = U (M = I), D with 2 x 2 blocks, so P = K_2 x I + I x K_1 with
+    # K_l = U D_l U^T, checked by applying P to the result in numpy
+    fdg = _fdg()
+    torch = torch_cuda()
+    n = 300
+    rng = np.random.default_rng(41)
+    ctx = fdg.Context(2, n)
+    Ks = []
+    for l in range(2):
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam = np.sort(rng.uniform(1.0, 50.0, n))
+        mu = np.zeros(n)
+        for c in range(l, n - 1, 7):
+            lam[c + 1] = lam[c]
+            mu[c], mu[c + 1] = 3.0 + c % 5, -(3.0 + c % 5)
+        D = np.diag(lam)
+        for c in range(n - 1):
+            if mu[c] > 0:
+                D[c, c + 1], D[c + 1, c] = mu[c], mu[c + 1]
+        ctx.set_prec_factors_blocks(l, Q, Q, lam, mu)
+        Ks.append(Q @ D @ Q.T)
+    b = inputs.rhs_normal(32, n * n)
+    s = torch.empty(n * n, dtype=torch.float64, device="cuda")
+    ctx.apply_prec(to_dev(b), s)
+    torch.cuda.synchronize()
+    S = s.cpu().numpy().reshape(n, n)           # S[i2][i1]
+    Ps = S @ Ks[0].T + Ks[1] @ S
+    assert relerr(Ps.ravel(), b) <= 1e-11
+    ctx.close()
+
+
+def test_galerkin_solve_with_complex_pencils():
+    # strong wind on a coarse mesh: the eq. 3.9 pencils have complex pairs; FGMRES with the
+    # block FD against the oracle (complex FD): same iterations, same iterate
+    fdg = _fdg()
+    torch = torch_cuda()
+    p, n, amp, wind, beta = 3, 10, 0.1, (10.0, 10.0, 10.0), 0.5
+    ctx = fdg.galerkin_problem(p, n, amp, wind, beta)
+    A = _oracle_operator(p, n, amp, wind, beta)
+    facs = [G.galerkin_factors(p, n, G.affine_wind(c)) for c in wind]
+    fac = [fd.factor_pencil(f[1] + f[2], f[0], allow_complex=True) for f in facs]
+    assert max(np.abs(f[2].imag).max() for f in fac) > 0
+    prec = lambda v: fd.fd_apply([f[0] for f in fac], [f[1] for f in fac], [f[2] for f in fac], v)
+    b = inputs.rhs_uniform(inputs.SEED_DEFORMED_96, n ** 3)
+    xo, io = fgmres.fgmres(lambda v: A @ v, prec, b, rtol=1e-8, restart=30)
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.solve(to_dev(b), x, rtol=1e-8, restart=30)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1
+    k = io["iterations"]
+    ctx.solve(to_dev(b), x, rtol=1e-8, restart=30, maxit=k, flags=fdg.SOLVE_FIXED_ITERS)
+    assert relerr(x.cpu().numpy(), xo) <= 1e-8
+    # the server runs such a context one request at a time, with the same bits
+    srv = fdg.Server(max_slots=4, restart=30, lanes=1, arena_bytes=64 << 20)
+    bd = to_dev(b)
+    xs = [torch.empty_like(bd) for _ in range(2)]
+    for t in range(2):
+        assert srv.admit(ctx, bd, xs[t], rtol=1e-8, tag=t)
+    while srv.pending() > 0:
+        srv.step(wait_us=1000)
+    x1 = torch.empty_like(bd)
+    ctx.solve(bd, x1, rtol=1e-8, restart=30)
+    for t in range(2):
+        assert np.array_equal(xs[t].cpu().numpy(), x1.cpu().numpy())
+    srv.close()
+    # reduced precision needs real eigenvalues
+    ctx.set_precision(fdg.PREC_FP32)
+    with pytest.raises(fdg.FdgError):
+        ctx.apply_prec(bd, x1)
+    ctx.close()

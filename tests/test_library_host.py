@@ -191,3 +191,33 @@ def test_galerkin_csr_matches_oracle(p, n, amp, wind, beta):
     assert np.array_equal(np.diff(rowptr), want)
     for r in range(0, n ** 3, 7):
         assert np.all(np.diff(col[rowptr[r]:rowptr[r + 1]]) > 0)
+
+
+@pytest.mark.parametrize("p,n,c", [(3, 8, 10.0), (2, 7, 20.0), (4, 10, 30.0), (3, 20, 100.0), (3, 48, 10.0)])
+def test_factor_pencil_blocks_matches_oracle(p, n, c):
+    # complex pairs (Sec. 4, the remark after eq. 4.7) as 2 x 2 real blocks: K U = M U D,
+    # V = (M U)^{-T}, the eigenvalues equal the oracle's complex ones as a set
+    _lib()
+    M, K, H = fdg.galerkin_factors(p, n, c, c)
+    U, V, lam, mu, _ = fdg.factor_pencil_blocks(K + H, M)
+    D = np.diag(lam)
+    firsts = [i for i in range(n) if mu[i] > 0]
+    for i in firsts:
+        assert mu[i + 1] == -mu[i] and lam[i + 1] == lam[i]
+        D[i, i + 1], D[i + 1, i] = mu[i], mu[i + 1]
+    assert np.count_nonzero(mu) == 2 * len(firsts)
+    assert np.abs((K + H) @ U - M @ U @ D).max() <= 1e-12 * np.abs(K + H).max()
+    assert np.abs(V.T @ M @ U - np.eye(n)).max() <= 1e-10
+    _, _, lo = fd.factor_pencil(K + H, M, allow_complex=True)
+    ev = np.concatenate([lam[mu == 0] + 0j, lam[mu > 0] + 1j * mu[mu > 0], lam[mu > 0] - 1j * mu[mu > 0]])
+    assert max(np.abs(lo - e).min() for e in ev) <= 1e-12 * np.abs(lo).max()
+    assert max(np.abs(ev - e).min() for e in lo) <= 1e-12 * np.abs(lo).max()
+
+
+def test_factor_pencil_blocks_equals_plain_for_real_pencils():
+    _lib()
+    M, K, _, _ = fdg.colloc_factors(4, 96)
+    U, V, lam, mu, _ = fdg.factor_pencil_blocks(K, M)
+    U2, V2, lam2, _ = fdg.factor_pencil(K, M, want_cond=False)
+    assert not np.any(mu)
+    assert np.array_equal(U, U2) and np.array_equal(V, V2) and np.array_equal(lam, lam2)
