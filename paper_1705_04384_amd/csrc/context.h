@@ -35,10 +35,13 @@ struct fdg_ctx {
   uint16_t *Wv16[3] = {nullptr, nullptr, nullptr}, *Wu16[3] = {nullptr, nullptr, nullptr};
   float *lam32[3] = {nullptr, nullptr, nullptr};
   double lam_min[3] = {0, 0, 0};
-  // complex eigenvalue pairs (2 x 2 blocks of D_l): imaginary parts and index roles
+  // blocks of D_l (complex eigenvalue pairs are 2 x 2 blocks): imaginary parts, index
+  // roles, block starts and block counts; kept for every direction with factors
   bool pairs[3] = {false, false, false};
   double *mu[3] = {nullptr, nullptr, nullptr};
   int8_t *role[3] = {nullptr, nullptr, nullptr};
+  int32_t *bstart[3] = {nullptr, nullptr, nullptr};
+  int nblocks[3] = {0, 0, 0};
   // operator
   int op_kind = 0;  // 0 none, 1 Kronecker bands, 2 ELL, 3 mapped (matrix-free)
   bool have_op[3] = {false, false, false};

@@ -160,7 +160,7 @@ int apply_blocks(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nent
   const double *b = in.base;
   double *s = out.base, *T1 = t1.base, *T2 = t2.base;
   BlockEig e[3];
-  for (int l = 0; l < c->d; ++l) e[l] = BlockEig{c->lam[l], c->mu[l], c->role[l]};
+  for (int l = 0; l < c->d; ++l) e[l] = BlockEig{c->lam[l], c->mu[l], c->role[l], c->bstart[l], c->nblocks[l]};
   TimedLaunch tl(c, 0, ex.stream, ex.timed);
   auto mode = [&](const double *X, double *Y, const double *W, int l) {
     if (l == 0)
@@ -176,31 +176,31 @@ int apply_blocks(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nent
       launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, n, false, nullptr, nullptr, a32,
                       nullptr, nullptr);
       mode(T1, T2, c->Wv[2], 2);
-      launch_blockdiv_f64(ex.stream, T2, 3, n, B, e[0], e[1], e[2]);
-      mode(T2, T1, c->Wu[2], 2);
-      launch_slab_f64(ex.stream, as_const(t1), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, n, false, nullptr,
+      launch_blockdiv_f64(ex.stream, T2, T1, 3, n, B, e[0], e[1], e[2]);
+      mode(T1, T2, c->Wu[2], 2);
+      launch_slab_f64(ex.stream, as_const(t2), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, n, false, nullptr,
                       nullptr, a32, nullptr, nullptr);
     } else {
       launch_slab_f64(ex.stream, in, t1, c->Wv[0], c->Wv[1], c->ldw, n, nent, 1, false, nullptr, nullptr, a32,
                       nullptr, nullptr);
-      launch_blockdiv_f64(ex.stream, T1, 2, n, B, e[0], e[1], e[1]);
-      launch_slab_f64(ex.stream, as_const(t1), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, 1, false, nullptr,
+      launch_blockdiv_f64(ex.stream, T1, T2, 2, n, B, e[0], e[1], e[1]);
+      launch_slab_f64(ex.stream, as_const(t2), out, c->Wu[0], c->Wu[1], c->ldw, n, nent, 1, false, nullptr,
                       nullptr, a32, nullptr, nullptr);
     }
   } else if (c->d == 3) {
     mode(b, T1, c->Wv[0], 0);
     mode(T1, T2, c->Wv[1], 1);
     mode(T2, T1, c->Wv[2], 2);
-    launch_blockdiv_f64(ex.stream, T1, 3, n, B, e[0], e[1], e[2]);
-    mode(T1, T2, c->Wu[0], 0);
-    mode(T2, T1, c->Wu[1], 1);
-    mode(T1, s, c->Wu[2], 2);
+    launch_blockdiv_f64(ex.stream, T1, T2, 3, n, B, e[0], e[1], e[2]);
+    mode(T2, T1, c->Wu[0], 0);
+    mode(T1, T2, c->Wu[1], 1);
+    mode(T2, s, c->Wu[2], 2);
   } else {
     mode(b, T1, c->Wv[0], 0);
     mode(T1, T2, c->Wv[1], 1);
-    launch_blockdiv_f64(ex.stream, T2, 2, n, B, e[0], e[1], e[1]);
-    mode(T2, T1, c->Wu[0], 0);
-    mode(T1, s, c->Wu[1], 1);
+    launch_blockdiv_f64(ex.stream, T2, T1, 2, n, B, e[0], e[1], e[1]);
+    mode(T1, T2, c->Wu[0], 0);
+    mode(T2, s, c->Wu[1], 1);
   }
   return hip_check(hipGetLastError(), "apply_prec launch");
 }
@@ -422,7 +422,7 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
     dfree(c->Wv[l]); dfree(c->Wu[l]); dfree(c->lam[l]);
     dfree(c->Wv32[l]); dfree(c->Wu32[l]); dfree(c->Wv16[l]); dfree(c->Wu16[l]); dfree(c->lam32[l]);
     dfree(c->bandM[l]); dfree(c->bandK[l]); dfree(c->bandD[l]); dfree(c->bandlo[l]);
-    dfree(c->mu[l]); dfree(c->role[l]);
+    dfree(c->mu[l]); dfree(c->role[l]); dfree(c->bstart[l]);
   }
   dfree(c->fields);
   dfree(c->ell_col); dfree(c->ell_val); dfree(c->ell_lo);
@@ -442,6 +442,41 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
   delete c;
   return FDG_OK;
 }
+
+namespace {
+
+// Block structure of D_l on the device (mu, roles, block starts); mu NULL or all zero:
+// n blocks of size 1.  The caller has validated mu.
+int store_blocks(fdg_ctx *c, int l, const double *mu) {
+  const int n = c->n;
+  std::vector<int8_t> role(c->ldw, 0);
+  std::vector<double> m(c->ldw, 0.0);
+  std::vector<int32_t> start;
+  bool any = false;
+  for (int i = 0; i < n; ++i) {
+    start.push_back(i);
+    if (mu && mu[i] != 0.0) {
+      role[i] = 1;
+      role[i + 1] = 2;
+      m[i] = mu[i];
+      m[i + 1] = mu[i + 1];
+      any = true;
+      ++i;
+    }
+  }
+  int st;
+  if ((st = dalloc(&c->mu[l], (size_t)c->ldw)) != FDG_OK) return st;
+  if ((st = dalloc(&c->role[l], (size_t)c->ldw)) != FDG_OK) return st;
+  if ((st = dalloc(&c->bstart[l], (size_t)c->ldw)) != FDG_OK) return st;
+  HIPCHK(hipMemcpy(c->mu[l], m.data(), m.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->role[l], role.data(), role.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->bstart[l], start.data(), start.size() * 4, hipMemcpyHostToDevice));
+  c->nblocks[l] = (int)start.size();
+  c->pairs[l] = any;
+  return FDG_OK;
+}
+
+}  // namespace
 
 extern "C" int fdg_set_prec_factors(fdg_ctx *c, int l, const double *U, const double *V, const double *lambda) {
   clear_error();
@@ -486,8 +521,8 @@ extern "C" int fdg_set_prec_factors(fdg_ctx *c, int l, const double *U, const do
   HIPCHK(hipMemcpy(c->Wv16[l], bv.data(), bv.size() * 2, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->Wu16[l], bu.data(), bu.size() * 2, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->lam32[l], fl.data(), fl.size() * 4, hipMemcpyHostToDevice));
+  if ((st = store_blocks(c, l, nullptr)) != FDG_OK) return st;
   c->have_factor[l] = true;
-  c->pairs[l] = false;
   c->lam_min[l] = lmin;
   bool all = true;
   double sum = 0.0;
@@ -518,9 +553,6 @@ extern "C" int fdg_set_prec_factors_blocks(fdg_ctx *c, int l, const double *U, c
   if (!c || !U || !V || !lambda) return set_error(FDG_EINVAL, "set_prec_factors_blocks: NULL argument");
   if (l < 0 || l >= c->d) return set_error(FDG_EINVAL, "set_prec_factors_blocks: bad direction %d", l);
   const int n = c->n;
-  std::vector<int8_t> role(c->ldw, 0);
-  std::vector<double> m(c->ldw, 0.0);
-  bool any = false;
   if (mu) {
     for (int i = 0; i < n; ++i) {
       if (!std::isfinite(mu[i])) return set_error(FDG_EINVAL, "set_prec_factors_blocks: non-finite mu");
@@ -528,23 +560,12 @@ extern "C" int fdg_set_prec_factors_blocks(fdg_ctx *c, int l, const double *U, c
       if (!(mu[i] > 0.0) || i + 1 >= n || mu[i + 1] != -mu[i] || lambda[i + 1] != lambda[i])
         return set_error(FDG_EINVAL, "set_prec_factors_blocks: index %d does not start a pair "
                                      "(mu[c] > 0, mu[c+1] = -mu[c], lambda[c+1] = lambda[c])", i);
-      role[i] = 1;
-      role[i + 1] = 2;
-      m[i] = mu[i];
-      m[i + 1] = mu[i + 1];
-      any = true;
       ++i;
     }
   }
   int st = fdg_set_prec_factors(c, l, U, V, lambda);
   if (st != FDG_OK) return st;
-  c->pairs[l] = any;
-  if (!any) return FDG_OK;
-  if ((st = dalloc(&c->mu[l], m.size())) != FDG_OK) return st;
-  if ((st = dalloc(&c->role[l], role.size())) != FDG_OK) return st;
-  HIPCHK(hipMemcpy(c->mu[l], m.data(), m.size() * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->role[l], role.data(), role.size(), hipMemcpyHostToDevice));
-  return FDG_OK;
+  return store_blocks(c, l, mu);
 }
 
 extern "C" int fdg_set_precision(fdg_ctx *c, int prec) {

@@ -25,17 +25,21 @@ void launch_modeprod_f64(hipStream_t s, const double *X, double *Y, const double
 void launch_divide_f64(hipStream_t s, double *t, int d, int n, int64_t nbatch, const double *lam1,
                        const double *lam2, const double *lam3);
 
-// Univariate D_l with 2 x 2 blocks: lam (n), mu (n; +b / -b on a pair's two indices) and
-// role (n; 0 single, 1 first of a pair, 2 second).  All device pointers.
+// Univariate D_l with 2 x 2 blocks: lam (n), mu (n; +b / -b on a pair's two indices),
+// role (n; 0 single, 1 first of a pair, 2 second) and the first index of each of the nb
+// blocks (start, nb entries).  Device pointers.
 struct BlockEig {
   const double *lam = nullptr;
   const double *mu = nullptr;
   const int8_t *role = nullptr;
+  const int32_t *start = nullptr;
+  int nb = 0;
 };
-// t[b] <- (sum_l I x D_l x I)^{-1} t[b] for block-diagonal D_l (e3 unused for d = 2); the
-// entries of a cell never straddle batch entries (a pair never straddles n).
-void launch_blockdiv_f64(hipStream_t s, double *t, int d, int n, int64_t nbatch, const BlockEig &e1,
-                         const BlockEig &e2, const BlockEig &e3);
+// y[b] = (sum_l I x D_l x I)^{-1} t[b] for block-diagonal D_l (e3 unused for d = 2), out
+// of place; one thread per cell (block combination), the entries of a cell never straddle
+// batch entries (a pair never straddles n).
+void launch_blockdiv_f64(hipStream_t s, const double *t, double *y, int d, int n, int64_t nbatch,
+                         const BlockEig &e1, const BlockEig &e2, const BlockEig &e3);
 
 // ---- operator ------------------------------------------------------------------------
 // Banded univariate factors of the unit-domain operator: row i of factor F holds

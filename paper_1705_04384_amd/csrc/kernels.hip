@@ -94,12 +94,12 @@ __global__ __launch_bounds__(kBlock) void k_divide_f64(double *__restrict__ t, i
 }
 
 // Solve of sum_l I x D_l x I for block-diagonal D_l (1 x 1 blocks lam, 2 x 2 blocks
-// [[a, b], [-b, a]] of a pair a +- ib, role 1 / 2 on its first / second index).  The
-// operator decouples into cells: the product of one block per direction (at most
-// 2 x 2 x 2 entries).  The thread of a cell's first entry solves it: in every paired
-// direction the pair (x0, x1) goes to the eigen-coordinates ((x0 - i x1) / 2,
-// (x0 + i x1) / 2) of a + ib and a - ib, each entry is divided by the complex sum of its
-// eigenvalues, and the transform is undone (x0 = z+ + z-, x1 = i (z+ - z-)).
+// [[a, b], [-b, a]] of a pair a +- ib).  The operator decouples into cells, one block
+// per direction (at most 2 x 2 x 2 entries); one thread per cell, consecutive threads
+// taking consecutive blocks of direction 1.  In every paired direction the pair (x0, x1)
+// goes to the eigen-coordinates ((x0 - i x1) / 2, (x0 + i x1) / 2) of a + ib and a - ib,
+// each entry is divided by the complex sum of its eigenvalues (one reciprocal of |sum|^2
+// per entry), and the transform is undone (x0 = z+ + z-, x1 = i (z+ - z-)).
 struct Cplx {
   double re, im;
 };
@@ -118,33 +118,39 @@ __device__ inline void pair_inv(Cplx &z0, Cplx &z1) {  // z0 + z1, i (z0 - z1)
   z1 = q;
 }
 
-// Block of index i in one direction: false when i is the second index of a pair.
-__device__ inline bool cell_dir(const BlockEig &e, int i, int &sz, double &a, double &b) {
-  const int r = e.role[i];
-  if (r == 2) return false;
-  sz = r == 1 ? 2 : 1;
+// Block k of one direction: first index, size and (a, b).
+__device__ inline int cell_dir(const BlockEig &e, int k, int &sz, double &a, double &b) {
+  const int i = e.start[k];
+  const bool pr = e.role[i] == 1;
+  sz = pr ? 2 : 1;
   a = e.lam[i];
-  b = r == 1 ? e.mu[i] : 0.0;
-  return true;
+  b = pr ? e.mu[i] : 0.0;
+  return i;
 }
 
-__global__ __launch_bounds__(kBlock) void k_blockdiv_f64(double *__restrict__ t, int d, int n, int64_t total,
-                                                         BlockEig e1, BlockEig e2, BlockEig e3) {
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const int64_t n2 = (int64_t)n * n;
-  const int i1 = (int)(idx % n), i2 = (int)((idx / n) % n), i3 = d == 3 ? (int)((idx / n2) % n) : 0;
+__global__ __launch_bounds__(kBlock) void k_blockdiv_f64(const double *__restrict__ t, double *__restrict__ y, int d,
+                                                         int n, int64_t cells, BlockEig e1, BlockEig e2,
+                                                         BlockEig e3) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= cells) return;
+  const int64_t nb12 = (int64_t)e1.nb * e2.nb;
+  const int64_t nb123 = d == 3 ? nb12 * e3.nb : nb12;
+  const int64_t ent = id / nb123, r = id - ent * nb123;
+  const int k1 = (int)(r % e1.nb), k2 = (int)((r / e1.nb) % e2.nb), k3 = d == 3 ? (int)(r / nb12) : 0;
   int sz[3] = {1, 1, 1};
   double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
-  if (!cell_dir(e1, i1, sz[0], a[0], b[0]) || !cell_dir(e2, i2, sz[1], a[1], b[1])) return;
-  if (d == 3 && !cell_dir(e3, i3, sz[2], a[2], b[2])) return;
+  const int i1 = cell_dir(e1, k1, sz[0], a[0], b[0]);
+  const int i2 = cell_dir(e2, k2, sz[1], a[1], b[1]);
+  const int i3 = d == 3 ? cell_dir(e3, k3, sz[2], a[2], b[2]) : 0;
+  const int64_t n2 = (int64_t)n * n;
   const int64_t st[3] = {1, n, n2};
+  const int64_t base = ent * (d == 3 ? n2 * n : n2) + i1 + (int64_t)n * i2 + n2 * i3;
   Cplx z[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int t1 = c & 1, t2 = (c >> 1) & 1, t3 = c >> 2;
     const bool in = t1 < sz[0] && t2 < sz[1] && t3 < sz[2];
-    z[c] = Cplx{in ? t[idx + t1 * st[0] + t2 * st[1] + t3 * st[2]] : 0.0, 0.0};
+    z[c] = Cplx{in ? t[base + t1 * st[0] + t2 * st[1] + t3 * st[2]] : 0.0, 0.0};
   }
   // eigen-coordinates in every paired direction (entries c and c + 2^l form a pair)
 #pragma unroll
@@ -156,14 +162,16 @@ __global__ __launch_bounds__(kBlock) void k_blockdiv_f64(double *__restrict__ t,
   }
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
+    const int t1 = c & 1, t2 = (c >> 1) & 1, t3 = c >> 2;
+    if (!(t1 < sz[0] && t2 < sz[1] && t3 < sz[2])) continue;
     double lr = 0.0, li = 0.0;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       lr += a[l];
       li += ((c >> l) & 1) ? -b[l] : b[l];
     }
-    const double den = lr * lr + li * li;  // z / (lr + i li)
-    const Cplx q{(z[c].re * lr + z[c].im * li) / den, (z[c].im * lr - z[c].re * li) / den};
+    const double inv = 1.0 / (lr * lr + li * li);  // z / (lr + i li)
+    const Cplx q{(z[c].re * lr + z[c].im * li) * inv, (z[c].im * lr - z[c].re * li) * inv};
     z[c] = q;
   }
 #pragma unroll
@@ -176,15 +184,14 @@ __global__ __launch_bounds__(kBlock) void k_blockdiv_f64(double *__restrict__ t,
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int t1 = c & 1, t2 = (c >> 1) & 1, t3 = c >> 2;
-    if (t1 < sz[0] && t2 < sz[1] && t3 < sz[2]) t[idx + t1 * st[0] + t2 * st[1] + t3 * st[2]] = z[c].re;
+    if (t1 < sz[0] && t2 < sz[1] && t3 < sz[2]) y[base + t1 * st[0] + t2 * st[1] + t3 * st[2]] = z[c].re;
   }
 }
 
-void launch_blockdiv_f64(hipStream_t s, double *t, int d, int n, int64_t nbatch, const BlockEig &e1,
-                         const BlockEig &e2, const BlockEig &e3) {
-  const int64_t N = (int64_t)n * n * (d == 3 ? n : 1);
-  const int64_t total = N * nbatch;
-  hipLaunchKernelGGL(k_blockdiv_f64, dim3(grid1(total, kBlock)), dim3(kBlock), 0, s, t, d, n, total, e1, e2, e3);
+void launch_blockdiv_f64(hipStream_t s, const double *t, double *y, int d, int n, int64_t nbatch,
+                         const BlockEig &e1, const BlockEig &e2, const BlockEig &e3) {
+  const int64_t cells = (int64_t)e1.nb * e2.nb * (d == 3 ? e3.nb : 1) * nbatch;
+  hipLaunchKernelGGL(k_blockdiv_f64, dim3(grid1(cells, kBlock)), dim3(kBlock), 0, s, t, y, d, n, cells, e1, e2, e3);
 }
 
 void launch_divide_f64(hipStream_t s, double *t, int d, int n, int64_t nbatch, const double *lam1,

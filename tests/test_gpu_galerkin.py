@@ -213,7 +213,10 @@ def _blocks_context(fdg, d, p, n, winds):
         U, V, lam, mu, cu = fdg.factor_pencil_blocks(K + H, M, want_cond=True)
         npairs += int((mu > 0).sum())
         cond = max(cond, cu)
-        ctx.set_prec_factors_blocks(l, U, V, lam, mu)
+        if mu.any():
+            ctx.set_prec_factors_blocks(l, U, V, lam, mu)
+        else:   # directions with real eigenvalues set through the plain entry point
+            ctx.set_prec_factors(l, U, V, lam)
         ctx.set_operator_kron(l, M, K + H)
         Ms.append(M)
         KHs.append(K + H)
@@ -224,7 +227,9 @@ def _blocks_context(fdg, d, p, n, winds):
 # condition (right after the transition they are nearly defective)
 @pytest.mark.parametrize("d,p,n,winds", [(3, 3, 8, (10.0, 20.0, 15.0)), (3, 3, 20, (100.0, 150.0, 80.0)),
                                          (2, 3, 33, (150.0, 150.0)), (2, 2, 17, (150.0, 80.0)),
-                                         (3, 4, 24, (150.0, 100.0, 80.0)), (3, 2, 17, (80.0, 100.0, 150.0))])
+                                         (3, 4, 24, (150.0, 100.0, 80.0)), (3, 2, 17, (80.0, 100.0, 150.0)),
+                                         (3, 2, 17, (150.0, 1.0, 5.0)), (3, 3, 20, (1.0, 100.0, 2.0)),
+                                         (2, 2, 17, (1.0, 150.0))])
 def test_complex_pencil_fd_apply_matches_oracle(d, p, n, winds):
     # the device keeps D in real 2 x 2 blocks; the oracle runs the FD in complex arithmetic.
     # Tolerance: rounding amplified by the condition of the eigenvector basis
