@@ -79,6 +79,10 @@ extern "C" int fdg_factor_pencil_sym(int n, const double *K, const double *M, do
   std::vector<double> Qt(nn, 0.0);
   for (int i = 0; i < n; ++i) Qt[(size_t)i * n + i] = 1.0;
   const double eps = 2.2e-16;
+  double cnorm = 0.0;  // Frobenius norm of C: floor of the skip test for indefinite input
+  for (double x : C) cnorm += x * x;
+  cnorm = std::sqrt(cnorm);
+  const double skip_floor = eps * eps * cnorm + 1e-300;
   bool done = false;
   for (int sweep = 0; sweep < 60 && !done; ++sweep) {
     done = true;
@@ -86,7 +90,7 @@ extern "C" int fdg_factor_pencil_sym(int n, const double *K, const double *M, do
       for (int q = p + 1; q < n; ++q) {
         const double apq = C[(size_t)p * n + q];
         const double app = C[(size_t)p * n + p], aqq = C[(size_t)q * n + q];
-        if (std::fabs(apq) <= eps * std::sqrt(std::fabs(app * aqq))) {
+        if (std::fabs(apq) <= eps * std::sqrt(std::fabs(app * aqq)) || std::fabs(apq) <= skip_floor) {
           C[(size_t)p * n + q] = C[(size_t)q * n + p] = 0.0;
           continue;
         }

@@ -345,10 +345,16 @@ extern "C" int fdg_galerkin_csr(int p, int n, double amp, const double *wind, do
     for (int e3 = cls; e3 < r.E; e3 += P) slabs.push_back(e3);
     const int nt = std::min<int>(nthr, (int)slabs.size());
     std::vector<std::thread> pool;
+    auto work = [&](int t) {
+      for (size_t s = t; s < slabs.size(); s += nt) as.slab(slabs[s]);
+    };
+    try {
+      for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+    } catch (...) {  // no more threads: the calling thread takes the rest
+    }
+    const int started = (int)pool.size() + 1;
     for (int t = 0; t < nt; ++t)
-      pool.emplace_back([&, t]() {
-        for (size_t s = t; s < slabs.size(); s += nt) as.slab(slabs[s]);
-      });
+      if (t == 0 || t >= started) work(t);
     for (auto &th : pool) th.join();
   }
   return FDG_OK;

@@ -323,3 +323,21 @@ def test_galerkin_solve_with_complex_pencils():
     with pytest.raises(fdg.FdgError):
         ctx.apply_prec(bd, x1)
     ctx.close()
+
+
+def test_block_factor_arguments_are_checked():
+    # malformed pairs are rejected before anything is stored
+    fdg = _fdg()
+    n = 12
+    ctx = fdg.Context(2, n)
+    M, K, H = fdg.galerkin_factors(3, n, 100.0, 100.0)
+    U, V, lam, mu, _ = fdg.factor_pencil_blocks(K + H, M)
+    c = int(np.flatnonzero(mu > 0)[0])
+    bad1 = mu.copy(); bad1[c + 1] = mu[c]            # second entry not -b
+    bad2 = mu.copy(); bad2[c] = -mu[c]; bad2[c + 1] = mu[c]   # pair starting with -b
+    bad3 = np.zeros(n); bad3[n - 1] = 1.0            # pair running past n
+    for bad in (bad1, bad2, bad3):
+        with pytest.raises(fdg.FdgError):
+            ctx.set_prec_factors_blocks(0, U, V, lam, bad)
+    ctx.set_prec_factors_blocks(0, U, V, lam, mu)
+    ctx.close()
