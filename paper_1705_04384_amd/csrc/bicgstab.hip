@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kRed) void k_bi_update(const double *__restrict__ s
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 // Device buffers of the context's BiCGStab solve, allocated on first use.
-int ensure_bicg(fdg_ctx *c, BiBufs &B, int G) {
+int ensure_bicg(fdg_ctx *c, BiBufs &B) {
   const size_t N = (size_t)c->N;
   int st;
   if (!c->bicg) {
@@ -217,7 +217,6 @@ int ensure_bicg(fdg_ctx *c, BiBufs &B, int G) {
   }
   B.hh = c->bicg_host;
   B.hh_dev = c->bicg_host_dev;
-  (void)G;
   return FDG_OK;
 }
 
@@ -246,7 +245,7 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
   const int64_t N = c->N;
   const int G = reduction_blocks(N);
   BiBufs B;
-  if ((st = ensure_bicg(c, B, G)) != FDG_OK) return st;
+  if ((st = ensure_bicg(c, B)) != FDG_OK) return st;
   if (!c->phase_ev) HIPCHK(hipEventCreateWithFlags(&c->phase_ev, hipEventDisableTiming));
   const hipStream_t s = c->stream;
   const Exec ex{s, true};
@@ -294,7 +293,6 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
   if ((st = wait()) != FDG_OK) return st;
   const double bnorm = std::sqrt(host_sum(hh + 2 * G, G));
   const double target = rtol * bnorm;
-  int status = FDG_NOT_CONVERGED;
   double rnorm = std::sqrt(host_sum(hh + G, G));
   int half = 0, full = 0;
   bool conv = false, brk = false;
@@ -305,8 +303,7 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
   } else if (!fixed && rnorm <= target) {
     conv = true;
   }
-  const int limit = maxit;
-  for (int i = 1; !conv && !brk && i <= limit; ++i) {
+  for (int i = 1; !conv && !brk && i <= maxit; ++i) {
     const int a = i & 1, o = a ^ 1;
     {
       TimedLaunch tl(c, 2, s, true);
@@ -371,7 +368,7 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
   inf.rel_res_est = bnorm > 0.0 ? rnorm / bnorm : 0.0;
   inf.rel_res_true = bnorm > 0.0 ? tr / bnorm : 0.0;
   inf.converged = bnorm == 0.0 || tr <= target;
-  status = inf.converged ? FDG_OK : FDG_NOT_CONVERGED;
+  const int status = inf.converged ? FDG_OK : FDG_NOT_CONVERGED;
   inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = inf;
   return status;
