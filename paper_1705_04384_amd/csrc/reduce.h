@@ -23,10 +23,11 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Contiguous chunk of block g; chunks are multiples of 2 * kRed elements.
+// Contiguous chunk of block g; chunks are multiples of 64 elements (even, so 2-wide
+// accesses stay aligned, and 512-byte aligned).
 __device__ inline void chunk_of(int64_t N, int G, int g, int64_t &beg, int64_t &end) {
   int64_t chunk = (N + G - 1) / G;
-  chunk = (chunk + 2 * kRed - 1) / (2 * kRed) * (2 * kRed);
+  chunk = (chunk + 63) / 64 * 64;
   beg = (int64_t)g * chunk;
   if (beg > N) beg = N;
   end = beg + chunk < N ? beg + chunk : N;
