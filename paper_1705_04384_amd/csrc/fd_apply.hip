@@ -28,14 +28,11 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-#ifndef FDG_FD_NT
-#define FDG_FD_NT 2
-#endif
 #ifndef FDG_FD_LDS_PAD
 #define FDG_FD_LDS_PAD 2
 #endif
-constexpr int kNT = FDG_FD_NT;   // 16-column MFMA tiles per wave
-constexpr int kNB = 16 * kNT;    // columns per workgroup
+// NT: 16-column MFMA tiles per wave, 16 NT columns per workgroup (a template parameter of
+// every kernel: 2 at large n, 1 where fewer columns per workgroup give more workgroups)
 constexpr int kPad = FDG_FD_LDS_PAD;  // LDS row padding (doubles, even: rows stay 16-byte aligned)
 
 __device__ inline dbl4 mfma(double a, double b, dbl4 c) {
@@ -59,65 +56,65 @@ __device__ inline void load4_pad(const double *p, double (&v)[4]) {  // always i
   v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
 }
 
-// Fragments of one 16-wide k-block: MT row tiles of A, kNT column tiles of B (4 contraction
+// Fragments of one 16-wide k-block: MT row tiles of A, NT column tiles of B (4 contraction
 // indices each per lane).
-template <int MT>
+template <int MT, int NT>
 struct Frag {
   double a[MT][4];
-  double b[kNT][4];
+  double b[NT][4];
 };
 
-template <int MT>
-__device__ inline void mma_block(const Frag<MT> &f, dbl4 (&acc)[MT][kNT]) {
+template <int MT, int NT>
+__device__ inline void mma_block(const Frag<MT, NT> &f, dbl4 (&acc)[MT][NT]) {
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
-      for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(f.a[a][t], f.b[b][t], acc[a][b]);
+      for (int b = 0; b < NT; ++b) acc[a][b] = mfma(f.a[a][t], f.b[b][t], acc[a][b]);
 }
 
 // acc = sum over k-blocks j0 = 0, 16, .., kpad-16 of load(j0); the next block's operands are
 // loaded before the current block's MFMAs are issued (two register buffers).
-template <int MT, typename Load>
-__device__ inline void gemm_pipelined(int kpad, Load load, dbl4 (&acc)[MT][kNT]) {
+template <int MT, int NT, typename Load>
+__device__ inline void gemm_pipelined(int kpad, Load load, dbl4 (&acc)[MT][NT]) {
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-  Frag<MT> f0, f1;
+    for (int b = 0; b < NT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  Frag<MT, NT> f0, f1;
   load(0, f0);
   for (int j0 = 0; j0 < kpad; j0 += 32) {
     const bool has1 = j0 + 16 < kpad;
     if (has1) load(j0 + 16, f1);
-    mma_block<MT>(f0, acc);
+    mma_block<MT, NT>(f0, acc);
     if (has1) {
       if (j0 + 32 < kpad) load(j0 + 32, f0);
-      mma_block<MT>(f1, acc);
+      mma_block<MT, NT>(f1, acc);
     }
   }
 }
 
 // acc = sum over the KB k-blocks of (A fragments already in registers) x (B from load_b);
 // B fragments are double-buffered.  k-blocks at or beyond kpad are skipped.
-template <int MT, int KB, typename LoadB>
+template <int MT, int NT, int KB, typename LoadB>
 __device__ inline void gemm_preloaded_a(int kpad, const double (&xa)[MT][KB][4], LoadB load_b,
-                                        dbl4 (&acc)[MT][kNT]) {
+                                        dbl4 (&acc)[MT][NT]) {
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < kNT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < NT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
     if (kb * 16 >= kpad) break;
-    double bv[kNT][4];
+    double bv[NT][4];
     load_b(kb * 16, bv);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int b = 0; b < kNT; ++b) acc[a][b] = mfma(xa[a][kb][t], bv[b][t], acc[a][b]);
+        for (int b = 0; b < NT; ++b) acc[a][b] = mfma(xa[a][kb][t], bv[b][t], acc[a][b]);
   }
 }
 
@@ -129,7 +126,7 @@ __device__ inline void gemm_preloaded_a(int kpad, const double (&xa)[MT][KB][4],
 //   2D divide: Y2[k2][c] /= lam2[k2] + lam1[c].
 // The LDS buffer holds the W1 column tile during GEMM1 and then Y1 (transposed).
 // ------------------------------------------------------------------------------------
-template <int WAVES, int MT, bool VEC, bool DIV, bool PRE>
+template <int WAVES, int MT, int NT, bool VEC, bool DIV, bool PRE>
 __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBatch Y,
                                                      const double *__restrict__ W1, const double *__restrict__ W2,
                                                      int ldw, int n, int64_t nslab, int spe, int ncb, int xcd_remap,
@@ -138,6 +135,7 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
   constexpr int MPAD = WAVES * MT * 16;
   constexpr int LDP = MPAD + kPad;
   constexpr int NTHR = 64 * WAVES;
+  constexpr int kNB = 16 * NT;
   __shared__ double buf[kNB * LDP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -188,18 +186,18 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
   __syncthreads();
 
   // ---- GEMM1 ----
-  dbl4 acc[MT][kNT];
+  dbl4 acc[MT][NT];
   if (PRE) {
-    gemm_preloaded_a<MT, KB>(kpad, xa, [&](int j0, double (&bv)[kNT][4]) {
+    gemm_preloaded_a<MT, NT, KB>(kpad, xa, [&](int j0, double (&bv)[NT][4]) {
       const int j = j0 + 4 * lg;
 #pragma unroll
-      for (int b = 0; b < kNT; ++b) {
+      for (int b = 0; b < NT; ++b) {
         const double *p = buf + (16 * b + li) * LDP + j;
         bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
       }
     }, acc);
   } else {
-    gemm_pipelined<MT>(kpad, [&](int j0, Frag<MT> &f) {
+    gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
       const int j = j0 + 4 * lg;
 #pragma unroll
       for (int a = 0; a < MT; ++a) {
@@ -207,7 +205,7 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
         load4<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
       }
 #pragma unroll
-      for (int b = 0; b < kNT; ++b) {
+      for (int b = 0; b < NT; ++b) {
         const double *p = buf + (16 * b + li) * LDP + j;
         f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
       }
@@ -217,24 +215,24 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < kNT; ++b)
+    for (int b = 0; b < NT; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + lg + 4 * r] = acc[a][b][r];
   __syncthreads();
 
   // ---- GEMM2 ----
-  gemm_pipelined<MT>(kpad, [&](int j0, Frag<MT> &f) {
+  gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
     const int j = j0 + 4 * lg;
 #pragma unroll
     for (int a = 0; a < MT; ++a) load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + j, f.a[a]);
 #pragma unroll
-    for (int b = 0; b < kNT; ++b) {
+    for (int b = 0; b < NT; ++b) {
       const double *p = buf + (16 * b + li) * LDP + j;
       f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
     }
   }, acc);
 #pragma unroll
-  for (int b = 0; b < kNT; ++b) {
+  for (int b = 0; b < NT; ++b) {
     const int c = c0 + 16 * b + li;
     if (c >= n) continue;
 #pragma unroll
@@ -257,7 +255,7 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
 //   GEMM1: T[k3][c] = sum_i3 Wa[k3][i3] X[i3][c];   T /= lam3[k3] + lam2[i2] + lam1[i1]
 //   GEMM2: S[k3][c] = sum_k Wb[k3][k] T[k][c]        (T back in LDS, transposed)
 // ------------------------------------------------------------------------------------
-template <int WAVES, int MT>
+template <int WAVES, int MT, int NT>
 __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
                                                       const double *__restrict__ Wa, const double *__restrict__ Wb,
                                                       int ldw, int n, int ncb, const double *__restrict__ lam1,
@@ -266,6 +264,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   constexpr int MPAD = WAVES * MT * 16;
   constexpr int LDP = MPAD + kPad;
   constexpr int NTHR = 64 * WAVES;
+  constexpr int kNB = 16 * NT;
   __shared__ double xt[kNB * LDP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -284,14 +283,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
     xt[c * LDP + i3] = (i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0;
   }
   __syncthreads();
-  dbl4 acc[MT][kNT];
+  dbl4 acc[MT][NT];
   auto lds_gemm = [&](const double *W) {
-    gemm_pipelined<MT>(kpad, [&](int j0, Frag<MT> &f) {
+    gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
       const int j = j0 + 4 * lg;
 #pragma unroll
       for (int a = 0; a < MT; ++a) load4_pad(W + (size_t)(m0 + 16 * a + li) * ldw + j, f.a[a]);
 #pragma unroll
-      for (int b = 0; b < kNT; ++b) {
+      for (int b = 0; b < NT; ++b) {
         const double *p = xt + (16 * b + li) * LDP + j;
         f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
       }
@@ -300,7 +299,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   lds_gemm(Wa);
   __syncthreads();  // every wave has finished reading xt
 #pragma unroll
-  for (int b = 0; b < kNT; ++b) {
+  for (int b = 0; b < NT; ++b) {
     const int64_t cg = c0 + 16 * b + li;
     const bool cok = cg < n2;
     const int i2 = cok ? (int)(cg / n) : 0, i1 = cok ? (int)(cg % n) : 0;
@@ -317,7 +316,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   __syncthreads();
   lds_gemm(Wb);
 #pragma unroll
-  for (int b = 0; b < kNT; ++b) {
+  for (int b = 0; b < NT; ++b) {
     const int64_t cg = c0 + 16 * b + li;
     if (cg >= n2) continue;
 #pragma unroll
@@ -339,10 +338,11 @@ void launch_timed(K kernel, dim3 grid, dim3 blk, hipStream_t s, hipEvent_t ev0, 
     hipLaunchKernelGGL(kernel, grid, blk, 0, s, args...);
 }
 
-template <int WAVES, int MT>
+template <int WAVES, int MT, int NT>
 void slab_launch(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
                  int64_t nslab, int spe, bool div, const double *lam1, const double *lam2, bool aligned32,
                  hipEvent_t ev0, hipEvent_t ev1) {
+  constexpr int kNB = 16 * NT;
   const int ncb = (n + kNB - 1) / kNB;
   const int64_t nwg = nslab * ncb;
   const int remap = (nslab % 8 == 0) ? 1 : 0;
@@ -351,64 +351,72 @@ void slab_launch(hipStream_t s, CBatch X, MBatch Y, const double *W1, const doub
   constexpr bool PRE = false;  // preloading the X strip measured slower at n = 128
   if (div) {
     if (vec)
-      launch_timed(k_slab<WAVES, MT, true, true, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe, ncb,
+      launch_timed(k_slab<WAVES, MT, NT, true, true, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe, ncb,
                    remap, lam1, lam2);
     else
-      launch_timed(k_slab<WAVES, MT, false, true, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+      launch_timed(k_slab<WAVES, MT, NT, false, true, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
                    ncb, remap, lam1, lam2);
   } else {
     if (vec)
-      launch_timed(k_slab<WAVES, MT, true, false, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+      launch_timed(k_slab<WAVES, MT, NT, true, false, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
                    ncb, remap, lam1, lam2);
     else
-      launch_timed(k_slab<WAVES, MT, false, false, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+      launch_timed(k_slab<WAVES, MT, NT, false, false, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
                    ncb, remap, lam1, lam2);
   }
 }
 
-template <int WAVES, int MT>
+template <int WAVES, int MT, int NT>
 void fibre_launch(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const double *Wb, int ldw, int n,
                   int64_t batch, const double *lam1, const double *lam2, const double *lam3, hipEvent_t ev0,
                   hipEvent_t ev1) {
+  constexpr int kNB = 16 * NT;
   const int64_t n2 = (int64_t)n * n;
   const int ncb = (int)((n2 + kNB - 1) / kNB);
   const dim3 grid((unsigned)(batch * ncb)), blk(64 * WAVES);
-  launch_timed(k_fibre<WAVES, MT>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
+  launch_timed(k_fibre<WAVES, MT, NT>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
 }
 
 }  // namespace
 
 bool fd_fused_supported(int n) { return n >= 1 && n <= 256; }
 
-// Workgroup shape (waves, 16-row tiles per wave) for a given n: MPAD = 16 * waves * MT
-// covers roundup(n, 16) with little padding (MPAD <= ldw always holds).
+// Workgroup shape (waves, 16-row tiles per wave, 16-column tiles per wave) for a given n:
+// MPAD = 16 * waves * MT covers roundup(n, 16) with little padding (MPAD <= ldw always
+// holds).  NT = 1 (16 columns per workgroup, twice the workgroups) where the passes would
+// otherwise leave compute units idle: 3D n <= 96 and the 2D solve (one slab per entry).
+// Measured (FP64 apply, us, NT = 2 -> 1): 3D n = 32: 16.8 -> 13.0, 64: 25.1 -> 19.3,
+// 96: 61 -> 57; 2D n = 256: 90 -> 70; 3D n = 128: 85 -> 113 (kept at NT = 2).
 struct Shape {
-  int waves, mt;
+  int waves, mt, nt;
 };
 
-static Shape pick_shape(int n) {
+static Shape pick_shape(int n, bool small_grid) {
 #if defined(FDG_FD_FORCE_W) && defined(FDG_FD_FORCE_MT)
   if (16 * FDG_FD_FORCE_W * FDG_FD_FORCE_MT >= ((n + 15) & ~15) &&
       16 * FDG_FD_FORCE_W * FDG_FD_FORCE_MT <= ((n + 63) / 64) * 64)
-    return {FDG_FD_FORCE_W, FDG_FD_FORCE_MT};
+    return {FDG_FD_FORCE_W, FDG_FD_FORCE_MT, 2};
 #endif
+  const int nt = (small_grid || n <= 96) ? 1 : 2;
   const int k = (n + 15) / 16;  // 16-row tiles needed
-  if (k <= 4) return {4, 1};
-  if (k <= 8) return {k, 1};    // 5..8 waves, one tile each
-  if (k <= 12) return {12, 1};  // measured: 12 x 1 beats 6 x 2 and 4 x 3 for n in 129..192
-  return {8, 2};
+  if (k <= 4) return {4, 1, nt};
+  if (k <= 8) return {k, 1, nt};    // 5..8 waves, one tile each
+  if (k <= 12) return {12, 1, nt};  // measured: 12 x 1 beats 6 x 2 and 4 x 3 for n in 129..192
+  return {8, 2, nt};
 }
 
-#define FDG_SHAPES(X) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(4, 2) X(6, 2) X(8, 2) X(4, 3) X(12, 1)
+#define FDG_SHAPES(X)                                                                             \
+  X(4, 1, 1) X(5, 1, 1) X(6, 1, 1) X(7, 1, 1) X(8, 1, 1) X(8, 2, 1) X(12, 1, 1)                 \
+  X(4, 1, 2) X(5, 1, 2) X(6, 1, 2) X(7, 1, 2) X(8, 1, 2) X(4, 2, 2) X(6, 2, 2) X(8, 2, 2) X(4, 3, 2) X(12, 1, 2)
 
 void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
                      int64_t nentries, int spe, bool divide, const double *lam1, const double *lam2, bool aligned32,
                      hipEvent_t ev0, hipEvent_t ev1) {
-  const Shape sh = pick_shape(n);
+  const Shape sh = pick_shape(n, spe == 1);
   const int64_t nslab = nentries * spe;
-#define FDG_CASE(W, M)                                                                    \
-  if (sh.waves == W && sh.mt == M) {                                                     \
-    slab_launch<W, M>(s, X, Y, W1, W2, ldw, n, nslab, spe, divide, lam1, lam2, aligned32, ev0, ev1); \
+#define FDG_CASE(W, M, T)                                                                  \
+  if (sh.waves == W && sh.mt == M && sh.nt == T) {                                       \
+    slab_launch<W, M, T>(s, X, Y, W1, W2, ldw, n, nslab, spe, divide, lam1, lam2, aligned32, ev0, ev1); \
     return;                                                                              \
   }
   FDG_SHAPES(FDG_CASE)
@@ -418,11 +426,11 @@ void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const 
 void launch_fibre_f64(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const double *Wb, int ldw, int n,
                       int64_t batch, const double *lam1, const double *lam2, const double *lam3, hipEvent_t ev0,
                       hipEvent_t ev1) {
-  const Shape sh = pick_shape(n);
-#define FDG_CASE(W, M)                                                                  \
-  if (sh.waves == W && sh.mt == M) {                                                   \
-    fibre_launch<W, M>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3, ev0, ev1);   \
-    return;                                                                            \
+  const Shape sh = pick_shape(n, false);
+#define FDG_CASE(W, M, T)                                                               \
+  if (sh.waves == W && sh.mt == M && sh.nt == T) {                                    \
+    fibre_launch<W, M, T>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3, ev0, ev1); \
+    return;                                                                           \
   }
   FDG_SHAPES(FDG_CASE)
 #undef FDG_CASE
