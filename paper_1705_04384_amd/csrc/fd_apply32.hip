@@ -22,8 +22,8 @@ namespace {
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-constexpr int kNT = 2;         // 16-column MFMA tiles per wave
-constexpr int kNB = 16 * kNT;  // columns per workgroup
+// NT: 16-column MFMA tiles per wave (16 NT columns per workgroup), a template parameter:
+// 2 at large n, 1 where more workgroups are needed to fill the device
 constexpr int kPad = 4;        // LDS row padding (floats)
 
 __device__ inline flt4 mfma32(float a, float b, flt4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
@@ -35,37 +35,37 @@ __device__ inline void load4f(const T *p, int j, int jmax, bool ok, float (&v)[4
   for (int t = 0; t < 4; ++t) v[t] = (ok && j + t < jmax) ? (float)p[t] : 0.0f;
 }
 
-template <int MT>
+template <int MT, int NT>
 struct Frag32 {
   float a[MT][4];
-  float b[kNT][4];
+  float b[NT][4];
 };
 
-template <int MT>
-__device__ inline void mma_block32(const Frag32<MT> &f, flt4 (&acc)[MT][kNT]) {
+template <int MT, int NT>
+__device__ inline void mma_block32(const Frag32<MT, NT> &f, flt4 (&acc)[MT][NT]) {
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
-      for (int b = 0; b < kNT; ++b) acc[a][b] = mfma32(f.a[a][t], f.b[b][t], acc[a][b]);
+      for (int b = 0; b < NT; ++b) acc[a][b] = mfma32(f.a[a][t], f.b[b][t], acc[a][b]);
 }
 
-template <int MT, typename Load>
-__device__ inline void gemm32(int kpad, Load load, flt4 (&acc)[MT][kNT]) {
+template <int MT, int NT, typename Load>
+__device__ inline void gemm32(int kpad, Load load, flt4 (&acc)[MT][NT]) {
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < kNT; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
-  Frag32<MT> f0, f1;
+    for (int b = 0; b < NT; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
+  Frag32<MT, NT> f0, f1;
   load(0, f0);
   for (int j0 = 0; j0 < kpad; j0 += 32) {
     const bool has1 = j0 + 16 < kpad;
     if (has1) load(j0 + 16, f1);
-    mma_block32<MT>(f0, acc);
+    mma_block32<MT, NT>(f0, acc);
     if (has1) {
       if (j0 + 32 < kpad) load(j0 + 32, f0);
-      mma_block32<MT>(f1, acc);
+      mma_block32<MT, NT>(f1, acc);
     }
   }
 }
@@ -75,7 +75,7 @@ __device__ inline void gemm32(int kpad, Load load, flt4 (&acc)[MT][kNT]) {
 //   GEMM1: Y1[i2][c] = sum_i1 X[s][i2][i1] W1[c][i1]   (W1 column tile in LDS)
 //   GEMM2: Y2[k2][c] = sum_i2 W2[k2][i2] Y1[i2][c]     (Y1 in LDS, transposed)
 //   2D: Y2[k2][c] /= lam2[k2] + lam1[c].
-template <int WAVES, int MT, typename TI, typename TO, bool DIV>
+template <int WAVES, int MT, int NT, typename TI, typename TO, bool DIV>
 __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X, TO *__restrict__ Y,
                                                        const float *__restrict__ W1, const float *__restrict__ W2,
                                                        int ldw, int n, int64_t nslab, int ncb, int xcd_remap,
@@ -83,6 +83,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
   constexpr int MPAD = WAVES * MT * 16;
   constexpr int LDP = MPAD + kPad;
   constexpr int NTHR = 64 * WAVES;
+  constexpr int kNB = 16 * NT;
   __shared__ float buf[kNB * LDP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -111,8 +112,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
     buf[c * LDP + j] = W1[(size_t)(c0 + c) * ldw + j];
   }
   __syncthreads();
-  flt4 acc[MT][kNT];
-  gemm32<MT>(kpad, [&](int j0, Frag32<MT> &f) {
+  flt4 acc[MT][NT];
+  gemm32<MT, NT>(kpad, [&](int j0, Frag32<MT, NT> &f) {
     const int j = j0 + 4 * lg;
 #pragma unroll
     for (int a = 0; a < MT; ++a) {
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
       load4f(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
     }
 #pragma unroll
-    for (int b = 0; b < kNT; ++b) {
+    for (int b = 0; b < NT; ++b) {
       const float *p = buf + (16 * b + li) * LDP + j;
       f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
     }
@@ -129,11 +130,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < kNT; ++b)
+    for (int b = 0; b < NT; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + 4 * lg + r] = acc[a][b][r];
   __syncthreads();
-  gemm32<MT>(kpad, [&](int j0, Frag32<MT> &f) {
+  gemm32<MT, NT>(kpad, [&](int j0, Frag32<MT, NT> &f) {
     const int j = j0 + 4 * lg;
 #pragma unroll
     for (int a = 0; a < MT; ++a) {
@@ -141,13 +142,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
       f.a[a][0] = w[0]; f.a[a][1] = w[1]; f.a[a][2] = w[2]; f.a[a][3] = w[3];
     }
 #pragma unroll
-    for (int b = 0; b < kNT; ++b) {
+    for (int b = 0; b < NT; ++b) {
       const float *p = buf + (16 * b + li) * LDP + j;
       f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
     }
   }, acc);
 #pragma unroll
-  for (int b = 0; b < kNT; ++b) {
+  for (int b = 0; b < NT; ++b) {
     const int c = c0 + 16 * b + li;
     if (c >= n) continue;
 #pragma unroll
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
 
 // Pass B: workgroup = (entry, block of kNB columns c of X[i3][c]); the block is staged
 // transposed in LDS, then T = Wa X, T /= lam3 + lam2 + lam1, S = Wb T.
-template <int WAVES, int MT>
+template <int WAVES, int MT, int NT>
 __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict__ X, float *__restrict__ Y,
                                                         const float *__restrict__ Wa, const float *__restrict__ Wb,
                                                         int ldw, int n, int ncb, const float *__restrict__ lam1,
@@ -174,6 +175,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
   constexpr int MPAD = WAVES * MT * 16;
   constexpr int LDP = MPAD + kPad;
   constexpr int NTHR = 64 * WAVES;
+  constexpr int kNB = 16 * NT;
   __shared__ float xt[kNB * LDP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -191,9 +193,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
     xt[c * LDP + i3] = (i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0f;
   }
   __syncthreads();
-  flt4 acc[MT][kNT];
+  flt4 acc[MT][NT];
   auto lds_gemm = [&](const float *W) {
-    gemm32<MT>(kpad, [&](int j0, Frag32<MT> &f) {
+    gemm32<MT, NT>(kpad, [&](int j0, Frag32<MT, NT> &f) {
       const int j = j0 + 4 * lg;
 #pragma unroll
       for (int a = 0; a < MT; ++a) {
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
         f.a[a][0] = w[0]; f.a[a][1] = w[1]; f.a[a][2] = w[2]; f.a[a][3] = w[3];
       }
 #pragma unroll
-      for (int b = 0; b < kNT; ++b) {
+      for (int b = 0; b < NT; ++b) {
         const float *p = xt + (16 * b + li) * LDP + j;
         f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
       }
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
   lds_gemm(Wa);
   __syncthreads();
 #pragma unroll
-  for (int b = 0; b < kNT; ++b) {
+  for (int b = 0; b < NT; ++b) {
     const int64_t cg = c0 + 16 * b + li;
     const bool cok = cg < n2;
     const int i2 = cok ? (int)(cg / n) : 0, i1 = cok ? (int)(cg % n) : 0;
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
   __syncthreads();
   lds_gemm(Wb);
 #pragma unroll
-  for (int b = 0; b < kNT; ++b) {
+  for (int b = 0; b < NT; ++b) {
     const int64_t cg = c0 + 16 * b + li;
     if (cg >= n2) continue;
 #pragma unroll
@@ -239,42 +241,48 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
   }
 }
 
+// Workgroup shape as for the FP64 passes (waves, 16-row tiles per wave, 16-column tiles
+// per wave): 16 columns per workgroup for 3D n <= 96 and the 2D solve.
 struct Shape32 {
-  int waves, mt;
+  int waves, mt, nt;
 };
 
-Shape32 pick_shape32(int n) {
+Shape32 pick_shape32(int n, bool small_grid) {
+  const int nt = (small_grid || n <= 96) ? 1 : 2;
   const int k = (n + 15) / 16;
-  if (k <= 4) return {4, 1};
-  if (k <= 8) return {k, 1};
-  if (k <= 12) return {12, 1};
-  return {8, 2};
+  if (k <= 4) return {4, 1, nt};
+  if (k <= 8) return {k, 1, nt};
+  if (k <= 12) return {12, 1, nt};
+  return {8, 2, nt};
 }
 
-#define FDG_SHAPES32(X) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(12, 1) X(8, 2)
+#define FDG_SHAPES32(X)                                                                          \
+  X(4, 1, 1) X(5, 1, 1) X(6, 1, 1) X(7, 1, 1) X(8, 1, 1) X(12, 1, 1) X(8, 2, 1)                  \
+  X(4, 1, 2) X(5, 1, 2) X(6, 1, 2) X(7, 1, 2) X(8, 1, 2) X(12, 1, 2) X(8, 2, 2)
 
-template <int W, int M, typename TI, typename TO>
+template <int W, int M, int NT, typename TI, typename TO>
 void slab32(hipStream_t s, const TI *X, TO *Y, const float *W1, const float *W2, int ldw, int n, int64_t nslab,
             bool div, const float *lam1, const float *lam2) {
+  constexpr int kNB = 16 * NT;
   const int ncb = (n + kNB - 1) / kNB;
   const int remap = (nslab % 8 == 0) ? 1 : 0;
   const dim3 grid((unsigned)(nslab * ncb)), blk(64 * W);
   if (div)
-    hipLaunchKernelGGL((k_slab32<W, M, TI, TO, true>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, lam1,
-                       lam2);
+    hipLaunchKernelGGL((k_slab32<W, M, NT, TI, TO, true>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap,
+                       lam1, lam2);
   else
-    hipLaunchKernelGGL((k_slab32<W, M, TI, TO, false>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap,
+    hipLaunchKernelGGL((k_slab32<W, M, NT, TI, TO, false>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap,
                        lam1, lam2);
 }
 
 template <typename TI, typename TO>
 void slab32_dispatch(hipStream_t s, const TI *X, TO *Y, const float *W1, const float *W2, int ldw, int n,
-                     int64_t nslab, bool div, const float *lam1, const float *lam2) {
-  const Shape32 sh = pick_shape32(n);
-#define FDG_CASE(W, M)                                                        \
-  if (sh.waves == W && sh.mt == M) {                                         \
-    slab32<W, M, TI, TO>(s, X, Y, W1, W2, ldw, n, nslab, div, lam1, lam2); \
-    return;                                                                  \
+                     int64_t nslab, bool two_d, bool div, const float *lam1, const float *lam2) {
+  const Shape32 sh = pick_shape32(n, two_d);
+#define FDG_CASE(W, M, T)                                                        \
+  if (sh.waves == W && sh.mt == M && sh.nt == T) {                              \
+    slab32<W, M, T, TI, TO>(s, X, Y, W1, W2, ldw, n, nslab, div, lam1, lam2);   \
+    return;                                                                     \
   }
   FDG_SHAPES32(FDG_CASE)
 #undef FDG_CASE
@@ -282,14 +290,14 @@ void slab32_dispatch(hipStream_t s, const TI *X, TO *Y, const float *W1, const f
 
 void fibre32_dispatch(hipStream_t s, const float *X, float *Y, const float *Wa, const float *Wb, int ldw, int n,
                       int64_t batch, const float *lam1, const float *lam2, const float *lam3) {
-  const Shape32 sh = pick_shape32(n);
+  const Shape32 sh = pick_shape32(n, false);
   const int64_t n2 = (int64_t)n * n;
-  const int ncb = (int)((n2 + kNB - 1) / kNB);
-  const dim3 grid((unsigned)(batch * ncb));
-#define FDG_CASE(W, M)                                                                                            \
-  if (sh.waves == W && sh.mt == M) {                                                                             \
-    hipLaunchKernelGGL((k_fibre32<W, M>), grid, dim3(64 * W), 0, s, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3); \
-    return;                                                                                                       \
+#define FDG_CASE(W, M, T)                                                                                         \
+  if (sh.waves == W && sh.mt == M && sh.nt == T) {                                                               \
+    const int ncb = (int)((n2 + 16 * T - 1) / (16 * T));                                                         \
+    hipLaunchKernelGGL((k_fibre32<W, M, T>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, Wa, Wb, ldw, \
+                       n, ncb, lam1, lam2, lam3);                                                                \
+    return;                                                                                                      \
   }
   FDG_SHAPES32(FDG_CASE)
 #undef FDG_CASE
@@ -301,12 +309,12 @@ void launch_fd_apply_f32(hipStream_t s, int d, int n, int64_t batch, const doubl
                          float *t2, const float *const *Wv, const float *const *Wu, const float *const *lam, int ldw) {
   if (d == 3) {
     const int64_t nslab = batch * n;
-    slab32_dispatch<double, float>(s, b, t1, Wv[0], Wv[1], ldw, n, nslab, false, nullptr, nullptr);
+    slab32_dispatch<double, float>(s, b, t1, Wv[0], Wv[1], ldw, n, nslab, false, false, nullptr, nullptr);
     fibre32_dispatch(s, t1, t2, Wv[2], Wu[2], ldw, n, batch, lam[0], lam[1], lam[2]);
-    slab32_dispatch<float, double>(s, t2, out, Wu[0], Wu[1], ldw, n, nslab, false, nullptr, nullptr);
+    slab32_dispatch<float, double>(s, t2, out, Wu[0], Wu[1], ldw, n, nslab, false, false, nullptr, nullptr);
   } else {
-    slab32_dispatch<double, float>(s, b, t1, Wv[0], Wv[1], ldw, n, batch, true, lam[0], lam[1]);
-    slab32_dispatch<float, double>(s, t1, out, Wu[0], Wu[1], ldw, n, batch, false, nullptr, nullptr);
+    slab32_dispatch<double, float>(s, b, t1, Wv[0], Wv[1], ldw, n, batch, true, true, lam[0], lam[1]);
+    slab32_dispatch<float, double>(s, t1, out, Wu[0], Wu[1], ldw, n, batch, true, false, nullptr, nullptr);
   }
 }
 
