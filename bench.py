@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-solves", type=int, default=4)
+    ap.add_argument("--cpu-solves", type=int, default=40)
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the oracle on every configuration, at one thread and at all cores")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the deformed-cube and precision-sweep fields")
@@ -391,8 +393,63 @@ def cpu_baseline(p, n, f, noise, count):
                        f"(alternating the two right-hand sides), {dt:.1f} s, iterations {its}")
 
 
+def oracle_timing():
+    """CPU-baseline leg, extended: the oracle on every configuration (one solve each, setup
+    excluded), at one BLAS thread and at all cores, with the host CPU named."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import colloc, fd, fgmres
+    from paper_1705_04384_amd import inputs
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"cpu": cpu, "cpu_count": os.cpu_count(), "configs": {}}
+
+    def unit(d, p, n):
+        M, K, _, _ = colloc.colloc_factors(p, n)
+        U, V, lam = fd.factor_pencil(K, M)
+        mv = lambda v: colloc.unit_matvec([M] * d, [K] * d, v)
+        pr = lambda v: fd.fd_apply([U] * d, [V] * d, [lam] * d, v)
+        return mv, pr
+
+    cases = []
+    mv, pr = unit(2, 3, 33)
+    cases.append(("2D p=3 n=33 FGMRES(30)", mv, pr, colloc.manufactured_rhs(3, 33, 2), 30))
+    mv, pr = unit(3, 4, 128)
+    cases.append(("3D p=4 n=128 FGMRES(30)", mv, pr, inputs.rhs_normal(inputs.SEED_NOISE_128, 128 ** 3), 30))
+    t0 = time.perf_counter()
+    A = colloc.deformed_operator(3, 96, 0.1)
+    asm = time.perf_counter() - t0
+    M, K, _, _ = colloc.colloc_factors(3, 96)
+    U, V, lam = fd.factor_pencil(K, M)
+    cases.append(("3D deformed p=3 n=96 FGMRES(30)", lambda v: A @ v,
+                  lambda v: fd.fd_apply([U] * 3, [V] * 3, [lam] * 3, v),
+                  inputs.rhs_uniform(inputs.SEED_DEFORMED_96, 96 ** 3), 30))
+    mv, pr = unit(3, 6, 192)
+    cases.append(("3D p=6 n=192 FGMRES(50)", mv, pr, inputs.rhs_normal(inputs.SEED_SWEEP_192, 192 ** 3), 50))
+    for name, mv, pr, b, m in cases:
+        row = {}
+        for label, limit in (("all_cores", None), ("one_thread", 1)):
+            with threadpool_limits(limits=limit):
+                t0 = time.perf_counter()
+                _, info = fgmres.fgmres(mv, pr, b, rtol=1e-8, restart=m)
+                row[label + "_s"] = time.perf_counter() - t0
+            row["iterations"] = info["iterations"]
+        out["configs"][name] = row
+    out["configs"]["3D deformed p=3 n=96 FGMRES(30)"]["assembly_s"] = asm
+    return out
+
+
 def main():
     args = parse()
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
