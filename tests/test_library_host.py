@@ -221,3 +221,33 @@ def test_factor_pencil_blocks_equals_plain_for_real_pencils():
     U2, V2, lam2, _ = fdg.factor_pencil(K, M, want_cond=False)
     assert not np.any(mu)
     assert np.array_equal(U, U2) and np.array_equal(V, V2) and np.array_equal(lam, lam2)
+
+
+def test_galerkin_and_block_entry_points_reject_bad_arguments():
+    _lib()
+    with pytest.raises(fdg.FdgError):
+        fdg.galerkin_factors(0, 10)          # degree must be >= 1
+    with pytest.raises(fdg.FdgError):
+        fdg.galerkin_factors(5, 2)           # fewer than p - 1 unknowns
+    with pytest.raises(fdg.FdgError):
+        fdg.galerkin_csr(3, 1300)            # n^3 beyond int32 column indices
+    with pytest.raises(fdg.FdgError):
+        fdg.galerkin_csr(3, 8, amp=float("nan"))
+    M, K, H = fdg.galerkin_factors(3, 10, 2.0, 2.0)
+    with pytest.raises(fdg.FdgError):
+        fdg.factor_pencil_sym(K + H, M)      # not symmetric
+    K2 = K.copy()
+    K2[0, 0] = float("inf")
+    with pytest.raises(fdg.FdgError):
+        fdg.factor_pencil_blocks(K2, M)      # non-finite input
+
+
+def test_galerkin_csr_sizes_and_symmetric_diffusion():
+    # without wind the Galerkin matrix is symmetric (Q is), assembled in its stencil
+    _lib()
+    p, n = 3, 9
+    rowptr, col, val = fdg.galerkin_csr(p, n, 0.1)
+    A = sp.csr_matrix((val, col, rowptr), shape=(n ** 3, n ** 3))
+    assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+    assert A.nnz == len(col) and rowptr[-1] == len(col)
+    assert np.all(np.diff(rowptr) >= (p + 1) ** 3)
