@@ -9,11 +9,21 @@
 
 namespace fdg {
 
+// Device pointers typed in the global address space.  Entry pointers come from tables or
+// pointer arithmetic and are otherwise generic, for which the compiler emits flat memory
+// instructions; a flat access also counts against the LDS wait counter, so every LDS wait
+// in a kernel would also wait for its outstanding memory loads.  Kernels take entries as
+// gat() pointers and keep them in this type.
+#define FDG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+using gptr = FDG_GLOBAL T *;
+
 struct CBatch {
   const double *base = nullptr;
   int64_t stride = 0;
   const double *const *ptrs = nullptr;
   __host__ __device__ inline const double *at(int64_t e) const { return ptrs ? ptrs[e] : base + e * stride; }
+  __device__ inline gptr<const double> gat(int64_t e) const { return (gptr<const double>)at(e); }
 };
 
 struct MBatch {
@@ -21,6 +31,7 @@ struct MBatch {
   int64_t stride = 0;
   double *const *ptrs = nullptr;
   __host__ __device__ inline double *at(int64_t e) const { return ptrs ? ptrs[e] : base + e * stride; }
+  __device__ inline gptr<double> gat(int64_t e) const { return (gptr<double>)at(e); }
   __host__ __device__ inline bool valid() const { return base != nullptr || ptrs != nullptr; }
 };
 

@@ -41,9 +41,9 @@ __device__ inline dbl4 mfma(double a, double b, dbl4 c) {
 
 // Four consecutive doubles p[0..3], zero where the index j + t >= jmax or !ok.
 template <bool VEC>
-__device__ inline void load4(const double *p, int j, int jmax, bool ok, double (&v)[4]) {
+__device__ inline void load4(gptr<const double> p, int j, int jmax, bool ok, double (&v)[4]) {
   if (VEC && ok && j + 3 < jmax) {
-    const dbl4 x = *reinterpret_cast<const dbl4 *>(p);
+    const dbl4 x = *(gptr<const dbl4>)p;
     v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
   } else {
 #pragma unroll
@@ -155,8 +155,8 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
   if (s >= nslab) return;
   const int64_t n2 = (int64_t)n * n;
   const int64_t ent = s / spe, loc = s - ent * spe;  // batch entry and slab inside it
-  const double *__restrict__ Xs = X.at(ent) + loc * n2;
-  double *__restrict__ Ys = Y.at(ent) + loc * n2;
+  FDG_GLOBAL const double *__restrict__ Xs = X.gat(ent) + loc * n2;
+  FDG_GLOBAL double *__restrict__ Ys = Y.gat(ent) + loc * n2;
   const int c0 = cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
@@ -271,8 +271,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   const int64_t bidx = blockIdx.x / ncb;
   const int cb = (int)(blockIdx.x % ncb);
   const int64_t n2 = (int64_t)n * n;
-  const double *__restrict__ Xb = X.at(bidx);
-  double *__restrict__ Yb = Y.at(bidx);
+  FDG_GLOBAL const double *__restrict__ Xb = X.gat(bidx);
+  FDG_GLOBAL double *__restrict__ Yb = Y.gat(bidx);
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;

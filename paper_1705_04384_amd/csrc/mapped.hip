@@ -58,8 +58,8 @@ __global__ __launch_bounds__(512) void k_mapped_wpp(CBatch x, MBatch y, int n, i
   const int i2a = ty * T2;
   const int e3 = s3 + C3 < n ? s3 + C3 : n;
   const int64_t n2 = (int64_t)n * n;
-  const double *__restrict__ xb = x.at(ent);
-  double *__restrict__ yb = y.at(ent);
+  gptr<const double> __restrict__ xb = x.gat(ent);
+  gptr<double> __restrict__ yb = y.gat(ent);
   const int w1 = op.w[0], w2 = op.w[1], w3 = op.w[2];
   const bool act1 = i1 < n;
   const int i1c = act1 ? i1 : n - 1;
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(512) void k_mapped_wpp(CBatch x, MBatch y, int n, i
   if (threadIdx.x < C3) lo3s[threadIdx.x] = vlo;
   __syncthreads();
   for (int pl = wave; pl < NPL; pl += NWV) {
-    const double *xp = xb + (int64_t)(P0 + pl) * n2 + (int64_t)R0 * n + L0;
+    gptr<const double> xp = xb + (int64_t)(P0 + pl) * n2 + (int64_t)R0 * n + L0;
     double xr[RMAX], xh[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {

@@ -254,9 +254,9 @@ __global__ __launch_bounds__(kBlock) void k_kron3_planes(CBatch x, MBatch ao, MB
   const int64_t n2 = (int64_t)n * n;
   const int64_t ent = pl / n;
   const int64_t j3 = pl - ent * n;
-  const double *__restrict__ xp = x.at(ent) + j3 * n2;
-  double *__restrict__ ap = ao.at(ent) + j3 * n2;
-  double *__restrict__ cp = co.at(ent) + j3 * n2;
+  gptr<const double> __restrict__ xp = x.gat(ent) + j3 * n2;
+  gptr<double> __restrict__ ap = ao.gat(ent) + j3 * n2;
+  gptr<double> __restrict__ cp = co.gat(ent) + j3 * n2;
   const int w1 = bd.w[0], w2 = bd.w[1];
   const bool act1 = i1 < n;
   const int i1c = act1 ? i1 : n - 1;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_kron3_planes(CBatch x, MBatch ao, MB
 #pragma unroll
   for (int u = 0; u < kRowsPerWave; ++u) {
     const int r = wave + 4 * u;
-    const double *xr = xp + (int64_t)(R0 + (r < NR ? r : 0)) * n + lo1;
+    gptr<const double> xr = xp + (int64_t)(R0 + (r < NR ? r : 0)) * n + lo1;
 #pragma unroll
     for (int t1 = 0; t1 < WMAX; ++t1) xv[u][t1] = (r < NR && t1 < w1) ? xr[t1] : 0.0;
   }
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_kron3_mode3(CBatch ai, CBatch ci, MB
   const int w3 = bd.w[2];
   const int P0 = bd.lo[2][s];
   const int np = bd.lo[2][e - 1] + w3 - P0;  // planes needed, <= kRowsPerThread - 1 + WMAX
-  const double *ab = ai.at(b) + col, *cb = ci.at(b) + col;
+  gptr<const double> ab = ai.gat(b) + col, cb = ci.gat(b) + col;
   constexpr int NPMAX = kRowsPerThread - 1 + WMAX;
   double av[NPMAX], cv[NPMAX];
 #pragma unroll
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_kron3_mode3(CBatch ai, CBatch ci, MB
         acc = fma(m3[t], cv[q], acc);
       }
     }
-    y.at(b)[(int64_t)i3 * n2 + col] = acc;
+    y.gat(b)[(int64_t)i3 * n2 + col] = acc;
   }
 }
 
@@ -370,8 +370,8 @@ __global__ __launch_bounds__(kBlock) void k_kron2_window(CBatch x, MBatch y, int
   const int s = blockIdx.y * kChunk;
   const int e = s + kChunk < n ? s + kChunk : n;
   const int64_t b = blockIdx.z;
-  const double *__restrict__ xb = x.at(b);
-  double *__restrict__ yb = y.at(b);
+  gptr<const double> __restrict__ xb = x.gat(b);
+  gptr<double> __restrict__ yb = y.gat(b);
   const int w1 = bd.w[0], w2 = bd.w[1];
   double m1[WMAX], k1[WMAX];
 #pragma unroll
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_kron2_window(CBatch x, MBatch y, int
   auto row = [&](int j2, double &sm, double &sk) {
     sm = 0.0;
     sk = 0.0;
-    const double *xr = xb + (int64_t)j2 * n + lo1;
+    gptr<const double> xr = xb + (int64_t)j2 * n + lo1;
 #pragma unroll
     for (int t1 = 0; t1 < WMAX; ++t1)
       if (t1 < w1) {
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_ell_f64(CBatch x, MBatch y, int64_t 
   const int64_t row = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) / S + (lane % R);
   const bool ok = row < nrows;
   const int64_t b = blockIdx.y;
-  const double *__restrict__ xb = x.at(b);
+  gptr<const double> __restrict__ xb = x.gat(b);
   double acc = 0.0;
   if (ok)
     for (int t = g; t < width; t += S) {
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_ell_f64(CBatch x, MBatch y, int64_t 
     }
 #pragma unroll
   for (int m = R; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
-  if (ok && g == 0) y.at(b)[row] = acc;
+  if (ok && g == 0) y.gat(b)[row] = acc;
 }
 
 // One-pass 3D form, one wave per plane.  A workgroup of 8 waves owns a tile of 64
@@ -494,8 +494,8 @@ __global__ __launch_bounds__(512) void k_kron3_wpp(CBatch x, MBatch y, int n, in
   const int i2a = ty * T2;
   const int e3 = s3 + C3 < n ? s3 + C3 : n;
   const int64_t n2 = (int64_t)n * n;
-  const double *__restrict__ xb = x.at(ent);
-  double *__restrict__ yb = y.at(ent);
+  gptr<const double> __restrict__ xb = x.gat(ent);
+  gptr<double> __restrict__ yb = y.gat(ent);
   const int w1 = bd.w[0], w2 = bd.w[1], w3 = bd.w[2];
   const bool act1 = i1 < n;
   const int i1c = act1 ? i1 : n - 1;
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(512) void k_kron3_wpp(CBatch x, MBatch y, int n, in
   if (threadIdx.x < C3) lo3s[threadIdx.x] = vlo3;
   __syncthreads();
   for (int pl = wave; pl < NPL; pl += NWV) {
-    const double *xp = xb + (int64_t)(P0 + pl) * n2 + (int64_t)R0 * n + L0;
+    gptr<const double> xp = xb + (int64_t)(P0 + pl) * n2 + (int64_t)R0 * n + L0;
     double xr[RMAX], xh[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(512) void k_kron3_wpp(CBatch x, MBatch y, int n, in
   __syncthreads();
   double rr = 0.0;  // RES: this thread's part of |b - A x|^2
   if (act1) {
-    const double *rb = RES ? rhs.at(ent) : nullptr;
+    gptr<const double> rb = RES ? rhs.gat(ent) : nullptr;
     for (int idx = wave; idx < C3 * T2; idx += NWV) {
       const int q = idx / T2, u = idx - q * T2;
       const int i2 = i2a + u;
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(512) void k_kron3_wpp(CBatch x, MBatch y, int n, in
     if (threadIdx.x == 0) {
       double sum = red[0];
       for (int k = 1; k < NWV; ++k) sum += red[k];
-      part.at(ent)[t - ent * (int64_t)ntx * nty * nchunk] = sum;
+      part.gat(ent)[t - ent * (int64_t)ntx * nty * nchunk] = sum;
     }
   }
 }
@@ -756,23 +756,23 @@ __global__ __launch_bounds__(kBlock) void k_ell_tensor_f64(CBatch x, MBatch y, i
   const int64_t row = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) / S + (lane % R);
   const bool ok = row < nrows;
   const int64_t b = blockIdx.y;
-  const double *__restrict__ xb = x.at(b);
+  gptr<const double> __restrict__ xb = x.gat(b);
   const int64_t n2 = (int64_t)n * n;
   double acc = 0.0;
   if (ok) {
     const int i1 = (int)(row % n), i2 = (int)((row / n) % n), i3 = (int)(row / n2);
-    const double *__restrict__ x0 = xb + lo[i1] + (int64_t)n * lo[n + i2] + n2 * lo[2 * n + i3];
+    gptr<const double> __restrict__ x0 = xb + lo[i1] + (int64_t)n * lo[n + i2] + n2 * lo[2 * n + i3];
     const int nq = w2 * w3;
     for (int q = g; q < nq; q += S) {
       const int t3 = q / w2, t2 = q - t3 * w2;
-      const double *__restrict__ xr = x0 + (int64_t)n * t2 + n2 * t3;
+      gptr<const double> __restrict__ xr = x0 + (int64_t)n * t2 + n2 * t3;
       const double *__restrict__ vr = val + (int64_t)q * w1 * nrows + row;
       for (int t1 = 0; t1 < w1; ++t1) acc = fma(vr[(int64_t)t1 * nrows], xr[t1], acc);
     }
   }
 #pragma unroll
   for (int m = R; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
-  if (ok && g == 0) y.at(b)[row] = acc;
+  if (ok && g == 0) y.gat(b)[row] = acc;
 }
 
 // Lanes per row: doubled (up to 4) while the launch has fewer than ~400K lanes and each

@@ -36,7 +36,8 @@ __device__ inline void chunk_of(int64_t N, int G, int g, int64_t &beg, int64_t &
 // Fixed-order sum of the G <= 256 partials of component q (partial g of component q at
 // P[g * ldp + q]), valid in every lane: lane l adds g = l, l + 64, l + 128, l + 192 in
 // order, then an xor butterfly.
-__device__ inline double sum_partials(const double *P, int G, int ldp, int q) {
+template <typename Ptr>
+__device__ inline double sum_partials(Ptr P, int G, int ldp, int q) {
   const int lane = threadIdx.x & 63;
   double v[kMaxG / 64];
 #pragma unroll

@@ -121,6 +121,30 @@ def test_solve_deformed_matches_oracle(p, n, restart):
     ctx.close()
 
 
+@pytest.mark.parametrize("k", [6, 20, 44])
+def test_fixed_iterations_span_every_orthogonalization_form(k):
+    # one restart cycle of 44 steps at N = 20^3 (8 reduction chunks, ragged sub-chunks):
+    # the Gram-Schmidt update-and-dots step takes nv = j + 1 basis vectors, so k = 6 uses
+    # the register form only, 20 adds the LDS-staged form (9..32) and 44 the two-read form
+    fdg = _fdg()
+    torch = torch_cuda()
+    p, n, restart = 3, 20, 44
+    ctx = fdg.deformed_problem(p, n, 0.1)
+    b = inputs.rhs_uniform(inputs.SEED_DEFORMED_96, n ** 3)
+    A = colloc.deformed_operator(p, n, 0.1)
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    U, V, lam = fd.factor_pencil(K, M)
+    prec = lambda v: fd.fd_apply([U] * 3, [V] * 3, [lam] * 3, v)
+    xo, io = fgmres.fgmres(lambda v: A @ v, prec, b, restart=restart, iters=k)
+    x = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.solve(to_dev(b), x, rtol=1e-8, restart=restart, maxit=k, flags=fdg.SOLVE_FIXED_ITERS)
+    assert info["iterations"] == k and info["restarts"] == io["restarts"]
+    assert relerr(x.cpu().numpy(), xo) <= 1e-8
+    if k <= 20:  # above, both estimates sit at the rounding floor
+        assert abs(info["rel_res_est"] - io["history"][-1]) <= 1e-6 * io["history"][-1]
+    ctx.close()
+
+
 def test_solve_use_x0_and_zero_rhs():
     fdg = _fdg()
     torch = torch_cuda()
