@@ -872,17 +872,40 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   run.init(c, rb, restart, b, x, rtol, maxit, flags);
   SolveRun *rp = &run;
   const Exec ex{c->stream, true};
+  bool stream_idle = true;
   while (!run.finished()) {
+    // the previous phase's last kernel may still be retiring (its results were read);
+    // the slots armed here are ones it has already written, so it cannot overwrite them
+    run.arm();
     if ((st = enqueue_phase(ex, &rp, 1, nullptr)) != FDG_OK) return st;
-    // wait for the phase by polling its event: the host sees the results as soon as
-    // the last kernel ends, without a blocking wake-up
     HIPCHK(hipEventRecord(c->phase_ev, c->stream));
+    stream_idle = false;
+    // the host needs the phase's scalars, not the end of its last kernel: poll the armed
+    // host-mapped slots, and the phase event every few rounds (no blocking wake-up)
+    hipError_t e = hipErrorNotReady;
+    for (unsigned k = 1; !run.ready(); ++k) {
+      if ((k & 63) == 0 && (e = hipEventQuery(c->phase_ev)) != hipErrorNotReady) break;
+    }
+    if (e != hipErrorNotReady) {  // the stream finished first (or failed)
+      (void)hipGetLastError();
+      HIPCHK(e);
+      stream_idle = true;
+    }
+    if (!run.ready()) {  // a phase without armed slots: its results need the whole stream
+      while ((e = hipEventQuery(c->phase_ev)) == hipErrorNotReady) {
+      }
+      (void)hipGetLastError();
+      HIPCHK(e);
+      stream_idle = true;
+    }
+    run.consume();
+  }
+  if (!stream_idle) {  // x and the buffers belong to the caller again only after the stream
     hipError_t e;
     while ((e = hipEventQuery(c->phase_ev)) == hipErrorNotReady) {
     }
     (void)hipGetLastError();
     HIPCHK(e);
-    run.consume();
   }
   if (info) *info = run.info();
   return run.status();

@@ -27,6 +27,12 @@ namespace {
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 constexpr int kBlock = 256;  // threads of the streaming kernels
+#ifndef FDG_DOTS_UNROLL
+#define FDG_DOTS_UNROLL 2
+#endif
+#ifndef FDG_UPD_UNROLL
+#define FDG_UPD_UNROLL 2
+#endif
 constexpr int kQB = 8;       // basis vectors per register batch
 
 // hs[q] = sum of the partials of component q, q < ncomp (all waves of the block help).
@@ -64,7 +70,7 @@ __device__ inline void chunk_dots(gptr<const double> Vb, int64_t ldv, int nv, in
 #pragma unroll
   for (int t = 0; t < kQB; ++t) acc[t] = 0.0;
   if (VEC) {
-#pragma unroll 2
+#pragma unroll FDG_DOTS_UNROLL
     for (int64_t i = beg + 2 * threadIdx.x; i < end; i += 2 * kRed) {
       const dbl2 wi = *(gptr<const dbl2>)(wb + i);
 #pragma unroll
@@ -91,7 +97,7 @@ __device__ inline double chunk_update(gptr<const double> Vb, int64_t ldv, int nv
                                       int64_t beg, int64_t end) {
   double nrm = 0.0;
   if (VEC) {
-#pragma unroll 2
+#pragma unroll FDG_UPD_UNROLL
     for (int64_t i = beg + 2 * threadIdx.x; i < end; i += 2 * kRed) {
       dbl2 wi = *(gptr<const dbl2>)(wb + i);
       for (int q = 0; q < nv; ++q) {
@@ -149,6 +155,9 @@ __device__ inline double block_sum(double v, double *red) {
 #define FDG_STAGE_NV 32
 #endif
 constexpr int kRegNV = FDG_REG_NV;
+#ifndef FDG_REG2_UNROLL
+#define FDG_REG2_UNROLL 4
+#endif
 constexpr int kStageNV = FDG_STAGE_NV;
 constexpr int kStage = 12288;   // doubles of staged basis values (96 KB)
 constexpr int kStageBatch = 8;  // basis loads in flight per thread in the staged form
@@ -160,32 +169,33 @@ struct PassLds {
   double accq[kStageNV > 0 ? kStageNV : 1];
 };
 
+template <int NVM, int UNR>
 __device__ inline void reg_update_dots(gptr<const double> __restrict__ Vb, int64_t ldv, int nv, const double *hs,
                                        gptr<double> __restrict__ wb, int64_t beg, int64_t end, gptr<double> Pg,
                                        PassLds &L) {
-  double acc[kRegNV > 0 ? kRegNV : 1];
+  double acc[NVM];
 #pragma unroll
-  for (int t = 0; t < kRegNV; ++t) acc[t] = 0.0;
-#pragma unroll 1
+  for (int t = 0; t < NVM; ++t) acc[t] = 0.0;
+#pragma unroll UNR
   for (int64_t i = beg + threadIdx.x; i < end; i += kRed) {
     gptr<const double> vcol = Vb + i;
-    double v[kRegNV > 0 ? kRegNV : 1];
+    double v[NVM];
 #pragma unroll
-    for (int t = 0; t < kRegNV; ++t) v[t] = t < nv ? vcol[(int64_t)t * ldv] : 0.0;
+    for (int t = 0; t < NVM; ++t) v[t] = t < nv ? vcol[(int64_t)t * ldv] : 0.0;
     double wi = wb[i];
 #pragma unroll
-    for (int t = 0; t < kRegNV; ++t)
+    for (int t = 0; t < NVM; ++t)
       if (t < nv) wi = fma(-v[t], hs[t], wi);
     wb[i] = wi;
 #pragma unroll
-    for (int t = 0; t < kRegNV; ++t) acc[t] = fma(v[t], wi, acc[t]);
+    for (int t = 0; t < NVM; ++t) acc[t] = fma(v[t], wi, acc[t]);
   }
 #pragma unroll
-  for (int q0 = 0; q0 < kRegNV; q0 += kQB) {
+  for (int q0 = 0; q0 < NVM; q0 += kQB) {
     if (q0 >= nv) break;
     double part[kQB];
 #pragma unroll
-    for (int t = 0; t < kQB; ++t) part[t] = q0 + t < kRegNV ? acc[q0 + t] : 0.0;
+    for (int t = 0; t < kQB; ++t) part[t] = q0 + t < NVM ? acc[q0 + t] : 0.0;
     store_partials(part, L.red, Pg, q0, nv);
   }
 }
@@ -267,8 +277,12 @@ __global__ __launch_bounds__(kRed) void k_update_dots(CBatch V, int64_t ldv, IBa
   gptr<const double> __restrict__ Vb = V.gat(b);
   gptr<double> __restrict__ wb = w.gat(b);
   gptr<double> Pg = Pout.gat(b) + (int64_t)g * ldp;
+  if (nv <= 2) {
+    reg_update_dots<2, FDG_REG2_UNROLL>(Vb, ldv, nv, hs, wb, beg, end, Pg, L);
+    return;
+  }
   if (nv <= kRegNV) {
-    reg_update_dots(Vb, ldv, nv, hs, wb, beg, end, Pg, L);
+    reg_update_dots<kRegNV, 1>(Vb, ldv, nv, hs, wb, beg, end, Pg, L);
     return;
   }
   if (nv <= kStageNV) {

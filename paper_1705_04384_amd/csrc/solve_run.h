@@ -78,6 +78,14 @@ class SolveRun {
   // The phase in flight has completed (stream or event synchronised): read its results,
   // advance the least-squares state and set the next phase.
   void consume();
+  // Host-mapped slots the phase about to be enqueued writes and consume() reads (the
+  // Hessenberg column, ||b||, the per-block norm partials): arm() fills them with a
+  // signalling-NaN pattern that no kernel stores (arithmetic yields quiet NaNs); ready()
+  // is true once every armed slot holds a kernel's value, which a host can poll instead
+  // of waiting for the end of the last kernel.  A phase without such slots arms nothing
+  // and is never ready (wait for the stream instead).
+  void arm();
+  bool ready() const;
   int status() const { return status_; }
   const fdg_info &info() const { return info_; }
   const Coeffs &coeffs() const { return y_; }
@@ -97,6 +105,8 @@ class SolveRun {
   void finish(bool converged);
   void zero_then_finish(bool converged);
 
+  int armed_hcol_ = 0, armed_parts_ = 0;  // armed slots: hh[0, hcol), hh[m+4, m+4+parts)
+  bool armed_bnorm_ = false;              // and hh[m+2]
   Phase ph_;
   double rtol_ = 0.0, bnorm_ = -1.0, target_ = 0.0, last_est_ = 1.0, rbeta_ = 0.0;
   int limit_ = 0, total_ = 0, restarts_ = 0, status_ = FDG_OK;

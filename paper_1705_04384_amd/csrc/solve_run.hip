@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "solve_run.h"
@@ -116,6 +117,38 @@ double SolveRun::host_norm(int count) const {
   double sum = 0.0;
   for (int g = 0; g < count; ++g) sum += buf.hh[m + 4 + g];
   return std::sqrt(sum);
+}
+
+namespace {
+constexpr uint64_t kUnwritten = 0x7FF4DEADBEEF0001ull;  // signalling NaN: never a kernel result
+}
+
+void SolveRun::arm() {
+  const unsigned st = ph_.steps;
+  armed_hcol_ = armed_parts_ = 0;
+  armed_bnorm_ = false;
+  if (st == 0 || (st & kStepZeroX)) return;
+  if (st & (kStepBNorm | kStepBScale)) armed_bnorm_ = true;
+  if (st & kStepIter) {
+    armed_hcol_ = ph_.j + 1;
+    armed_parts_ = G;
+  } else if (st & kStepRes) {
+    armed_parts_ = res_parts > 0 ? res_parts : G;
+  }
+  volatile uint64_t *w = reinterpret_cast<volatile uint64_t *>(buf.hh);
+  for (int q = 0; q < armed_hcol_; ++q) w[q] = kUnwritten;
+  if (armed_bnorm_) w[m + 2] = kUnwritten;
+  for (int g = 0; g < armed_parts_; ++g) w[m + 4 + g] = kUnwritten;
+}
+
+bool SolveRun::ready() const {
+  if (armed_hcol_ == 0 && armed_parts_ == 0 && !armed_bnorm_) return false;
+  const volatile uint64_t *w = reinterpret_cast<const volatile uint64_t *>(buf.hh);
+  for (int g = armed_parts_ - 1; g >= 0; --g)
+    if (w[m + 4 + g] == kUnwritten) return false;
+  for (int q = 0; q < armed_hcol_; ++q)
+    if (w[q] == kUnwritten) return false;
+  return !armed_bnorm_ || w[m + 2] != kUnwritten;
 }
 
 void SolveRun::zero_then_finish(bool converged) {
