@@ -21,6 +21,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "context.h"
@@ -251,13 +252,47 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
   const Exec ex{s, true};
   double *hd = B.hh_dev;
   volatile double *hh = B.hh;
-  auto wait = [&]() -> int {
-    HIPCHK(hipEventRecord(c->phase_ev, s));
+  // The host-mapped slots a phase writes are armed with a signalling-NaN pattern no
+  // kernel stores before its launches; the host continues once they all hold values
+  // (not at the end of the last kernel), polling the phase event as a fallback: a
+  // breakdown in the half step leaves the |s| partials unwritten.
+  constexpr uint64_t kUnwritten = 0x7FF4DEADBEEF0001ull;
+  volatile uint64_t *hw = reinterpret_cast<volatile uint64_t *>(hh);
+  int armed[2][2] = {{0, 0}, {0, 0}};
+  bool stream_idle = true;
+  auto arm = [&](int a0, int n0, int a1, int n1) {
+    armed[0][0] = a0, armed[0][1] = n0, armed[1][0] = a1, armed[1][1] = n1;
+    for (int k = 0; k < 2; ++k)
+      for (int g = 0; g < armed[k][1]; ++g) hw[armed[k][0] + g] = kUnwritten;
+  };
+  auto ready = [&]() {
+    for (int k = 0; k < 2; ++k)
+      for (int g = armed[k][1] - 1; g >= 0; --g)
+        if (hw[armed[k][0] + g] == kUnwritten) return false;
+    return armed[0][1] + armed[1][1] > 0;
+  };
+  auto drain = [&]() -> int {
     hipError_t e;
     while ((e = hipEventQuery(c->phase_ev)) == hipErrorNotReady) {
     }
     (void)hipGetLastError();
     HIPCHK(e);
+    stream_idle = true;
+    return FDG_OK;
+  };
+  auto wait = [&]() -> int {
+    HIPCHK(hipEventRecord(c->phase_ev, s));
+    stream_idle = false;
+    hipError_t e = hipErrorNotReady;
+    for (unsigned k = 1; !ready(); ++k) {
+      if ((k & 63) == 0 && (e = hipEventQuery(c->phase_ev)) != hipErrorNotReady) break;
+    }
+    if (e != hipErrorNotReady) {
+      (void)hipGetLastError();
+      HIPCHK(e);
+      stream_idle = true;
+    }
+    if (!ready() && !stream_idle) return drain();
     return FDG_OK;
   };
   auto apply = [&](const double *in, double *out) {
@@ -270,6 +305,7 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
   // true residual |b - A x| (into sh, using t), partials to hh[3G ..)
   auto true_res = [&](double &nrm) -> int {
     int e;
+    arm(3 * G, G, 0, 0);
     if ((e = matvec(x, B.t)) != FDG_OK) return e;
     {
       TimedLaunch tl(c, 2, s, true);
@@ -283,6 +319,7 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
 
   fdg_info inf{};
   const bool use_x0 = flags & FDG_SOLVE_USE_X0, fixed = flags & FDG_SOLVE_FIXED_ITERS;
+  arm(G, G, 2 * G, G);
   if (use_x0 && (st = matvec(x, B.t)) != FDG_OK) return st;
   {
     TimedLaunch tl(c, 2, s, true);
@@ -305,6 +342,7 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
   }
   for (int i = 1; !conv && !brk && i <= maxit; ++i) {
     const int a = i & 1, o = a ^ 1;
+    arm(0, G, 4 * G, 2);
     {
       TimedLaunch tl(c, 2, s, true);
       hipLaunchKernelGGL(k_bi_dir, dim3(cdiv(N, kStream)), dim3(kStream), 0, s, B.r, B.p, B.v, N, i == 1 ? 1 : 0, G,
@@ -335,6 +373,7 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
         break;
       }
     }
+    arm(G, G, 4 * G + 2, 1);
     if ((st = apply(B.s, B.sh)) != FDG_OK) return st;
     if ((st = matvec(B.sh, B.t)) != FDG_OK) return st;
     {
@@ -361,6 +400,10 @@ extern "C" int fdg_bicgstab(fdg_ctx *c, const double *b, double *x, double rtol,
   }
   double tr = 0.0;
   if (bnorm > 0.0 && (st = true_res(tr)) != FDG_OK) return st;
+  if (!stream_idle || (bnorm == 0.0 && use_x0)) {  // x is the caller's once the stream is done
+    HIPCHK(hipEventRecord(c->phase_ev, s));
+    if ((st = drain()) != FDG_OK) return st;
+  }
   inf.iterations = full;
   inf.half_steps = half;
   inf.restarts = 0;
