@@ -63,15 +63,15 @@ __device__ inline void store_partials(double (&acc)[kQB], double (*red)[kQB], gp
   __syncthreads();
 }
 
-// acc[t] += V_{q0+t} . w over the block's chunk.
+// acc[t] = V_{q0+t} . w over the block's chunk, thread tid of nthr taking a strided share.
 template <bool VEC>
 __device__ inline void chunk_dots(gptr<const double> Vb, int64_t ldv, int nv, int q0, gptr<const double> wb, int64_t beg,
-                                  int64_t end, double (&acc)[kQB]) {
+                                  int64_t end, double (&acc)[kQB], int tid = threadIdx.x, int nthr = kRed) {
 #pragma unroll
   for (int t = 0; t < kQB; ++t) acc[t] = 0.0;
   if (VEC) {
 #pragma unroll FDG_DOTS_UNROLL
-    for (int64_t i = beg + 2 * threadIdx.x; i < end; i += 2 * kRed) {
+    for (int64_t i = beg + 2 * tid; i < end; i += 2 * nthr) {
       const dbl2 wi = *(gptr<const dbl2>)(wb + i);
 #pragma unroll
       for (int t = 0; t < kQB; ++t)
@@ -82,7 +82,7 @@ __device__ inline void chunk_dots(gptr<const double> Vb, int64_t ldv, int nv, in
         }
     }
   } else {
-    for (int64_t i = beg + threadIdx.x; i < end; i += kRed) {
+    for (int64_t i = beg + tid; i < end; i += nthr) {
       const double wi = wb[i];
 #pragma unroll
       for (int t = 0; t < kQB; ++t)
@@ -238,7 +238,14 @@ __device__ inline void staged_update_dots(gptr<const double> __restrict__ Vb, in
   if (tid < nv) Pg[tid] = L.accq[tid];
 }
 
-// P = partial dots V^T w.
+// P = partial dots V^T w.  The nb = ceil(nv / kQB) batches of kQB components are spread
+// over ng = 1, 2 or 4 groups of waves that stream the chunk side by side (one batch per
+// group per round), so the basis is read in ceil(nb / ng) passes instead of nb.  Group
+// gg sums its batch thread-strided, by butterflies, then its waves in index order; ng
+// depends on nv only (ng = 1 is the whole block, one batch after another).
+#ifndef FDG_DOTS_GROUPS
+#define FDG_DOTS_GROUPS 4
+#endif
 template <bool VEC>
 __global__ __launch_bounds__(kRed) void k_dots(CBatch V, int64_t ldv, IBatch nvs, CBatch w, int64_t N, int G,
                                                int ldp, MBatch P) {
@@ -251,10 +258,37 @@ __global__ __launch_bounds__(kRed) void k_dots(CBatch V, int64_t ldv, IBatch nvs
   gptr<const double> __restrict__ wb = w.gat(b);
   gptr<const double> __restrict__ Vb = V.gat(b);
   gptr<double> Pg = P.gat(b) + (int64_t)g * ldp;
-  for (int q0 = 0; q0 < nv; q0 += kQB) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb = (nv + kQB - 1) / kQB;
+  const int ng = nb >= 4 && FDG_DOTS_GROUPS >= 4 ? 4 : (nb >= 2 && FDG_DOTS_GROUPS >= 2 ? 2 : 1);
+  const int gw = kRedWaves / ng, grp = wave / gw;
+  const int gtid = (int)threadIdx.x - grp * gw * 64;
+  const int rounds = (nb + ng - 1) / ng;
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int bq = rd * ng + grp;  // this group's batch (none when bq >= nb)
     double acc[kQB];
-    chunk_dots<VEC>(Vb, ldv, nv, q0, wb, beg, end, acc);
-    store_partials(acc, red, Pg, q0, nv);
+    if (bq < nb) {
+      chunk_dots<VEC>(Vb, ldv, nv, bq * kQB, wb, beg, end, acc, gtid, gw * 64);
+    } else {
+#pragma unroll
+      for (int t = 0; t < kQB; ++t) acc[t] = 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kQB; ++t) {
+      const double v = wave_sum(acc[t]);
+      if (lane == 0) red[wave][t] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ng * kQB) {
+      const int gg = threadIdx.x / kQB, t = threadIdx.x - gg * kQB;
+      const int q = (rd * ng + gg) * kQB + t;
+      if (q < nv) {
+        double sum = red[gg * gw][t];
+        for (int k = 1; k < gw; ++k) sum += red[gg * gw + k][t];
+        Pg[q] = sum;
+      }
+    }
+    __syncthreads();
   }
 }
 
