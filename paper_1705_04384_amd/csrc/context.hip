@@ -220,6 +220,13 @@ int apply_entries(fdg_ctx *c, const Exec &ex, CBatch in, MBatch out, int64_t nen
                         c->lam32, c->ldw);
     return hip_check(hipGetLastError(), "apply_prec launch");
   }
+  if (c->prec == FDG_PREC_BF16 && fd_fused_supported(n)) {  // fused BF16 passes
+    if (gathered) return set_error(FDG_EINVAL, "apply: gathered batches need the FP64 preconditioner");
+    TimedLaunch tl(c, 0, ex.stream, ex.timed);
+    launch_fd_apply_bf16(ex.stream, c->d, n, nent, in.base, out.base, (float *)t32a, (float *)t32b,
+                         (const void *const *)c->Wv16, (const void *const *)c->Wu16, c->lam32, c->ldw);
+    return hip_check(hipGetLastError(), "apply_prec launch");
+  }
   if (c->prec != FDG_PREC_FP64) {
     if (gathered) return set_error(FDG_EINVAL, "apply: gathered batches need the FP64 preconditioner");
     TimedLaunch tl(c, 0, ex.stream, ex.timed);

@@ -33,4 +33,10 @@ void launch_fibre_f64(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const
 void launch_fd_apply_f32(hipStream_t s, int d, int n, int64_t batch, const double *b, double *out, float *t1,
                          float *t2, const float *const *Wv, const float *const *Wu, const float *const *lam, int ldw);
 
+// The same with BF16 products (inputs rounded to BF16 on entry to each MFMA, FP32
+// accumulation and FP32 intermediates): Wv, Wu are the BF16 factor copies (ldw x ldw,
+// zero-padded), lam the FP32 eigenvalues (padded with 1).  n <= 256.
+void launch_fd_apply_bf16(hipStream_t s, int d, int n, int64_t batch, const double *b, double *out, float *t1,
+                          float *t2, const void *const *Wv, const void *const *Wu, const float *const *lam, int ldw);
+
 }  // namespace fdg

@@ -1,0 +1,383 @@
+// Fused BF16 fast-diagonalization solve (eq. 4.9 / 4.7): the three passes of the FP64
+// solve (slab: modes 1 and 2; fibre: mode 3, divide, mode 3; slab: modes 1 and 2) on
+// v_mfma_f32_16x16x32_bf16.  Every mode-product input, factor and tensor, is rounded to
+// BF16 (round to nearest even) where it enters an MFMA; products accumulate in FP32; the
+// intermediates between passes are FP32, and so are the diagonal solve and the scaling.
+// The first pass reads the FP64 Krylov vector and the last one writes FP64.
+//
+// v_mfma_f32_16x16x32_bf16 lane layout (li = lane % 16, lg = lane / 16), per 32-wide
+// block of the contraction index starting at j0:
+//   A[m = li][k = j0 + 8 lg + t], B[k = j0 + 8 lg + t][n = li], t < 8 (eight BF16 per lane),
+//   D[m = 4 lg + r][n = li] in register r.
+// Intermediates that feed the next MFMA inside a pass are kept in LDS already rounded to
+// BF16, which is the rounding the next product applies on load.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "fd_apply.h"
+
+namespace fdg {
+
+namespace {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kPadB = 8;  // LDS row padding (BF16 elements: rows stay 16-byte aligned)
+
+// Round to nearest even; infinities and NaNs keep their class.
+__device__ inline __bf16 to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+  const uint16_t h = (uint16_t)(u >> 16);
+  __bf16 r;
+  __builtin_memcpy(&r, &h, 2);
+  return r;
+}
+
+__device__ inline flt4 mfma16(const bf16x8 &a, const bf16x8 &b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Eight consecutive elements p[0..7] rounded to BF16, zero where j + t >= jmax or !ok.
+template <typename T>
+__device__ inline bf16x8 load8(const T *p, int j, int jmax, bool ok) {
+  bf16x8 v;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) v[t] = to_bf16((ok && j + t < jmax) ? (float)p[t] : 0.0f);
+  return v;
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// The same with two 4-wide loads where the whole group is in range (VEC: p is aligned to
+// 4 elements, i.e. n % 4 == 0 and 32-byte aligned rows).
+template <bool VEC, typename T>
+__device__ inline bf16x8 load8v(const T *p, int j, int jmax, bool ok) {
+  if (VEC && ok && j + 7 < jmax) {
+    bf16x8 v;
+    if constexpr (sizeof(T) == 8) {
+      const dbl4 x0 = *reinterpret_cast<const dbl4 *>(p), x1 = *reinterpret_cast<const dbl4 *>(p + 4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        v[t] = to_bf16((float)x0[t]);
+        v[4 + t] = to_bf16((float)x1[t]);
+      }
+    } else {
+      const flt4 x0 = *reinterpret_cast<const flt4 *>(p), x1 = *reinterpret_cast<const flt4 *>(p + 4);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        v[t] = to_bf16(x0[t]);
+        v[4 + t] = to_bf16(x1[t]);
+      }
+    }
+    return v;
+  }
+  return load8(p, j, jmax, ok);
+}
+
+// Eight consecutive BF16 (16-byte aligned, always in bounds).
+__device__ inline bf16x8 load8_bf(const __bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+
+template <int MT, int NT>
+struct Frag16 {
+  bf16x8 a[MT];
+  bf16x8 b[NT];
+};
+
+template <int MT, int NT>
+__device__ inline void mma_block16(const Frag16<MT, NT> &f, flt4 (&acc)[MT][NT]) {
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = mfma16(f.a[a], f.b[b], acc[a][b]);
+}
+
+// acc = sum over the 32-wide k-blocks j0 = 0, 32, .., kpad - 32 of load(j0); the next
+// block's operands are loaded before the current block's MFMAs (two register buffers).
+template <int MT, int NT, typename Load>
+__device__ inline void gemm16(int kpad, Load load, flt4 (&acc)[MT][NT]) {
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
+  Frag16<MT, NT> f0, f1;
+  load(0, f0);
+  for (int j0 = 0; j0 < kpad; j0 += 64) {
+    const bool has1 = j0 + 32 < kpad;
+    if (has1) load(j0 + 32, f1);
+    mma_block16<MT, NT>(f0, acc);
+    if (has1) {
+      if (j0 + 64 < kpad) load(j0 + 64, f0);
+      mma_block16<MT, NT>(f1, acc);
+    }
+  }
+}
+
+// Pass A / C: workgroup = (slab s, block of kNB columns); wave w owns rows
+// [w*MT*16, (w+1)*MT*16) of both contractions.  MPAD = 16 WAVES MT is a multiple of 32
+// and at least n, so the 32-wide k-blocks never leave the staged rows.
+//   GEMM1: Y1[i2][c] = sum_i1 X[s][i2][i1] W1[c][i1]   (W1 column tile in LDS, BF16)
+//   GEMM2: Y2[k2][c] = sum_i2 W2[k2][i2] Y1[i2][c]     (Y1 in LDS transposed, BF16)
+//   2D: Y2[k2][c] /= lam2[k2] + lam1[c].
+template <int WAVES, int MT, int NT, typename TI, typename TO, bool DIV, bool VEC>
+__global__ __launch_bounds__(64 * WAVES) void k_slab16(const TI *__restrict__ X, TO *__restrict__ Y,
+                                                       const __bf16 *__restrict__ W1, const __bf16 *__restrict__ W2,
+                                                       int ldw, int n, int64_t nslab, int ncb, int xcd_remap,
+                                                       const float *__restrict__ lam1, const float *__restrict__ lam2) {
+  constexpr int MPAD = WAVES * MT * 16;
+  static_assert(MPAD % 32 == 0, "k-blocks of 32 need MPAD a multiple of 32");
+  constexpr int LDP = MPAD + kPadB;
+  constexpr int NTHR = 64 * WAVES;
+  constexpr int kNB = 16 * NT;
+  __shared__ __attribute__((aligned(16))) __bf16 buf[kNB * LDP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  int64_t s;
+  int cb;
+  {
+    const int64_t bid = blockIdx.x;
+    if (xcd_remap) {  // the ncb workgroups of one slab share an XCD
+      const int64_t xcd = bid & 7, local = bid >> 3;
+      s = (local / ncb) * 8 + xcd;
+      cb = (int)(local % ncb);
+    } else {
+      s = bid / ncb;
+      cb = (int)(bid % ncb);
+    }
+  }
+  if (s >= nslab) return;
+  const int64_t n2 = (int64_t)n * n;
+  const TI *__restrict__ Xs = X + s * n2;
+  TO *__restrict__ Ys = Y + s * n2;
+  const int c0 = cb * kNB;
+  const int m0 = wave * MT * 16;
+  const int kpad = (n + 31) & ~31;
+  // the wave's whole strip of X (its MT*16 rows, every 32-wide k-block) is loaded first,
+  // eight BF16 per lane and k-block (4 VGPRs), so its memory latency overlaps the W1
+  // staging below
+  constexpr int KB = MPAD / 32;
+  bf16x8 xa[MT][KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const int j = kb * 32 + 8 * lg;
+#pragma unroll
+    for (int a = 0; a < MT; ++a) {
+      const int row = m0 + 16 * a + li;
+      xa[a][kb] = load8v<VEC>(Xs + (int64_t)row * n + j, j, n, row < n && kb * 32 < kpad);
+    }
+  }
+  // W1 columns c0 .. c0 + kNB (zero-padded factor rows and columns beyond n), 8 at a time
+  for (int e = threadIdx.x; e < kNB * (kpad / 8); e += NTHR) {
+    const int c = e / (kpad / 8), j = 8 * (e - c * (kpad / 8));
+    *reinterpret_cast<bf16x8 *>(buf + c * LDP + j) = load8_bf(W1 + (size_t)(c0 + c) * ldw + j);
+  }
+  __syncthreads();
+  flt4 acc[MT][NT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (kb * 32 >= kpad) break;
+    const int j = kb * 32 + 8 * lg;
+    bf16x8 bv[NT];
+#pragma unroll
+    for (int b = 0; b < NT; ++b) bv[b] = load8_bf(buf + (16 * b + li) * LDP + j);
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int b = 0; b < NT; ++b) acc[a][b] = mfma16(xa[a][kb], bv[b], acc[a][b]);
+  }
+  __syncthreads();  // every wave is done with the W1 tile
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + 4 * lg + r] = to_bf16(acc[a][b][r]);
+  __syncthreads();
+  gemm16<MT, NT>(kpad, [&](int j0, Frag16<MT, NT> &f) {
+    const int j = j0 + 8 * lg;
+#pragma unroll
+    for (int a = 0; a < MT; ++a) f.a[a] = load8_bf(W2 + (size_t)(m0 + 16 * a + li) * ldw + j);
+#pragma unroll
+    for (int b = 0; b < NT; ++b) f.b[b] = load8_bf(buf + (16 * b + li) * LDP + j);
+  }, acc);
+#pragma unroll
+  for (int b = 0; b < NT; ++b) {
+    const int c = c0 + 16 * b + li;
+    if (c >= n) continue;
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k2 = m0 + 16 * a + 4 * lg + r;
+        if (k2 < n) {
+          float v = acc[a][b][r];
+          if (DIV) v = v / (lam2[k2] + lam1[c]);
+          Ys[(int64_t)k2 * n + c] = (TO)v;
+        }
+      }
+  }
+}
+
+// Pass B: workgroup = (entry, block of kNB columns c of X[i3][c]); the block is staged
+// transposed in LDS (BF16), then T = Wa X, T /= lam3 + lam2 + lam1 (FP32), S = Wb T.
+template <int WAVES, int MT, int NT>
+__global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict__ X, float *__restrict__ Y,
+                                                        const __bf16 *__restrict__ Wa, const __bf16 *__restrict__ Wb,
+                                                        int ldw, int n, int ncb, const float *__restrict__ lam1,
+                                                        const float *__restrict__ lam2, const float *__restrict__ lam3) {
+  constexpr int MPAD = WAVES * MT * 16;
+  static_assert(MPAD % 32 == 0, "k-blocks of 32 need MPAD a multiple of 32");
+  constexpr int LDP = MPAD + kPadB;
+  constexpr int NTHR = 64 * WAVES;
+  constexpr int kNB = 16 * NT;
+  __shared__ __attribute__((aligned(16))) __bf16 xt[kNB * LDP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t bidx = blockIdx.x / ncb;
+  const int cb = (int)(blockIdx.x % ncb);
+  const int64_t n2 = (int64_t)n * n;
+  const float *__restrict__ Xb = X + bidx * n2 * n;
+  float *__restrict__ Yb = Y + bidx * n2 * n;
+  const int64_t c0 = (int64_t)cb * kNB;
+  const int m0 = wave * MT * 16;
+  const int kpad = (n + 31) & ~31;
+  for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
+    const int i3 = e / kNB, c = e % kNB;
+    const int64_t cg = c0 + c;
+    xt[c * LDP + i3] = to_bf16((i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0f);
+  }
+  __syncthreads();
+  flt4 acc[MT][NT];
+  auto lds_gemm = [&](const __bf16 *W) {
+    gemm16<MT, NT>(kpad, [&](int j0, Frag16<MT, NT> &f) {
+      const int j = j0 + 8 * lg;
+#pragma unroll
+      for (int a = 0; a < MT; ++a) f.a[a] = load8_bf(W + (size_t)(m0 + 16 * a + li) * ldw + j);
+#pragma unroll
+      for (int b = 0; b < NT; ++b) f.b[b] = load8_bf(xt + (16 * b + li) * LDP + j);
+    }, acc);
+  };
+  lds_gemm(Wa);
+  __syncthreads();  // every wave is done with the staged block
+#pragma unroll
+  for (int b = 0; b < NT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    const bool cok = cg < n2;
+    const int i2 = cok ? (int)(cg / n) : 0, i1 = cok ? (int)(cg % n) : 0;
+    const float l12 = lam2[i2] + lam1[i1];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k3 = m0 + 16 * a + 4 * lg + r;
+        // rows k3 >= n are zero (zero-padded Wa); lam3 is padded with 1
+        xt[(16 * b + li) * LDP + k3] = to_bf16(acc[a][b][r] / (lam3[k3] + l12));
+      }
+  }
+  __syncthreads();
+  lds_gemm(Wb);
+#pragma unroll
+  for (int b = 0; b < NT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    if (cg >= n2) continue;
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k3 = m0 + 16 * a + 4 * lg + r;
+        if (k3 < n) Yb[(int64_t)k3 * n2 + cg] = acc[a][b][r];
+      }
+  }
+}
+
+// Workgroup shape: waves and 16-row tiles per wave with 16 WAVES MT >= roundup(n, 32) and
+// a multiple of 32; 16 columns per workgroup for 3D n <= 96 and the 2D solve (more
+// workgroups), 32 otherwise.
+struct Shape16 {
+  int waves, mt, nt;
+};
+
+Shape16 pick_shape16(int n, bool small_grid) {
+  const int nt = (small_grid || n <= 96) ? 1 : 2;
+  const int k = (n + 31) / 32;
+  if (k <= 2) return {4, 1, nt};
+  if (k <= 4) return {2 * k, 1, nt};
+  if (k <= 6) return {12, 1, nt};
+  return {8, 2, nt};
+}
+
+#define FDG_SHAPES16(X) \
+  X(4, 1, 1) X(6, 1, 1) X(8, 1, 1) X(12, 1, 1) X(8, 2, 1) X(4, 1, 2) X(6, 1, 2) X(8, 1, 2) X(12, 1, 2) X(8, 2, 2)
+
+template <int W, int M, int NT, typename TI, typename TO>
+void slab16(hipStream_t s, const TI *X, TO *Y, const __bf16 *W1, const __bf16 *W2, int ldw, int n, int64_t nslab,
+            bool div, const float *lam1, const float *lam2) {
+  constexpr int kNB = 16 * NT;
+  const int ncb = (n + kNB - 1) / kNB;
+  const int remap = (nslab % 8 == 0) ? 1 : 0;
+  const dim3 grid((unsigned)(nslab * ncb)), blk(64 * W);
+  const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 31) == 0;
+#define FDG_SLAB16(D, V)                                                                                        \
+  hipLaunchKernelGGL((k_slab16<W, M, NT, TI, TO, D, V>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, \
+                     lam1, lam2)
+  if (div) {
+    if (vec) FDG_SLAB16(true, true); else FDG_SLAB16(true, false);
+  } else {
+    if (vec) FDG_SLAB16(false, true); else FDG_SLAB16(false, false);
+  }
+#undef FDG_SLAB16
+}
+
+template <typename TI, typename TO>
+void slab16_dispatch(hipStream_t s, const TI *X, TO *Y, const __bf16 *W1, const __bf16 *W2, int ldw, int n,
+                     int64_t nslab, bool two_d, bool div, const float *lam1, const float *lam2) {
+  const Shape16 sh = pick_shape16(n, two_d);
+#define FDG_CASE(W, M, T)                                                        \
+  if (sh.waves == W && sh.mt == M && sh.nt == T) {                              \
+    slab16<W, M, T, TI, TO>(s, X, Y, W1, W2, ldw, n, nslab, div, lam1, lam2);   \
+    return;                                                                     \
+  }
+  FDG_SHAPES16(FDG_CASE)
+#undef FDG_CASE
+}
+
+void fibre16_dispatch(hipStream_t s, const float *X, float *Y, const __bf16 *Wa, const __bf16 *Wb, int ldw, int n,
+                      int64_t batch, const float *lam1, const float *lam2, const float *lam3) {
+  const Shape16 sh = pick_shape16(n, false);
+  const int64_t n2 = (int64_t)n * n;
+#define FDG_CASE(W, M, T)                                                                                         \
+  if (sh.waves == W && sh.mt == M && sh.nt == T) {                                                               \
+    const int ncb = (int)((n2 + 16 * T - 1) / (16 * T));                                                         \
+    hipLaunchKernelGGL((k_fibre16<W, M, T>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, Wa, Wb, ldw, \
+                       n, ncb, lam1, lam2, lam3);                                                                \
+    return;                                                                                                      \
+  }
+  FDG_SHAPES16(FDG_CASE)
+#undef FDG_CASE
+}
+
+}  // namespace
+
+void launch_fd_apply_bf16(hipStream_t s, int d, int n, int64_t batch, const double *b, double *out, float *t1,
+                          float *t2, const void *const *Wv, const void *const *Wu, const float *const *lam, int ldw) {
+  const __bf16 *V0 = (const __bf16 *)Wv[0], *V1 = (const __bf16 *)Wv[1];
+  const __bf16 *U0 = (const __bf16 *)Wu[0], *U1 = (const __bf16 *)Wu[1];
+  if (d == 3) {
+    const int64_t nslab = batch * n;
+    slab16_dispatch<double, float>(s, b, t1, V0, V1, ldw, n, nslab, false, false, nullptr, nullptr);
+    fibre16_dispatch(s, t1, t2, (const __bf16 *)Wv[2], (const __bf16 *)Wu[2], ldw, n, batch, lam[0], lam[1], lam[2]);
+    slab16_dispatch<float, double>(s, t2, out, U0, U1, ldw, n, nslab, false, false, nullptr, nullptr);
+  } else {
+    slab16_dispatch<double, float>(s, b, t1, V0, V1, ldw, n, batch, true, true, lam[0], lam[1]);
+    slab16_dispatch<float, double>(s, t1, out, U0, U1, ldw, n, batch, true, false, nullptr, nullptr);
+  }
+}
+
+}  // namespace fdg

@@ -234,6 +234,29 @@ def test_errors_through_the_abi():
     ctx.close()
 
 
+@pytest.mark.parametrize("d,p,n,bound", [(3, 4, 40, 5e-2), (3, 3, 33, 5e-2), (3, 6, 65, 5e-2), (2, 4, 130, 5e-2),
+                                         (2, 3, 47, 5e-2), (3, 5, 96, 5e-2), (3, 4, 129, 5e-2), (3, 3, 200, 5e-2),
+                                         (2, 2, 260, 0.2)])
+def test_bf16_apply_fused_passes(d, p, n, bound):
+    """BF16 products with FP32 accumulation (fused passes for n <= 256, mode products
+    beyond): the one-apply contraction |b - P P~^{-1} b| / |b| stays at the BF16 rounding
+    level times the conditioning of P, which grows like n^2 (0.14 for the 2D p = 2, n = 260
+    case, which takes the mode-product form)."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.unit_problem(d, p, n, prec=fdg.PREC_BF16)
+    b = inputs.rhs_normal(7, n ** d)
+    s = torch.empty(n ** d, dtype=torch.float64, device="cuda")
+    ctx.apply_prec(to_dev(b), s)
+    torch.cuda.synchronize()
+    P, prec64 = oracle_unit(p, n, d)
+    sg = s.cpu().numpy()
+    assert np.all(np.isfinite(sg))
+    assert relerr(P @ sg, b) <= bound
+    assert relerr(sg, prec64(b)) <= 0.5
+    ctx.close()
+
+
 @pytest.mark.parametrize("d,p,n", [(3, 4, 40), (3, 3, 33), (3, 6, 65), (2, 4, 130), (2, 3, 47), (3, 5, 96),
                                    (3, 4, 129), (2, 2, 260)])
 def test_fp32_apply_fused_passes(d, p, n):
