@@ -35,6 +35,27 @@ __device__ inline void load4f(const T *p, int j, int jmax, bool ok, float (&v)[4
   for (int t = 0; t < 4; ++t) v[t] = (ok && j + t < jmax) ? (float)p[t] : 0.0f;
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// The same with one 4-wide load where the whole group is in range (VEC: p is aligned to
+// 4 elements, i.e. n % 4 == 0 and 32-byte aligned rows).
+template <bool VEC, typename T>
+__device__ inline void load4v(const T *p, int j, int jmax, bool ok, float (&v)[4]) {
+  if (VEC && ok && j + 3 < jmax) {
+    if constexpr (sizeof(T) == 8) {
+      const dbl4 x = *reinterpret_cast<const dbl4 *>(p);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t] = (float)x[t];
+    } else {
+      const flt4 x = *reinterpret_cast<const flt4 *>(p);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t] = x[t];
+    }
+    return;
+  }
+  load4f(p, j, jmax, ok, v);
+}
+
 template <int MT, int NT>
 struct Frag32 {
   float a[MT][4];
@@ -75,7 +96,7 @@ __device__ inline void gemm32(int kpad, Load load, flt4 (&acc)[MT][NT]) {
 //   GEMM1: Y1[i2][c] = sum_i1 X[s][i2][i1] W1[c][i1]   (W1 column tile in LDS)
 //   GEMM2: Y2[k2][c] = sum_i2 W2[k2][i2] Y1[i2][c]     (Y1 in LDS, transposed)
 //   2D: Y2[k2][c] /= lam2[k2] + lam1[c].
-template <int WAVES, int MT, int NT, typename TI, typename TO, bool DIV>
+template <int WAVES, int MT, int NT, typename TI, typename TO, bool DIV, bool VEC>
 __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X, TO *__restrict__ Y,
                                                        const float *__restrict__ W1, const float *__restrict__ W2,
                                                        int ldw, int n, int64_t nslab, int ncb, int xcd_remap,
@@ -118,7 +139,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
 #pragma unroll
     for (int a = 0; a < MT; ++a) {
       const int row = m0 + 16 * a + li;
-      load4f(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
+      load4v<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
     }
 #pragma unroll
     for (int b = 0; b < NT; ++b) {
@@ -267,12 +288,16 @@ void slab32(hipStream_t s, const TI *X, TO *Y, const float *W1, const float *W2,
   const int ncb = (n + kNB - 1) / kNB;
   const int remap = (nslab % 8 == 0) ? 1 : 0;
   const dim3 grid((unsigned)(nslab * ncb)), blk(64 * W);
-  if (div)
-    hipLaunchKernelGGL((k_slab32<W, M, NT, TI, TO, true>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap,
-                       lam1, lam2);
-  else
-    hipLaunchKernelGGL((k_slab32<W, M, NT, TI, TO, false>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap,
-                       lam1, lam2);
+  const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 31) == 0;
+#define FDG_SLAB32(D, V)                                                                                        \
+  hipLaunchKernelGGL((k_slab32<W, M, NT, TI, TO, D, V>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, \
+                     lam1, lam2)
+  if (div) {
+    if (vec) FDG_SLAB32(true, true); else FDG_SLAB32(true, false);
+  } else {
+    if (vec) FDG_SLAB32(false, true); else FDG_SLAB32(false, false);
+  }
+#undef FDG_SLAB32
 }
 
 template <typename TI, typename TO>
