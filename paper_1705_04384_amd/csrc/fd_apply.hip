@@ -255,7 +255,7 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
 //   GEMM1: T[k3][c] = sum_i3 Wa[k3][i3] X[i3][c];   T /= lam3[k3] + lam2[i2] + lam1[i1]
 //   GEMM2: S[k3][c] = sum_k Wb[k3][k] T[k][c]        (T back in LDS, transposed)
 // ------------------------------------------------------------------------------------
-template <int WAVES, int MT, int NT>
+template <int WAVES, int MT, int NT, bool VEC>
 __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
                                                       const double *__restrict__ Wa, const double *__restrict__ Wb,
                                                       int ldw, int n, int ncb, const double *__restrict__ lam1,
@@ -276,11 +276,24 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
-  // stage X[i3][c0 .. c0+kNB) -> xt[c][i3], zero beyond n or n^2
-  for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
-    const int i3 = e / kNB, c = e % kNB;
-    const int64_t cg = c0 + c;
-    xt[c * LDP + i3] = (i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0;
+  // stage X[i3][c0 .. c0+kNB) -> xt[c][i3], zero beyond n or n^2 (VEC: n^2 % 4 == 0 and
+  // 32-byte aligned entries, four columns per load)
+  if (VEC) {
+    constexpr int Q = kNB / 4;
+    for (int e = threadIdx.x; e < kpad * Q; e += NTHR) {
+      const int i3 = e / Q, q = e - i3 * Q;
+      const int64_t cg = c0 + 4 * q;
+      dbl4 v = dbl4{0.0, 0.0, 0.0, 0.0};
+      if (i3 < n && cg < n2) v = *(gptr<const dbl4>)(Xb + (int64_t)i3 * n2 + cg);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = v[t];
+    }
+  } else {
+    for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
+      const int i3 = e / kNB, c = e % kNB;
+      const int64_t cg = c0 + c;
+      xt[c * LDP + i3] = (i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0;
+    }
   }
   __syncthreads();
   dbl4 acc[MT][NT];
@@ -374,7 +387,13 @@ void fibre_launch(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const dou
   const int64_t n2 = (int64_t)n * n;
   const int ncb = (int)((n2 + kNB - 1) / kNB);
   const dim3 grid((unsigned)(batch * ncb)), blk(64 * WAVES);
-  launch_timed(k_fibre<WAVES, MT, NT>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
+  // 4-wide staging loads: every entry and every i3 row 32-byte aligned
+  const bool vec = n2 % 4 == 0 && !X.ptrs && (reinterpret_cast<uintptr_t>(X.base) & 31) == 0 &&
+                   (batch == 1 || X.stride % 4 == 0);
+  if (vec)
+    launch_timed(k_fibre<WAVES, MT, NT, true>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
+  else
+    launch_timed(k_fibre<WAVES, MT, NT, false>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
 }
 
 }  // namespace
