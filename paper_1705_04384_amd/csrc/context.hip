@@ -382,7 +382,9 @@ int ensure_krylov(fdg_ctx *c, int m) {
   if ((st = dalloc(&c->Hcol, (size_t)(m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->hbuf, (size_t)2 * (m + 2) * c->batch)) != FDG_OK) return st;
   if ((st = dalloc(&c->scal, (size_t)4 * c->batch)) != FDG_OK) return st;
-  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * (size_t)host_doubles(m) * c->batch, hipHostMallocMapped));
+  // two banks of host-mapped slots: a speculative Arnoldi step writes the other bank
+  HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * 2 * (size_t)host_doubles(m) * c->batch,
+                       hipHostMallocMapped));
   HIPCHK(hipHostGetDevicePointer((void **)&c->hpin_dev, c->hpin, 0));
 
   c->restart_alloc = m;
@@ -877,14 +879,31 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   if (!c->phase_ev) HIPCHK(hipEventCreateWithFlags(&c->phase_ev, hipEventDisableTiming));
   SolveRun run;
   run.init(c, rb, restart, b, x, rtol, maxit, flags);
+  run.bank_stride = (size_t)host_doubles(restart);
   SolveRun *rp = &run;
   const Exec ex{c->stream, true};
   bool stream_idle = true;
+  bool queued = false;  // the current phase is already on the stream (an adopted speculation)
+  Phase spec;
+  bool spec_queued = false;
   while (!run.finished()) {
-    // the previous phase's last kernel may still be retiring (its results were read);
-    // the slots armed here are ones it has already written, so it cannot overwrite them
-    run.arm();
-    if ((st = enqueue_phase(ex, &rp, 1, nullptr)) != FDG_OK) return st;
+    if (!queued) {
+      // the previous phase's last kernel may still be retiring (its results were read);
+      // the slots armed here are ones it has already written, so it cannot overwrite them
+      run.arm();
+      if ((st = enqueue_phase(ex, &rp, 1, nullptr)) != FDG_OK) return st;
+    }
+    // the next Arnoldi step needs nothing from the host: queue it behind this one (other
+    // bank of slots) while the host waits, unless the cycle may end here
+    if (!spec_queued && run.speculative(&spec)) {
+      const Phase cur = run.phase();
+      run.arm(spec);
+      run.set_phase(spec);
+      st = enqueue_phase(ex, &rp, 1, nullptr);
+      run.set_phase(cur);
+      if (st != FDG_OK) return st;
+      spec_queued = true;
+    }
     HIPCHK(hipEventRecord(c->phase_ev, c->stream));
     stream_idle = false;
     // the host needs the phase's scalars, not the end of its last kernel: poll the armed
@@ -905,7 +924,15 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       HIPCHK(e);
       stream_idle = true;
     }
+    const int consumed_bank = run.phase().bank;
     run.consume();
+    // the next phase: the queued speculation when consume() chose the same step, else a
+    // new phase in the bank just read (a discarded speculation still writes the other)
+    Phase next = run.phase();
+    queued = spec_queued && next.steps == spec.steps && next.j == spec.j;
+    next.bank = queued ? spec.bank : consumed_bank;
+    run.set_phase(next);
+    spec_queued = false;  // adopted, or discarded (it runs ahead of the next phase, harmlessly)
   }
   if (!stream_idle) {  // x and the buffers belong to the caller again only after the stream
     hipError_t e;

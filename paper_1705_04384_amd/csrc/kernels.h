@@ -107,10 +107,11 @@ void launch_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch w, int6
 // h1 = sum(Pin) (block 0 stores it to hout.at(e)); w -= V h1; Pout = partials of V^T w.
 void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch Pin, int G, int ldp,
                         MBatch w, int64_t N, int64_t nbatch, MBatch Pout, MBatch hout, bool aligned16_all);
-// h2 = sum(Pin); Hcol = h1 + h2 (and host copy); w -= V h2; Pnorm = partials of |w|^2.
+// h2 = sum(Pin); Hcol = h1 + h2 (and host copy); w -= V h2; Pnorm = partials of |w|^2
+// (and, when valid, the same partials to Pdev, device memory a later kernel reduces).
 void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch Pin, int G, int ldp,
                         MBatch w, int64_t N, int64_t nbatch, MBatch Pnorm, CBatch h1, MBatch Hcol,
-                        MBatch host, bool aligned16_all);
+                        MBatch host, bool aligned16_all, MBatch Pdev = MBatch{});
 // d = sqrt(sum of Pn.at(e)[g], g < G); v = w / d (0 if d = 0; v may equal w); d to
 // out.at(e)[0] and host.at(e)[0] (either may be invalid).
 void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, CBatch Pn, int G, int64_t N, int64_t nbatch,

@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kRed) void k_update_dots(CBatch V, int64_t ldv, IBa
 template <bool VEC>
 __global__ __launch_bounds__(kRed) void k_update_norm(CBatch V, int64_t ldv, IBatch nvs, CBatch Pin, int G,
                                                       int ldp, MBatch w, int64_t N, MBatch Pnorm, CBatch h1,
-                                                      MBatch Hcol, MBatch host) {
+                                                      MBatch Hcol, MBatch host, MBatch Pdev) {
   __shared__ double hs[256];
   __shared__ double red[kRedWaves];
   const int g = blockIdx.x;
@@ -358,7 +358,10 @@ __global__ __launch_bounds__(kRed) void k_update_norm(CBatch V, int64_t ldv, IBa
   chunk_of(N, G, g, beg, end);
   const double nrm = chunk_update<VEC>(V.gat(b), ldv, nv, hs, w.gat(b), beg, end);
   const double s = block_sum(nrm, red);
-  if (threadIdx.x == 0) Pnorm.gat(b)[g] = s;
+  if (threadIdx.x == 0) {
+    Pnorm.gat(b)[g] = s;
+    if (Pdev.valid()) Pdev.gat(b)[g] = s;
+  }
 }
 
 // d = sqrt(reduce(Pn)); v = w / d (0 if d = 0).  Block 0 stores d to out and host.
@@ -552,13 +555,15 @@ void launch_update_dots(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch 
 
 void launch_update_norm(hipStream_t s, CBatch V, int64_t ldv, IBatch nv, CBatch Pin, int G, int ldp, MBatch w,
                         int64_t N, int64_t nbatch, MBatch Pnorm, CBatch h1, MBatch Hcol, MBatch host,
-                        bool aligned16_all) {
+                        bool aligned16_all, MBatch Pdev) {
   const bool vec = N % 2 == 0 && ldv % 2 == 0 && aligned16_all;
   const dim3 grid(G, (unsigned)nbatch), blk(kRed);
   if (vec)
-    hipLaunchKernelGGL(k_update_norm<true>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pnorm, h1, Hcol, host);
+    hipLaunchKernelGGL(k_update_norm<true>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pnorm, h1, Hcol, host,
+                       Pdev);
   else
-    hipLaunchKernelGGL(k_update_norm<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pnorm, h1, Hcol, host);
+    hipLaunchKernelGGL(k_update_norm<false>, grid, blk, 0, s, V, ldv, nv, Pin, G, ldp, w, N, Pnorm, h1, Hcol, host,
+                       Pdev);
 }
 
 void launch_scale_reduce(hipStream_t s, CBatch w, MBatch v, CBatch Pn, int G, int64_t N, int64_t nbatch,

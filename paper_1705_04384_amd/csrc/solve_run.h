@@ -56,6 +56,7 @@ enum : unsigned {
   kStepIter = 1u << 6,     // Z_j = P^-1 V_j; w = V_{j+1} = A Z_j; CGS2; column -> hh,
                            // partials of |w|^2 -> hh[m+4 ..] (w is scaled by the next phase)
   kStepZeroX = 1u << 7,    // x = 0
+  kStepScaleVDev = 1u << 8,  // V_j /= sqrt(sum of the |w|^2 partials in P3), formed on the device
 };
 
 struct Phase {
@@ -64,6 +65,7 @@ struct Phase {
   int k = 0;               // coefficients of kStepLincomb
   bool overwrite = false;  // kStepLincomb starts from x = 0
   double div = 1.0;        // divisor of kStepScaleV
+  int bank = 0;            // bank of host-mapped slots the phase writes (see bank_stride)
 };
 
 class SolveRun {
@@ -84,8 +86,18 @@ class SolveRun {
   // is true once every armed slot holds a kernel's value, which a host can poll instead
   // of waiting for the end of the last kernel.  A phase without such slots arms nothing
   // and is never ready (wait for the stream instead).
-  void arm();
+  void arm() { arm(ph_); }
+  void arm(const Phase &p);  // the slots of phase p (not necessarily the current one)
   bool ready() const;
+  // The next Arnoldi step (v_{j+1} scaled on the device, then step j + 1) when the phase
+  // in flight is step j and the host expects to continue the cycle after it: the caller
+  // may enqueue it before reading step j's results, in the other bank of slots.  The
+  // continuation is taken only while the residual estimate is well above the target, so
+  // a step launched in vain (a cycle that ends after all) is rare.
+  bool speculative(Phase *next) const;
+  // Replaces the current phase (the caller enqueues a speculative phase, or adopts one
+  // that consume() chose after all, with its bank).
+  void set_phase(const Phase &p) { ph_ = p; }
   int status() const { return status_; }
   const fdg_info &info() const { return info_; }
   const Coeffs &coeffs() const { return y_; }
@@ -96,17 +108,26 @@ class SolveRun {
   int64_t N = 0;
   int G = 0;
   int res_parts = 0;  // partials of the fused residual matvec, 0 if it does not apply
+  // Host-mapped slots of bank k start at buf.hh + k * bank_stride (0: one bank, no
+  // speculation; the request server uses one bank per run).
+  size_t bank_stride = 0;
+  volatile double *hh(int bank) const { return buf.hh + (size_t)bank * bank_stride; }
+  double *hh_dev(int bank) const { return buf.hh_dev + (size_t)bank * bank_stride; }
   const double *b = nullptr;
   double *x = nullptr;
 
  private:
   double &Hij(int i, int jj) { return H_[(size_t)i * m + jj]; }
   double host_norm(int count) const;  // sqrt of the block-ordered sum of count partials in hh
+  double tree_norm() const;           // sqrt of the G partials summed in the device's order
   void finish(bool converged);
   void zero_then_finish(bool converged);
 
-  int armed_hcol_ = 0, armed_parts_ = 0;  // armed slots: hh[0, hcol), hh[m+4, m+4+parts)
-  bool armed_bnorm_ = false;              // and hh[m+2]
+  struct Armed {
+    int hcol = 0, parts = 0;  // armed slots: hh[0, hcol), hh[m+4, m+4+parts)
+    bool bnorm = false;       // and hh[m+2]
+  };
+  Armed armed_[2];
   Phase ph_;
   double rtol_ = 0.0, bnorm_ = -1.0, target_ = 0.0, last_est_ = 1.0, rbeta_ = 0.0;
   int limit_ = 0, total_ = 0, restarts_ = 0, status_ = FDG_OK;

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 
+#include "reduce.h"
 #include "solve_run.h"
 
 namespace fdg {
@@ -114,41 +115,79 @@ void SolveRun::finish(bool converged) {
 }
 
 double SolveRun::host_norm(int count) const {
+  const volatile double *h = hh(ph_.bank);
   double sum = 0.0;
-  for (int g = 0; g < count; ++g) sum += buf.hh[m + 4 + g];
+  for (int g = 0; g < count; ++g) sum += h[m + 4 + g];
   return std::sqrt(sum);
+}
+
+// The order of sum_partials: lane l adds partials l, l + 64, l + 128, l + 192 to 0, then
+// an xor butterfly over the 64 lanes.  The device scales v_{j+1} by the square root of
+// this sum, and the Hessenberg entry is the same number.
+double SolveRun::tree_norm() const {
+  const volatile double *h = hh(ph_.bank) + m + 4;
+  double v[64];
+  for (int l = 0; l < 64; ++l) {
+    double s = 0.0;
+    for (int k = 0; k < kMaxG / 64; ++k) {
+      const int g = l + 64 * k;
+      s += g < G ? h[g] : 0.0;
+    }
+    v[l] = s;
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    double t[64];
+    for (int l = 0; l < 64; ++l) t[l] = v[l] + v[l ^ off];
+    for (int l = 0; l < 64; ++l) v[l] = t[l];
+  }
+  return std::sqrt(v[0]);
 }
 
 namespace {
 constexpr uint64_t kUnwritten = 0x7FF4DEADBEEF0001ull;  // signalling NaN: never a kernel result
 }
 
-void SolveRun::arm() {
-  const unsigned st = ph_.steps;
-  armed_hcol_ = armed_parts_ = 0;
-  armed_bnorm_ = false;
+void SolveRun::arm(const Phase &p) {
+  const unsigned st = p.steps;
+  Armed &a = armed_[p.bank];
+  a = Armed{};
   if (st == 0 || (st & kStepZeroX)) return;
-  if (st & (kStepBNorm | kStepBScale)) armed_bnorm_ = true;
+  if (st & (kStepBNorm | kStepBScale)) a.bnorm = true;
   if (st & kStepIter) {
-    armed_hcol_ = ph_.j + 1;
-    armed_parts_ = G;
+    a.hcol = p.j + 1;
+    a.parts = G;
   } else if (st & kStepRes) {
-    armed_parts_ = res_parts > 0 ? res_parts : G;
+    a.parts = res_parts > 0 ? res_parts : G;
   }
-  volatile uint64_t *w = reinterpret_cast<volatile uint64_t *>(buf.hh);
-  for (int q = 0; q < armed_hcol_; ++q) w[q] = kUnwritten;
-  if (armed_bnorm_) w[m + 2] = kUnwritten;
-  for (int g = 0; g < armed_parts_; ++g) w[m + 4 + g] = kUnwritten;
+  volatile uint64_t *w = reinterpret_cast<volatile uint64_t *>(hh(p.bank));
+  for (int q = 0; q < a.hcol; ++q) w[q] = kUnwritten;
+  if (a.bnorm) w[m + 2] = kUnwritten;
+  for (int g = 0; g < a.parts; ++g) w[m + 4 + g] = kUnwritten;
 }
 
 bool SolveRun::ready() const {
-  if (armed_hcol_ == 0 && armed_parts_ == 0 && !armed_bnorm_) return false;
-  const volatile uint64_t *w = reinterpret_cast<const volatile uint64_t *>(buf.hh);
-  for (int g = armed_parts_ - 1; g >= 0; --g)
+  const Armed &a = armed_[ph_.bank];
+  if (a.hcol == 0 && a.parts == 0 && !a.bnorm) return false;
+  const volatile uint64_t *w = reinterpret_cast<const volatile uint64_t *>(hh(ph_.bank));
+  for (int g = a.parts - 1; g >= 0; --g)
     if (w[m + 4 + g] == kUnwritten) return false;
-  for (int q = 0; q < armed_hcol_; ++q)
+  for (int q = 0; q < a.hcol; ++q)
     if (w[q] == kUnwritten) return false;
-  return !armed_bnorm_ || w[m + 2] != kUnwritten;
+  return !a.bnorm || w[m + 2] != kUnwritten;
+}
+
+bool SolveRun::speculative(Phase *next) const {
+  if (bank_stride == 0 || !(ph_.steps & kStepIter) || breakdown_) return false;
+  const int j = ph_.j;
+  if (j + 2 > m || total_ + 2 > limit_) return false;  // step j ends the cycle or the budget
+  // estimates exist from the first consumed step on; margin 20 on the relative estimate
+  if (!fixed_ && (total_ < 1 || !(last_est_ > 20.0 * rtol_))) return false;
+  Phase p;
+  p.steps = kStepScaleVDev | kStepIter;
+  p.j = j + 1;
+  p.bank = 1 - ph_.bank;
+  *next = p;
+  return true;
 }
 
 void SolveRun::zero_then_finish(bool converged) {
@@ -164,8 +203,9 @@ void SolveRun::consume() {
     finish(pending_conv_);
     return;
   }
+  const volatile double *hb = hh(ph_.bank);
   auto learn_bnorm = [&]() {
-    bnorm_ = buf.hh[m + 2];
+    bnorm_ = hb[m + 2];
     target_ = rtol_ * bnorm_;
   };
   if (st & kStepRes) {  // true residual r = b - A x in V0, its norm from the partials
@@ -211,8 +251,8 @@ void SolveRun::consume() {
     }
   }
   const int nv = j + 1;
-  for (int q = 0; q < nv; ++q) Hij(q, j) = buf.hh[q];
-  Hij(nv, j) = host_norm(G);
+  for (int q = 0; q < nv; ++q) Hij(q, j) = hb[q];
+  Hij(nv, j) = tree_norm();
   double wn0 = 0.0;
   for (int q = 0; q <= nv; ++q) wn0 += Hij(q, j) * Hij(q, j);
   wn0 = std::sqrt(wn0);
@@ -242,11 +282,12 @@ void SolveRun::consume() {
   breakdown_ = hn <= 1e-14 * wn0;
   const bool end_cycle =
       total_ >= limit_ || breakdown_ || j + 1 >= m || (!fixed_ && std::fabs(g_[j + 1]) <= target_);
-  if (!end_cycle) {  // v_{j+1} = w / h_{j+1,j}, then the next Arnoldi step
+  if (!end_cycle) {  // v_{j+1} = w / h_{j+1,j} (the norm formed on the device), next step
+    const int bank = ph_.bank;
     ph_ = Phase{};
-    ph_.steps = kStepScaleV | kStepIter;
+    ph_.steps = kStepScaleVDev | kStepIter;
     ph_.j = j + 1;
-    ph_.div = hn;
+    ph_.bank = bank;
     return;
   }
   const int k = j + 1;
@@ -371,8 +412,8 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
   const MBatch T2 = ga.m([](R r) { return r.buf.t2; });
   const MBatch P3 = ga.m([](R r) { return r.buf.P3; });
   const MBatch Sb = ga.m([](R r) { return r.buf.scal; });
-  const MBatch Hb = ga.m([m](R r) { return r.buf.hh_dev + m + 2; });
-  const MBatch Hp = ga.m([m](R r) { return r.buf.hh_dev + m + 4; });  // host-summed partials
+  const MBatch Hb = ga.m([m](R r) { return r.hh_dev(r.phase().bank) + m + 2; });
+  const MBatch Hp = ga.m([m](R r) { return r.hh_dev(r.phase().bank) + m + 4; });  // host-summed partials
   MBatch X, Z0, Vj, Zj, Vj1, P1, P2, H1, Hc, Hh;
   CBatch Zb;
   IBatch K, OW, NV;
@@ -387,7 +428,7 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
     OW = ga.i([](R r) { return r.phase().overwrite ? 1 : 0; });
     ytab = ga.ytab();
   }
-  if (steps & (kStepIter | kStepScaleV)) {
+  if (steps & (kStepIter | kStepScaleV | kStepScaleVDev)) {
     Vj = ga.m([](R r) { return r.buf.V + (size_t)r.phase().j * r.N; });
   }
   if (steps & kStepScaleV) dtab = ga.dtab();
@@ -399,7 +440,7 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
     P2 = ga.m([](R r) { return r.buf.P2; });
     H1 = ga.m([](R r) { return r.buf.h1; });
     Hc = ga.m([](R r) { return r.buf.Hcol; });
-    Hh = ga.m([](R r) { return r.buf.hh_dev; });
+    Hh = ga.m([](R r) { return r.hh_dev(r.phase().bank); });
   }
   if (ga.full) return set_error(FDG_ENOMEM, "enqueue_phase: pointer-table arena full");
   if (nrun > 1) {
@@ -449,6 +490,10 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
     TimedLaunch tl(c, 2, s, timed);
     launch_scale_by(s, as_const(Vj), Vj, dtab, r0.phase().div, N, nrun, true);
   }
+  if (steps & kStepScaleVDev) {  // v_j = w / ||w|| with the norm formed from P3 on the device
+    TimedLaunch tl(c, 2, s, timed);
+    launch_scale_reduce(s, as_const(Vj), Vj, as_const(P3), G, N, nrun, MBatch{}, MBatch{}, true);
+  }
   if (steps & kStepIter) {
     if ((st = apply_entries(c, ex, as_const(Vj), Zj, nrun, T1, T2, r0.buf.t32a, r0.buf.t32b, a32)) != FDG_OK)
       return st;
@@ -463,7 +508,7 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
     }
     {  // w -= V h2; Hessenberg column h1 + h2 (device and host-mapped); |w|^2 partials
       TimedLaunch tl(c, 2, s, timed);
-      launch_update_norm(s, Vb, N, NV, as_const(P2), G, ldp, Vj1, N, nrun, Hp, as_const(H1), Hc, Hh, true);
+      launch_update_norm(s, Vb, N, NV, as_const(P2), G, ldp, Vj1, N, nrun, Hp, as_const(H1), Hc, Hh, true, P3);
     }
   }
   return hip_check(hipGetLastError(), "solve phase launch");
