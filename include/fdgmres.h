@@ -52,7 +52,8 @@ typedef enum {
 
 enum {
   FDG_SOLVE_USE_X0 = 1,       /* start from the x passed in instead of 0                     */
-  FDG_SOLVE_FIXED_ITERS = 2   /* run exactly maxit inner iterations, ignore rtol in a cycle  */
+  FDG_SOLVE_FIXED_ITERS = 2,  /* run exactly maxit inner iterations, ignore rtol in a cycle  */
+  FDG_SOLVE_NO_AHEAD = 4      /* fdg_solve: do not queue Arnoldi steps ahead (same results)  */
 };
 
 typedef struct {
@@ -221,6 +222,9 @@ int fdg_matvec(fdg_ctx *ctx, const double *x, double *y);
  * classical Gram-Schmidt with one reorthogonalisation, Givens rotations in FP64 on the
  * host, x += Z y at its end and a true FP64 residual; converged iff
  * ||b - A x|| <= rtol ||b||.  With FDG_SOLVE_FIXED_ITERS exactly maxit iterations run.
+ * While the residual estimate is well above the target, the next Arnoldi step is queued
+ * before the host has read the current one (FDG_SOLVE_NO_AHEAD turns this off; the
+ * results are the same bits either way).
  * Blocks until done.  Returns FDG_OK, FDG_NOT_CONVERGED, or an error.
  * info may be NULL. */
 int fdg_solve(fdg_ctx *ctx, const double *b, double *x, double rtol, int restart,

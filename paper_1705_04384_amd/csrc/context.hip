@@ -879,7 +879,7 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   if (!c->phase_ev) HIPCHK(hipEventCreateWithFlags(&c->phase_ev, hipEventDisableTiming));
   SolveRun run;
   run.init(c, rb, restart, b, x, rtol, maxit, flags);
-  run.bank_stride = (size_t)host_doubles(restart);
+  if (!(flags & FDG_SOLVE_NO_AHEAD)) run.bank_stride = (size_t)host_doubles(restart);
   SolveRun *rp = &run;
   const Exec ex{c->stream, true};
   bool stream_idle = true;

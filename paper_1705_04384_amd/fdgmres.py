@@ -19,6 +19,7 @@ FDG_EFULL = -7
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 SOLVE_USE_X0 = 1
 SOLVE_FIXED_ITERS = 2
+SOLVE_NO_AHEAD = 4
 TIMER_APPLY, TIMER_MATVEC, TIMER_KRYLOV, TIMER_FIBRE = 0, 1, 2, 3
 
 _dp = ctypes.POINTER(ctypes.c_double)

@@ -145,6 +145,27 @@ def test_fixed_iterations_span_every_orthogonalization_form(k):
     ctx.close()
 
 
+@pytest.mark.parametrize("kind,p,n,restart,rtol", [("csr", 3, 12, 30, 1e-8), ("csr", 3, 10, 6, 1e-10),
+                                                    ("csr", 2, 9, 3, 1e-9), ("mapped", 3, 12, 30, 1e-8),
+                                                    ("mapped", 4, 9, 5, 1e-11)])
+def test_steps_queued_ahead_change_nothing(kind, p, n, restart, rtol):
+    # the single solve queues the next Arnoldi step before reading the current one; with
+    # that turned off the iterates, counts and residuals are the same bits
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.deformed_problem(p, n, 0.1) if kind == "csr" else fdg.mapped_problem(p, n, 0.1)
+    b = to_dev(inputs.rhs_uniform(inputs.SEED_DEFORMED_96, n ** 3))
+    xa = torch.empty_like(b)
+    xs = torch.empty_like(b)
+    ia = ctx.solve(b, xa, rtol=rtol, restart=restart)
+    is_ = ctx.solve(b, xs, rtol=rtol, restart=restart, flags=fdg.SOLVE_NO_AHEAD)
+    assert ia["converged"] and is_["converged"]
+    assert (ia["iterations"], ia["restarts"]) == (is_["iterations"], is_["restarts"])
+    assert ia["rel_res_true"] == is_["rel_res_true"] and ia["rel_res_est"] == is_["rel_res_est"]
+    assert np.array_equal(xa.cpu().numpy(), xs.cpu().numpy())
+    ctx.close()
+
+
 def test_solve_use_x0_and_zero_rhs():
     fdg = _fdg()
     torch = torch_cuda()
