@@ -227,7 +227,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab16(const TI *__restrict__ X,
 
 // Pass B: workgroup = (entry, block of kNB columns c of X[i3][c]); the block is staged
 // transposed in LDS (BF16), then T = Wa X, T /= lam3 + lam2 + lam1 (FP32), S = Wb T.
-template <int WAVES, int MT, int NT>
+template <int WAVES, int MT, int NT, bool VEC>
 __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict__ X, float *__restrict__ Y,
                                                         const __bf16 *__restrict__ Wa, const __bf16 *__restrict__ Wb,
                                                         int ldw, int n, int ncb, const float *__restrict__ lam1,
@@ -248,10 +248,22 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 31) & ~31;
-  for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
-    const int i3 = e / kNB, c = e % kNB;
-    const int64_t cg = c0 + c;
-    xt[c * LDP + i3] = to_bf16((i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0f);
+  if (VEC) {  // n^2 % 4 == 0 and a 16-byte aligned X: four columns per load
+    constexpr int Q = kNB / 4;
+    for (int e = threadIdx.x; e < kpad * Q; e += NTHR) {
+      const int i3 = e / Q, q = e - i3 * Q;
+      const int64_t cg = c0 + 4 * q;
+      flt4 v = flt4{0.f, 0.f, 0.f, 0.f};
+      if (i3 < n && cg < n2) v = *reinterpret_cast<const flt4 *>(Xb + (int64_t)i3 * n2 + cg);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = to_bf16(v[t]);
+    }
+  } else {
+    for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
+      const int i3 = e / kNB, c = e % kNB;
+      const int64_t cg = c0 + c;
+      xt[c * LDP + i3] = to_bf16((i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0f);
+    }
   }
   __syncthreads();
   flt4 acc[MT][NT];
@@ -352,11 +364,16 @@ void fibre16_dispatch(hipStream_t s, const float *X, float *Y, const __bf16 *Wa,
                       int64_t batch, const float *lam1, const float *lam2, const float *lam3) {
   const Shape16 sh = pick_shape16(n, false);
   const int64_t n2 = (int64_t)n * n;
+  const bool vec = n2 % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
 #define FDG_CASE(W, M, T)                                                                                         \
   if (sh.waves == W && sh.mt == M && sh.nt == T) {                                                               \
     const int ncb = (int)((n2 + 16 * T - 1) / (16 * T));                                                         \
-    hipLaunchKernelGGL((k_fibre16<W, M, T>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, Wa, Wb, ldw, \
-                       n, ncb, lam1, lam2, lam3);                                                                \
+    if (vec)                                                                                                     \
+      hipLaunchKernelGGL((k_fibre16<W, M, T, true>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, Wa, Wb,  \
+                         ldw, n, ncb, lam1, lam2, lam3);                                                         \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_fibre16<W, M, T, false>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, Wa, Wb, \
+                         ldw, n, ncb, lam1, lam2, lam3);                                                         \
     return;                                                                                                      \
   }
   FDG_SHAPES16(FDG_CASE)
