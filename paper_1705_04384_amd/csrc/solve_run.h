@@ -3,11 +3,12 @@
 // A solve alternates between a phase of device work (kernels enqueued on a stream) and a
 // host step that reads the few scalars the phase left in host-mapped memory (Hessenberg
 // column, norms), updates the Givens least-squares problem in FP64 and chooses the next
-// phase.  The single-solve entry point drives one run with a stream synchronisation per
-// phase; the request server drives many runs, and launches the phases of runs that share
-// a context and a step mask together (gathered batch entries).  Both use the same
-// kernels with the same per-entry reduction order, so a solve gives the same bits alone
-// or inside any mix.
+// phase.  The single-solve entry point drives one run: it polls the phase's host-mapped
+// slots (armed before the launch) rather than the stream, and may queue the next Arnoldi
+// step before reading the current one (two banks of slots).  The request server drives
+// many runs, one bank each, and launches the phases of runs that share a context and a
+// step mask together (gathered batch entries).  Both use the same kernels with the same
+// per-entry reduction order, so a solve gives the same bits alone or inside any mix.
 #pragma once
 
 #include <chrono>
