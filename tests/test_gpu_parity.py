@@ -61,6 +61,27 @@ def test_kron_matvec(d, p, n, batch):
         assert relerr(got[k * N:(k + 1) * N], P @ x[k * N:(k + 1) * N]) <= 1e-13
     ctx.close()
 
+@pytest.mark.parametrize("p,n,batch", [(4, 70, 2), (3, 131, 1), (6, 67, 1), (2, 66, 1), (4, 5, 3)])
+def test_kron_matvec_tiles_and_tails(p, n, batch):
+    """One-pass 3D matvec over several 64-column tiles, i2 row pairs and i3 chunks with
+    ragged tails (n = 70, 131, 67, 66), bands of 3 to 7 taps (p = 2 .. 6) and a tensor
+    smaller than one tile; against the oracle's sum-factorised product."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.unit_problem(3, p, n, batch=batch)
+    N = n ** 3
+    x = np.concatenate([inputs.rhs_normal(300 + k, N) for k in range(batch)])
+    y = torch.empty(batch * N, dtype=torch.float64, device="cuda")
+    ctx.matvec(to_dev(x), y)
+    torch.cuda.synchronize()
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    got = y.cpu().numpy()
+    for k in range(batch):
+        ref = colloc.unit_matvec([M] * 3, [K] * 3, x[k * N:(k + 1) * N])
+        assert relerr(got[k * N:(k + 1) * N], ref) <= 1e-13, (p, n, k)
+    ctx.close()
+
+
 
 @pytest.mark.parametrize("p,n,band", [(3, 12, False), (4, 9, False), (3, 8, True)])
 def test_csr_matvec_deformed(p, n, band):
