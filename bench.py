@@ -16,7 +16,7 @@ factor cache and (0.8x) a cold one.
 
 Extra fields: the P^{-1} apply rate (algorithmic 12 n^4 flops per apply), the roofline
 of the dominant kernel (the FP64 MFMA slab pass, two mode products of 2 n^4 flops per
-launch) from HIP events recorded by the dispatches of its launches during every 4th step
+launch) from HIP events recorded by the dispatches of its launches during every 16th step
 of the timed region, its HBM traffic from the committed counter summary, and the oracle
 (CPU, FP64) timed on a bounded sample.
 """
@@ -35,7 +35,7 @@ PEAK_FP64_TFLOPS = 78.6
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--p", type=int, default=4)
@@ -499,7 +499,7 @@ def main():
     # FD kernel timing (HIP events recorded by the kernels' dispatches) during every
     # TIMED_EVERY-th step of the timed region: a timed dispatch leaves a few microseconds
     # of idle queue around it, which would otherwise inflate every step
-    timed_every = 4
+    timed_every = 16
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
