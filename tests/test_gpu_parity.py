@@ -206,6 +206,29 @@ def test_solve_use_x0_and_zero_rhs():
     ctx.close()
 
 
+@pytest.mark.parametrize("p,n", [(4, 70), (3, 131), (6, 67)])
+def test_true_residual_of_a_start_guess(p, n):
+    """maxit = 0 from a start guess: the solve only forms r = b - A x0 (the one-pass
+    matvec with the residual fused, its per-workgroup partials of |r|^2 summed on the
+    host) over several tiles with ragged tails; the reported |r| / |b| against the
+    oracle's product, and x0 left as it was."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.unit_problem(3, p, n)
+    N = n ** 3
+    b = inputs.rhs_normal(400, N)
+    x0 = inputs.rhs_normal(401, N)
+    x = to_dev(x0).clone()
+    info = ctx.solve(to_dev(b), x, rtol=1e-8, maxit=0, flags=fdg.SOLVE_USE_X0)
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    r = b - colloc.unit_matvec([M] * 3, [K] * 3, x0)
+    ref = np.linalg.norm(r) / np.linalg.norm(b)
+    assert info["iterations"] == 0 and not info["converged"]
+    assert abs(info["rel_res_true"] - ref) <= 1e-13 * ref, (info["rel_res_true"], ref)
+    assert np.array_equal(x.cpu().numpy(), x0)
+    ctx.close()
+
+
 def test_not_converged_status():
     fdg = _fdg()
     torch = torch_cuda()
