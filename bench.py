@@ -470,7 +470,7 @@ def main():
         print(json.dumps(oracle_timing()), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
