@@ -1,4 +1,5 @@
 """Builds libfdgmres.so (HIP for gfx950 + host C++) in-tree next to this file."""
+import concurrent.futures
 import glob
 import os
 import shutil
@@ -8,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfdgmres.so")
+OBJ = os.path.join(ROOT, "_build")
 
 
 def sources():
@@ -15,22 +17,48 @@ def sources():
     return sorted(glob.glob(os.path.join(csrc, "*.cpp"))) + sorted(glob.glob(os.path.join(csrc, "*.hip")))
 
 
-def build(verbose=False):
-    """Compile every source into libfdgmres.so (always recompiles)."""
-    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+def _hipcc():
+    return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+def compile_flags():
+    return ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+            # no packed-FP32 instructions in device code
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-command-line-argument",
+            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+
+
+def _compile(src, verbose):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    cmd = [_hipcc()] + compile_flags() + ["-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    return obj, res
+
+
+def build(verbose=False, jobs=None):
+    """Compile every source (always; one process per source, in parallel) and link
+    libfdgmres.so."""
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or max(1, min(8, os.cpu_count() or 1, len(srcs)))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as pool:
+        results = list(pool.map(lambda s: _compile(s, verbose), srcs))
+    failed = [(o, r) for o, r in results if r.returncode != 0]
+    for _, r in failed:
+        sys.stderr.write(r.stdout + r.stderr)
+    if failed:
+        raise RuntimeError("hipcc failed on " + ", ".join(os.path.basename(o) for o, _ in failed))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
-           # no packed-FP32 instructions in device code
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", tmp] + sources()
+    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + [o for o, _ in results]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfdgmres.so")
+        raise RuntimeError("hipcc failed linking libfdgmres.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -232,13 +232,24 @@ def footprint_bytes(d, n, batch=1, prec=PREC_FP64, restart=30):
 _torch = None
 
 
-def _dev_ptr(t):
+def _dev_ptr(t, numel, device):
+    """Device address of t after checking that it is a contiguous float64 tensor of exactly
+    numel elements on CUDA device index `device` (the C ABI takes bare pointers, so an
+    undersized or foreign tensor would be read or written out of bounds)."""
     global _torch
     if _torch is None:
         import torch
         _torch = torch
-    if not isinstance(t, _torch.Tensor) or not t.is_cuda or t.dtype != _torch.float64 or not t.is_contiguous():
-        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if not isinstance(t, _torch.Tensor):
+        raise ValueError("expected a torch tensor")
+    if t.dtype != _torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 tensor")
+    if t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    if not t.is_cuda:
+        raise ValueError("expected a CUDA tensor")
+    if t.device.index != device:
+        raise ValueError(f"tensor on cuda:{t.device.index}, context on cuda:{device}")
     return t.data_ptr()
 
 
@@ -252,6 +263,7 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.device = torch.cuda.current_device()
         h = ctypes.c_void_p()
         dims = (ctypes.c_int32 * 3)(n, n, n)
         _check(lib().fdg_create(ctypes.byref(h), d, dims, batch, ctypes.c_void_p(stream.cuda_stream)))
@@ -306,15 +318,19 @@ class Context:
         coef = np.ascontiguousarray(coef, dtype=np.float64).ravel()
         _check(lib().fdg_set_operator_fields(self._h, _ptr(coef)))
 
+    def _vec(self, t):
+        """Pointer of a batch*N vector of this context."""
+        return _dev_ptr(t, self.N * self.batch, self.device)
+
     def apply_prec(self, b, s):
-        _check(lib().fdg_apply_prec(self._h, _dev_ptr(b), _dev_ptr(s)))
+        _check(lib().fdg_apply_prec(self._h, self._vec(b), self._vec(s)))
 
     def matvec(self, x, y):
-        _check(lib().fdg_matvec(self._h, _dev_ptr(x), _dev_ptr(y)))
+        _check(lib().fdg_matvec(self._h, self._vec(x), self._vec(y)))
 
     def solve(self, b, x, rtol=1e-8, restart=30, maxit=1000, flags=0):
         info = fdg_info()
-        st = _lib.fdg_solve(self._h, _dev_ptr(b), _dev_ptr(x), rtol, restart, maxit, flags, ctypes.byref(info))
+        st = _lib.fdg_solve(self._h, self._vec(b), self._vec(x), rtol, restart, maxit, flags, ctypes.byref(info))
         if st != FDG_OK and st != FDG_NOT_CONVERGED:
             _check(st)
         return {"iterations": info.iterations, "restarts": info.restarts, "converged": info.converged,
@@ -328,7 +344,7 @@ class Context:
     def bicgstab(self, b, x, rtol=1e-8, maxit=1000, flags=0):
         """Preconditioned BiCGStab; "iterations" is the paper's count (k or k + 0.5)."""
         info = fdg_info()
-        st = _lib.fdg_bicgstab(self._h, _dev_ptr(b), _dev_ptr(x), rtol, maxit, flags, ctypes.byref(info))
+        st = _lib.fdg_bicgstab(self._h, self._vec(b), self._vec(x), rtol, maxit, flags, ctypes.byref(info))
         if st != FDG_OK and st != FDG_NOT_CONVERGED:
             _check(st)
         return {"iterations": info.half_steps / 2.0, "full_iterations": info.iterations,
@@ -354,6 +370,9 @@ class Server:
         self.restart = restart
         self._cap = max_slots
         self._done = (fdg_done * max_slots)()
+        # b and x of every request in flight, by tag: the server writes x (and reads b)
+        # until the request completes, so their memory must not return to torch's allocator
+        self._held = {}
 
     def close(self):
         if self._h:
@@ -371,8 +390,12 @@ class Server:
 
     def admit(self, ctx, b, x, rtol=1e-8, maxit=1000, flags=0, tag=0):
         """True when admitted, False when no slot or arena space is free (FDG_EFULL)."""
-        st = lib().fdg_server_admit(self._h, ctx._h, _dev_ptr(b), _dev_ptr(x), rtol, maxit, flags, tag)
+        if ctx.batch != 1:
+            raise ValueError("served requests need a context with batch 1")
+        st = lib().fdg_server_admit(self._h, ctx._h, ctx._vec(b), ctx._vec(x), rtol, maxit, flags, tag)
         _check(st, allow=(FDG_OK, FDG_EFULL))
+        if st == FDG_OK:
+            self._held.setdefault(tag, []).append((b, x))
         return st == FDG_OK
 
     def step(self, wait_us=0):
@@ -382,6 +405,11 @@ class Server:
         out = []
         for k in range(nd.value):
             d = self._done[k]
+            held = self._held.get(d.tag)
+            if held:
+                held.pop(0)
+                if not held:
+                    del self._held[d.tag]
             out.append((d.tag, d.status, {f: getattr(d.info, f) for f, _ in fdg_info._fields_}))
         return out
 

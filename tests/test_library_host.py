@@ -251,3 +251,21 @@ def test_galerkin_csr_sizes_and_symmetric_diffusion():
     assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
     assert A.nnz == len(col) and rowptr[-1] == len(col)
     assert np.all(np.diff(rowptr) >= (p + 1) ** 3)
+
+
+def test_device_vector_checks_reject_wrong_tensors():
+    """The binding passes bare pointers to the C ABI, so it checks every device vector
+    first: dtype, contiguity and the exact element count come before the device checks,
+    so they are caught without a GPU."""
+    torch = pytest.importorskip("torch")
+    ok = torch.zeros(12, dtype=torch.float64)
+    with pytest.raises(ValueError, match="elements"):
+        fdg._dev_ptr(torch.zeros(11, dtype=torch.float64), 12, 0)
+    with pytest.raises(ValueError, match="float64"):
+        fdg._dev_ptr(torch.zeros(12, dtype=torch.float32), 12, 0)
+    with pytest.raises(ValueError, match="float64"):
+        fdg._dev_ptr(torch.zeros(24, dtype=torch.float64)[::2], 12, 0)
+    with pytest.raises(ValueError, match="torch tensor"):
+        fdg._dev_ptr(np.zeros(12), 12, 0)
+    with pytest.raises(ValueError, match="CUDA"):
+        fdg._dev_ptr(ok, 12, 0)
