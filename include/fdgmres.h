@@ -214,6 +214,25 @@ int fdg_deformed_coefficients(int p, int n, double amp, double *coef);
 /* s = P^{-1} b (eq. 4.7 / 4.9) for every batch entry.  b, s: device, batch*N FP64. */
 int fdg_apply_prec(fdg_ctx *ctx, const double *b, double *s);
 
+/* Device bytes of the scratch array fdg_apply_prec_noalloc uses on each device. */
+#define FDG_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): s = P^{-1} b exactly as
+ * fdg_apply_prec (same kernels, same bits), with the intermediates between the FD
+ * passes held in a file-scope device array of FDG_NOALLOC_SCRATCH_BYTES that every
+ * device holds until the process ends, instead of the context's own workspace.  The
+ * call allocates nothing (no hipMalloc, no events) and records no kernel timers.
+ * Limit: two intermediates of batch*N doubles (FDG_PREC_FP64, or pencils with complex
+ * pairs) or floats (FP32, BF16), each rounded up to 256 bytes plus 256 bytes of slack,
+ * must fit in the array: batch*N <= 8388576 in FP64, <= 16777152 otherwise; larger
+ * shapes fail with FDG_EINVAL and launch nothing.  All calls on one device share that
+ * device's array: calls that overlap in time on one device (different streams, or
+ * different host threads) race and must be serialized by the caller.  b, s: device,
+ * batch*N FP64.  Errors as fdg_apply_prec, and FDG_EHIP if the array could not be
+ * located on the device when the context was created. */
+int fdg_apply_prec_noalloc(fdg_ctx *ctx, const double *b, double *s);
+
 /* y = A x for every batch entry.  x, y: device, batch*N FP64. */
 int fdg_matvec(fdg_ctx *ctx, const double *x, double *y);
 

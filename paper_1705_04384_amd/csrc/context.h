@@ -182,6 +182,11 @@ int residual_entries(fdg_ctx *c, const Exec &ex, CBatch x, CBatch b, MBatch r, i
 int residual_partials(const fdg_ctx *c);
 // FDG_OK when the preconditioner factors and the operator are set, else FDG_ENOTREADY.
 int ctx_ready(fdg_ctx *c);
+// FDG_OK when the preconditioner factors of every direction are set, else FDG_ENOTREADY.
+int ctx_ready_prec(fdg_ctx *c);
+// Device address of the no-allocation apply's scratch array on device dev (current),
+// looked up once per device; called when a context is created.
+int scratch_setup(int dev);
 // Some direction's pencil has complex eigenvalue pairs (block-diagonal D).
 bool ctx_has_pairs(const fdg_ctx *c);
 // Apply/matvec scratch t1, t2 (and t32a, t32b for a reduced-precision context).

@@ -86,6 +86,8 @@ int ctx_ready(fdg_ctx *c) {
   return st;
 }
 
+int ctx_ready_prec(fdg_ctx *c) { return check_ready_prec(c); }
+
 int ensure_solve_workspace(fdg_ctx *c) {
   int st = ensure_workspace(c);
   if (st == FDG_OK && c->prec != FDG_PREC_FP64) st = ensure_lowp_workspace(c);
@@ -411,6 +413,10 @@ extern "C" int fdg_create(fdg_ctx **out, int d, const int32_t *n, int batch, voi
   int dev = 0;
   int st = hip_check(hipGetDevice(&dev), "hipGetDevice");
   if (st != FDG_OK) return st;
+  // set-up of the no-allocation apply on this device (once per device); a failure is
+  // reported by that entry point, not here
+  (void)scratch_setup(dev);
+  clear_error();
   fdg_ctx *c = new fdg_ctx();
   c->d = d;
   c->n = n[0];

@@ -54,7 +54,7 @@ EXPORTS = [
     "fdg_server_pending", "fdg_server_stats", "fdg_set_operator_mapped", "fdg_set_operator_fields",
     "fdg_deformed_coefficients", "fdg_factor_pencil_sym", "fdg_galerkin_factors", "fdg_galerkin_csr",
     "fdg_set_prec_factors_sym", "fdg_bicgstab", "fdg_operator_bytes", "fdg_factor_pencil_blocks",
-    "fdg_set_prec_factors_blocks",
+    "fdg_set_prec_factors_blocks", "fdg_apply_prec_noalloc",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
     L.fdg_set_operator_kron.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     L.fdg_set_operator_csr.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _dp]
     L.fdg_apply_prec.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.fdg_apply_prec_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.fdg_matvec.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     L.fdg_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(fdg_info)]
@@ -324,6 +325,11 @@ class Context:
 
     def apply_prec(self, b, s):
         _check(lib().fdg_apply_prec(self._h, self._vec(b), self._vec(s)))
+
+    def apply_prec_noalloc(self, b, s):
+        """fdg_apply_prec_noalloc: the same result, intermediates in the library's static
+        device scratch array (nothing allocated)."""
+        _check(lib().fdg_apply_prec_noalloc(self._h, self._vec(b), self._vec(s)))
 
     def matvec(self, x, y):
         _check(lib().fdg_matvec(self._h, self._vec(x), self._vec(y)))
