@@ -9,6 +9,7 @@
 #include <cstring>
 #include <vector>
 
+#include "bf16_round.h"
 #include "common.h"
 #include "context.h"
 #include "fd_apply.h"
@@ -25,15 +26,6 @@ bool finite_all(const double *a, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(a[i])) return false;
   return true;
-}
-
-uint16_t to_bf16_rne(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan kept
-  const uint32_t lsb = (u >> 16) & 1u;
-  u += 0x7fffu + lsb;
-  return (uint16_t)(u >> 16);
 }
 
 int ensure_workspace(fdg_ctx *c) {
@@ -522,8 +514,8 @@ extern "C" int fdg_set_prec_factors(fdg_ctx *c, int l, const double *U, const do
   for (size_t i = 0; i < wv.size(); ++i) {
     fv[i] = (float)wv[i];
     fu[i] = (float)wu[i];
-    bv[i] = to_bf16_rne((float)wv[i]);
-    bu[i] = to_bf16_rne((float)wu[i]);
+    bv[i] = bf16_bits_from_f64(wv[i]);
+    bu[i] = bf16_bits_from_f64(wu[i]);
   }
   for (size_t i = 0; i < lm.size(); ++i) fl[i] = (float)lm[i];
   if ((st = dalloc(&c->Wv32[l], fv.size())) != FDG_OK) return st;

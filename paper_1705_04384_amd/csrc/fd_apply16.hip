@@ -16,6 +16,7 @@
 #include <cstdint>
 #include <cstring>
 
+#include "bf16_round.h"
 #include "fd_apply.h"
 
 namespace fdg {
@@ -27,16 +28,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kPadB = 8;  // LDS row padding (BF16 elements: rows stay 16-byte aligned)
 
-// Round to nearest even; infinities and NaNs keep their class.
-__device__ inline __bf16 to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
-  const uint16_t h = (uint16_t)(u >> 16);
-  __bf16 r;
-  __builtin_memcpy(&r, &h, 2);
-  return r;
-}
-
 __device__ inline flt4 mfma16(const bf16x8 &a, const bf16x8 &b, flt4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
@@ -46,7 +37,7 @@ template <typename T>
 __device__ inline bf16x8 load8(const T *p, int j, int jmax, bool ok) {
   bf16x8 v;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) v[t] = to_bf16((ok && j + t < jmax) ? (float)p[t] : 0.0f);
+  for (int t = 0; t < 8; ++t) v[t] = to_bf16_once((ok && j + t < jmax) ? p[t] : T(0));
   return v;
 }
 
@@ -62,15 +53,15 @@ __device__ inline bf16x8 load8v(const T *p, int j, int jmax, bool ok) {
       const dbl4 x0 = *reinterpret_cast<const dbl4 *>(p), x1 = *reinterpret_cast<const dbl4 *>(p + 4);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        v[t] = to_bf16((float)x0[t]);
-        v[4 + t] = to_bf16((float)x1[t]);
+        v[t] = to_bf16_once(x0[t]);
+        v[4 + t] = to_bf16_once(x1[t]);
       }
     } else {
       const flt4 x0 = *reinterpret_cast<const flt4 *>(p), x1 = *reinterpret_cast<const flt4 *>(p + 4);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        v[t] = to_bf16(x0[t]);
-        v[4 + t] = to_bf16(x1[t]);
+        v[t] = to_bf16_once(x0[t]);
+        v[4 + t] = to_bf16_once(x1[t]);
       }
     }
     return v;
@@ -198,7 +189,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab16(const TI *__restrict__ X,
 #pragma unroll
     for (int b = 0; b < NT; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + 4 * lg + r] = to_bf16(acc[a][b][r]);
+      for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + 4 * lg + r] = to_bf16_once(acc[a][b][r]);
   __syncthreads();
   gemm16<MT, NT>(kpad, [&](int j0, Frag16<MT, NT> &f) {
     const int j = j0 + 8 * lg;
@@ -256,13 +247,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
       flt4 v = flt4{0.f, 0.f, 0.f, 0.f};
       if (i3 < n && cg < n2) v = *reinterpret_cast<const flt4 *>(Xb + (int64_t)i3 * n2 + cg);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = to_bf16(v[t]);
+      for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = to_bf16_once(v[t]);
     }
   } else {
     for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
       const int i3 = e / kNB, c = e % kNB;
       const int64_t cg = c0 + c;
-      xt[c * LDP + i3] = to_bf16((i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0f);
+      xt[c * LDP + i3] = to_bf16_once((i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0f);
     }
   }
   __syncthreads();
@@ -290,7 +281,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
       for (int r = 0; r < 4; ++r) {
         const int k3 = m0 + 16 * a + 4 * lg + r;
         // rows k3 >= n are zero (zero-padded Wa); lam3 is padded with 1
-        xt[(16 * b + li) * LDP + k3] = to_bf16(acc[a][b][r] / (lam3[k3] + l12));
+        xt[(16 * b + li) * LDP + k3] = to_bf16_once(acc[a][b][r] / (lam3[k3] + l12));
       }
   }
   __syncthreads();

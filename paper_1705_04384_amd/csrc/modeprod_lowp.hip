@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstring>
 
+#include "bf16_round.h"
 #include "common.h"
 #include "modeprod.h"
 
@@ -21,15 +22,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 namespace {
 
 constexpr int kBlock = 256;
-
-__device__ inline __bf16 bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
-  const uint16_t h = (uint16_t)(u >> 16);
-  __bf16 r;
-  __builtin_memcpy(&r, &h, 2);
-  return r;
-}
 
 template <typename T>
 __device__ inline float ld_f(const T *p) { return (float)*p; }
@@ -105,8 +97,8 @@ __global__ __launch_bounds__(kBlock) void k_modeprod_bf16(const TIn *__restrict_
       const bool jok = j < n;
       a0[t] = Wr0[j];
       a1[t] = Wr1[j];
-      b0[t] = bf16_rne((jok && okA) ? ld_f(Xo + j * sJ + cA * sC) : 0.f);
-      b1[t] = bf16_rne((jok && okB) ? ld_f(Xo + j * sJ + cB * sC) : 0.f);
+      b0[t] = to_bf16_once((jok && okA) ? Xo[j * sJ + cA * sC] : TIn(0));
+      b1[t] = to_bf16_once((jok && okB) ? Xo[j * sJ + cB * sC] : TIn(0));
     }
     acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
     acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
@@ -131,8 +123,8 @@ __global__ __launch_bounds__(kBlock) void k_divide_f32(float *__restrict__ t, in
   if (idx >= total) return;
   const int i1 = (int)(idx % n);
   const int i2 = (int)((idx / n) % n);
-  float den = l1[i1] + l2[i2];
-  if (d == 3) den += l3[(idx / ((int64_t)n * n)) % n];
+  float den = l2[i2] + l1[i1];
+  if (d == 3) den = l3[(idx / ((int64_t)n * n)) % n] + den;
   t[idx] = t[idx] / den;
 }
 
@@ -186,15 +178,18 @@ int fd_apply_lowp(hipStream_t s, int prec, int d, int n, int64_t B, const double
   // stage 2: diagonal solve
   hipLaunchKernelGGL(k_divide_f32, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cur, d, n, N,
                      lam[0], lam[1], d == 3 ? lam[2] : lam[1]);
-  // stage 3: (U_d x .. x U_1)
-  q = g(0);
-  modeprod<float, float>(s, prec, cur, oth, Wu[0], ldw, n, q.ncols, q.sO, q.sJ, q.sC, q.nb);
+  // stage 3: (U_d x .. x U_1), in 3D in the order of the fused passes (direction 3, then
+  // 1 and 2), so that the roundings between the products fall at the same points
   if (d == 3) {
-    q = g(1);
-    modeprod<float, float>(s, prec, oth, cur, Wu[1], ldw, n, q.ncols, q.sO, q.sJ, q.sC, q.nb);
     q = g(2);
-    modeprod<float, double>(s, prec, cur, out, Wu[2], ldw, n, q.ncols, q.sO, q.sJ, q.sC, q.nb);
+    modeprod<float, float>(s, prec, cur, oth, Wu[2], ldw, n, q.ncols, q.sO, q.sJ, q.sC, q.nb);
+    q = g(0);
+    modeprod<float, float>(s, prec, oth, cur, Wu[0], ldw, n, q.ncols, q.sO, q.sJ, q.sC, q.nb);
+    q = g(1);
+    modeprod<float, double>(s, prec, cur, out, Wu[1], ldw, n, q.ncols, q.sO, q.sJ, q.sC, q.nb);
   } else {
+    q = g(0);
+    modeprod<float, float>(s, prec, cur, oth, Wu[0], ldw, n, q.ncols, q.sO, q.sJ, q.sC, q.nb);
     q = g(1);
     modeprod<float, double>(s, prec, oth, out, Wu[1], ldw, n, q.ncols, q.sO, q.sJ, q.sC, q.nb);
   }

@@ -28,3 +28,9 @@ def oracle_unit(p, n, d):
 
 def relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def maxrel(a, b):
+    """Largest element-wise difference relative to the largest element of b."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

@@ -15,7 +15,7 @@ import pytest
 
 from oracle import colloc, fd, fgmres
 from paper_1705_04384_amd import inputs
-from tests.gpu_helpers import relerr, to_dev, torch_cuda
+from tests.gpu_helpers import maxrel, relerr, to_dev, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_c1_2d_p3_n33():
     mv, pr = _oracle_unit(p, n, d)
     xo, io = fgmres.fgmres(mv, pr, f, rtol=1e-8, restart=30)
     assert info["converged"] and info["iterations"] == io["iterations"]
-    assert relerr(x.cpu().numpy(), xo) <= 1e-8
+    assert relerr(x.cpu().numpy(), xo) <= 1e-8 and maxrel(x.cpu().numpy(), xo) <= 1e-8
     ctx.close()
 
 
@@ -64,7 +64,7 @@ def test_c2_3d_p4_n128(rhs):
     xo, io = fgmres.fgmres(mv, pr, f, rtol=1e-8, restart=30)
     assert info["converged"] and info["iterations"] == io["iterations"] == 1
     assert info["rel_res_true"] <= 1e-8
-    assert relerr(x.cpu().numpy(), xo) <= 1e-8
+    assert relerr(x.cpu().numpy(), xo) <= 1e-8 and maxrel(x.cpu().numpy(), xo) <= 1e-8
     ctx.close()
 
 
@@ -96,7 +96,9 @@ def test_c3_deformed_p3_n96():
     k = io["iterations"]
     xf = torch.empty(N, dtype=torch.float64, device="cuda")
     ctx.solve(to_dev(b), xf, rtol=1e-8, restart=restart, maxit=k, flags=fdg.SOLVE_FIXED_ITERS)
-    assert relerr(xf.cpu().numpy(), xo) <= 1e-8
+    assert relerr(xf.cpu().numpy(), xo) <= 1e-8 and maxrel(xf.cpu().numpy(), xo) <= 1e-8
+    # the free-running solve stops at the same iteration, so it is the same iterate
+    assert relerr(xg, xo) <= 1e-8 and maxrel(xg, xo) <= 1e-8
     ctx.close()
 
 
@@ -134,14 +136,15 @@ def test_c4_precision_sweep_p6_n192():
     ctx = fdg.unit_problem(d, p, n)
     info = ctx.solve(bd, x, rtol=1e-8, restart=50)
     assert info["converged"] and info["iterations"] == 1
-    assert relerr(x.cpu().numpy(), x_ref) <= 1e-8
+    assert relerr(x.cpu().numpy(), x_ref) <= 1e-8 and maxrel(x.cpu().numpy(), x_ref) <= 1e-8
     ctx.close()
-    for prec, kmax in ((fdg.PREC_FP32, 3), (fdg.PREC_BF16, 8)):
+    for prec, kmax in ((fdg.PREC_FP32, 4), (fdg.PREC_BF16, 10)):
         ctx = fdg.unit_problem(d, p, n, prec=prec)
         errs = []
         for k in range(1, kmax + 1):
             ctx.solve(bd, x, rtol=0.0, restart=50, maxit=k, flags=fdg.SOLVE_FIXED_ITERS)
-            errs.append(relerr(x.cpu().numpy(), x_ref))
+            xk = x.cpu().numpy()
+            errs.append(max(relerr(xk, x_ref), maxrel(xk, x_ref)))
             if errs[-1] <= 1e-8:
                 break
         assert errs[-1] <= 1e-8, (prec, errs)

@@ -1,0 +1,103 @@
+"""GPU parity of the reduced-precision preconditioner (FP32 and BF16 passes) against the
+oracle's reduced-precision FD solve (oracle/reduced.py), element by element.
+
+Both sides get the same FP64 factors (computed by the oracle and handed to the library
+through fdg_set_prec_factors), so they round the same numbers.  Three checks:
+* identity factors: the result is the input rounded once to the mode's precision
+  (FP64 -> BF16 directly, ties to even) and divided, bit for bit;
+* ternary factors on integer data: every product is exact in FP32, so the kernels must
+  reproduce the oracle's chain of roundings bit for bit, which also proves that the BF16
+  passes round where the definition says and that they are not FP32 passes;
+* collocation factors on N(0,1) data at ragged sizes: max-abs and 2-norm distance within
+  the tolerances that tests/test_oracle_reduced.py shows a different accumulation order
+  stays inside and planted mistakes do not.
+"""
+import numpy as np
+import pytest
+
+from oracle import fd, reduced
+from paper_1705_04384_amd import inputs
+from tests.gpu_helpers import to_dev, torch_cuda
+from tests.test_oracle_reduced import GPU_TOL, _bf16_textbook, _real_problem, _ternary_problem
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"fp32": 1, "bf16": 2}
+
+
+def _fdg():
+    torch_cuda()
+    from paper_1705_04384_amd import fdgmres
+    fdgmres.lib()
+    return fdgmres
+
+
+def _apply(d, n, Us, Vs, lams, b, mode, noalloc=False):
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.Context(d, n)
+    for l in range(d):
+        ctx.set_prec_factors(l, Us[l], Vs[l], lams[l])
+    ctx.set_precision(MODES[mode])
+    s = torch.full((n ** d,), float("nan"), dtype=torch.float64, device="cuda")
+    print(f"reduced apply d={d} n={n} mode={mode}", flush=True)
+    ctx.apply_prec(to_dev(b), s)
+    torch.cuda.synchronize()
+    ctx.close()
+    return s.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16"])
+@pytest.mark.parametrize("d,n", [(2, 40), (3, 33), (2, 300), (3, 260)])
+def test_identity_factors_round_the_input_once(mode, d, n):
+    """Fused passes (n <= 256) and unfused mode products (n > 256)."""
+    rng = np.random.default_rng(31)
+    N = n ** d
+    b = rng.standard_normal(N) * 10.0 ** rng.integers(-3, 4, N)
+    # values just off BF16 ties, where rounding through the nearest FP32 goes the wrong way
+    k = np.arange(min(N, 4096))
+    b[k] = (1.0 + (2 * (k % 64) + 1) * 2.0 ** -8 + ((-1.0) ** k) * 2.0 ** -40) * 2.0 ** (k % 9 - 4)
+    I = np.eye(n)
+    lams = [np.ones(n), np.ones(n), 2.0 * np.ones(n)][:d]
+    got = _apply(d, n, [I] * d, [I] * d, lams, b, mode)
+    rounded = reduced.bf16_from_fp64(b) if mode == "bf16" else reduced.fp32_from_fp64(b)
+    want = rounded.astype(np.float64) / (4.0 if d == 3 else 2.0)
+    assert np.array_equal(got, want), int(np.sum(got != want))
+    if N <= 100000:
+        textbook = _bf16_textbook(b) if mode == "bf16" else b.astype(np.float32).astype(np.float64)
+        assert np.array_equal(want, textbook / (4.0 if d == 3 else 2.0))
+        assert np.array_equal(got, reduced.fd_apply_reduced([I] * d, [I] * d, lams, b, mode))
+
+
+@pytest.mark.parametrize("d,n", [(2, 40), (2, 130), (3, 17), (3, 33), (3, 47), (3, 65), (3, 96), (2, 260), (2, 300)])
+def test_integer_chain_bit_for_bit(d, n):
+    Us, Vs, lams, b = _ternary_problem(d, n, 40 + n)
+    res = {}
+    for mode in ("fp32", "bf16"):
+        want = reduced.fd_apply_reduced(Us, Vs, lams, b, mode)
+        got = _apply(d, n, Us, Vs, lams, b, mode)
+        assert np.array_equal(got, want), (mode, int(np.sum(got != want)), float(np.max(np.abs(got - want))))
+        res[mode] = got
+    assert not np.array_equal(res["fp32"], res["bf16"])
+
+
+@pytest.mark.parametrize("d,p,n", [(3, 4, 40), (3, 3, 33), (3, 6, 65), (2, 4, 130), (2, 3, 47), (3, 5, 96),
+                                   (3, 4, 129), (3, 3, 200), (2, 2, 260)])
+def test_collocation_factors_elementwise(d, p, n):
+    Us, Vs, lams, b = _real_problem(d, p, n)
+    s64 = fd.fd_apply(Us, Vs, lams, b)
+    got = {}
+    for mode in ("fp32", "bf16"):
+        want = reduced.fd_apply_reduced(Us, Vs, lams, b, mode)
+        g = _apply(d, n, Us, Vs, lams, b, mode)
+        assert np.all(np.isfinite(g))
+        mx = np.max(np.abs(g - want)) / np.max(np.abs(want))
+        nm = np.linalg.norm(g - want) / np.linalg.norm(want)
+        assert mx <= GPU_TOL[mode][0] and nm <= GPU_TOL[mode][1], (mode, mx, nm)
+        got[mode] = g
+    # the BF16 result differs from the FP32 one by about what the BF16 roundings make of it
+    e_emul = np.linalg.norm(reduced.fd_apply_reduced(Us, Vs, lams, b, "bf16") - s64) / np.linalg.norm(s64)
+    e_gpu = np.linalg.norm(got["bf16"] - s64) / np.linalg.norm(s64)
+    assert 0.7 * e_emul <= e_gpu <= 1.3 * e_emul, (e_gpu, e_emul)
+    d16_32 = np.linalg.norm(got["bf16"] - got["fp32"]) / np.linalg.norm(got["fp32"])
+    assert d16_32 > 0.5 * e_emul

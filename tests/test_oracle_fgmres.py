@@ -94,3 +94,37 @@ def test_iterations_nearly_flat_in_h_and_p():
             its[(p, n)] = info["iterations"]
     assert max(its.values()) <= 40
     assert max(its.values()) <= 2 * min(its.values())
+
+
+@pytest.mark.parametrize("k,m", [(12, 5), (7, 7), (9, 4), (20, 6)])
+def test_fixed_count_iterate_is_the_restarted_minimal_residual_iterate(k, m):
+    """The fixed-count mode (iters=k), the reference of every fixed-count GPU comparison,
+    against its definition computed another way: each cycle of restarted, right-
+    preconditioned GMRES minimises ||b - A x|| over x_c + P^{-1} K_s(A P^{-1}, r_c)
+    (s = m, the last cycle shorter), here by a dense least-squares solve over an explicit
+    (normalised power) basis of that Krylov space, on a small deformed-cube system."""
+    from paper_1705_04384_amd import inputs
+    p, n = 3, 6
+    A = colloc.deformed_operator(p, n, 0.1).toarray()
+    _, _, prec = _fd(p, n, 3)
+    b = inputs.rhs_uniform(5, n ** 3)
+    xo, info = fgmres.fgmres(lambda v: A @ v, prec, b, restart=m, iters=k)
+    assert info["iterations"] == k and info["restarts"] == -(-k // m)
+    x = np.zeros(n ** 3)
+    done = 0
+    while done < k:
+        s = min(m, k - done)
+        r = b - A @ x
+        cols = [r / np.linalg.norm(r)]
+        for _ in range(1, s):
+            w = A @ prec(cols[-1])
+            cols.append(w / np.linalg.norm(w))
+        Z = np.column_stack([prec(c) for c in cols])
+        c, *_ = np.linalg.lstsq(A @ Z, r, rcond=None)
+        x = x + Z @ c
+        done += s
+    assert np.linalg.norm(x - xo) <= 1e-11 * np.linalg.norm(x)
+    assert np.max(np.abs(x - xo)) <= 1e-11 * np.max(np.abs(x))
+    # and the agreement is sharp: one step fewer is far further away
+    xk1, _ = fgmres.fgmres(lambda v: A @ v, prec, b, restart=m, iters=k - 1)
+    assert np.linalg.norm(xk1 - xo) > 100 * np.linalg.norm(x - xo)
