@@ -116,6 +116,17 @@ def serving(count):
     return out
 
 
+def err_vs(x, ref):
+    """Relative 2-norm and max-abs error of a device solution against an oracle solution
+    (None without one)."""
+    if ref is None:
+        return None
+    import numpy as np
+    xg = x.detach().cpu().numpy()
+    return {"rel_2norm": float(np.linalg.norm(xg - ref) / np.linalg.norm(ref)),
+            "max_abs_rel": float(np.max(np.abs(xg - ref)) / np.max(np.abs(ref)))}
+
+
 def timed_solves(ctx, b, x, reps, **kw):
     """Average wall time of reps solves (no kernel timers: a timed dispatch idles the queue
     around it), then the per-class kernel time (HIP events) over another reps solves."""
@@ -152,12 +163,34 @@ def timed_bicgstab(ctx, b, x, reps, **kw):
     return _timed(ctx.bicgstab, ctx, b, x, reps, **kw)
 
 
-def deformed_96():
-    """Deformed cube, p = 3, n = 96: CSR operator (27 nnz per row), FD preconditioner."""
+def k_star_search(ctx, b, x, ref, restart, k_from, k_to):
+    """Smallest fixed FGMRES iteration count k in [k_from, k_to] whose iterate is within
+    1e-8 (relative 2-norm) of the reference solution, and that error; (None, last error)
+    when none is."""
+    import torch
+    from paper_1705_04384_amd import fdgmres
+    refd = torch.from_numpy(ref).cuda()
+    nref = float(torch.linalg.norm(refd))
+    err = None
+    for k in range(k_from, k_to + 1):
+        ctx.solve(b, x, rtol=0.0, restart=restart, maxit=k, flags=fdgmres.SOLVE_FIXED_ITERS)
+        err = float(torch.linalg.norm(x - refd)) / nref
+        if err <= 1e-8:
+            return k, err
+    return None, err
+
+
+def deformed_96(refs):
+    """Deformed cube, p = 3, n = 96: CSR operator (27 nnz per row), FD preconditioner in
+    FP64, FP32 and BF16, the operator also matrix-free; each solve's error against the
+    oracle's solution (FP64 FGMRES to rtol 1e-8), and, at equal accuracy, the iteration
+    count k* at which each precision's iterate is within 1e-8 of a tight oracle solve
+    (rtol 1e-12) with the time of that many iterations."""
     import torch
     from paper_1705_04384_amd import fdgmres, inputs
     p, n = 3, 96
     N = n ** 3
+    ref, tight = refs.get("deformed_96"), refs.get("deformed_96_tight")
     t = time.perf_counter()
     ctx = fdgmres.deformed_problem(p, n, 0.1)
     setup = time.perf_counter() - t
@@ -172,7 +205,8 @@ def deformed_96():
     out = {"workload": f"deformed cube (cyclic sin map, amplitude 0.1), p={p}, n={n} (N={N}), CSR {ctx.nnz} nnz "
                        "(27/row) on the device as slot-major values with implicit columns, U[-1,1] RHS, FGMRES(30) to rtol 1e-8, FP64",
            "solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": info["iterations"],
-           "restarts": info["restarts"], "rel_res_true": info["rel_res_true"], "setup_s": setup,
+           "restarts": info["restarts"], "rel_res_true": info["rel_res_true"], "err_vs_oracle": err_vs(x, ref),
+           "err_vs_tight_oracle": err_vs(x, tight), "setup_s": setup,
            "kernel_ms_per_solve": split,
            "spmv": {"avg_us": spmv_s * 1e6, "algorithmic_bytes": spmv_bytes,
                     "gbps": spmv_bytes / spmv_s / 1e9, "frac_hbm": spmv_bytes / spmv_s / 8e12}}
@@ -181,6 +215,7 @@ def deformed_96():
     dtb, infob, splitb = timed_bicgstab(ctx, b, x, 5, rtol=1e-8)
     out["bicgstab"] = {"solves_per_s": 1.0 / dtb, "ms_per_solve": dtb * 1e3, "iterations": infob["iterations"],
                        "preconditioner_applies": infob["half_steps"], "rel_res_true": infob["rel_res_true"],
+                       "err_vs_tight_oracle": err_vs(x, tight),
                        "fgmres_iterations": info["iterations"], "speedup_vs_fgmres": dt_csr / dtb,
                        "kernel_ms_per_solve": splitb}
     ctx.close()
@@ -196,41 +231,56 @@ def deformed_96():
     l_s = mvl["ms_per_solve"] / 1e3 / max(mvl["launches_per_solve"], 1)
     out["literal_343_stencil"] = {
         "nnz": lctx.nnz, "solves_per_s": 1.0 / dtl, "ms_per_solve": dtl * 1e3, "iterations": infol["iterations"],
-        "rel_res_true": infol["rel_res_true"], "setup_s": lsetup,
+        "rel_res_true": infol["rel_res_true"], "setup_s": lsetup, "err_vs_oracle": err_vs(x, ref),
         "x_rel_diff_vs_true_pattern": float(torch.linalg.norm(x - x_true) / torch.linalg.norm(x_true)),
         "kernel_ms_per_solve": splitl,
         "spmv": {"avg_us": l_s * 1e6, "algorithmic_bytes": l_bytes, "gbps": l_bytes / l_s / 1e9,
                  "frac_hbm": l_bytes / l_s / 8e12}}
     lctx.close()
-    # the same solve with the FD preconditioner in FP32 (fused FP32 MFMA passes)
-    ctx32 = fdgmres.deformed_problem(p, n, 0.1, prec=fdgmres.PREC_FP32)
-    dt32, info32, split32 = timed_solves(ctx32, b, x, 5, rtol=1e-8, restart=30)
-    out["fp32_preconditioner"] = {"solves_per_s": 1.0 / dt32, "ms_per_solve": dt32 * 1e3,
-                                  "iterations": info32["iterations"], "rel_res_true": info32["rel_res_true"],
-                                  "speedup_vs_fp64": dt_csr / dt32, "kernel_ms_per_solve": split32}
-    ctx32.close()
-    # the same operator applied matrix-free: 1D factors + 9 coefficient fields per point
-    t = time.perf_counter()
-    mctx = fdgmres.mapped_problem(p, n, 0.1)
-    msetup = time.perf_counter() - t
-    dt, info, split = timed_solves(mctx, b, x, 5, rtol=1e-8, restart=30)
-    mv = split["matvec"]
-    mf_bytes = mctx.operator_bytes() + 2 * N * 8  # 9 coefficient fields, x and y
-    mv_s = mv["ms_per_solve"] / 1e3 / max(mv["launches_per_solve"], 1)
-    out["matrix_free"] = {"solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "iterations": info["iterations"],
-                          "rel_res_true": info["rel_res_true"], "setup_s": msetup, "kernel_ms_per_solve": split,
-                          "matvec": {"avg_us": mv_s * 1e6, "algorithmic_bytes": mf_bytes,
-                                     "gbps": mf_bytes / mv_s / 1e9, "frac_hbm": mf_bytes / mv_s / 8e12}}
-    mctx.close()
-    # matrix-free operator and FP32 preconditioner together
-    mctx32 = fdgmres.mapped_problem(p, n, 0.1, prec=fdgmres.PREC_FP32)
-    dtm32, infom32, _ = timed_solves(mctx32, b, x, 5, rtol=1e-8, restart=30)
-    out["matrix_free_fp32_preconditioner"] = {"solves_per_s": 1.0 / dtm32, "ms_per_solve": dtm32 * 1e3,
-                                              "iterations": infom32["iterations"],
-                                              "rel_res_true": infom32["rel_res_true"],
-                                              "speedup_vs_csr_fp64": dt_csr / dtm32,
-                                              "speedup_vs_matrix_free_fp64": dt / dtm32}
-    mctx32.close()
+    # the same solve with the FD preconditioner in FP32 and in BF16 (FP32 accumulation), with
+    # the operator assembled (CSR) and matrix-free (1D factors + 9 coefficient fields)
+    for op in ("csr", "matrix_free"):
+        for name, prec in (("fp64", fdgmres.PREC_FP64), ("fp32", fdgmres.PREC_FP32), ("bf16", fdgmres.PREC_BF16)):
+            if op == "csr" and name == "fp64":
+                continue
+            t = time.perf_counter()
+            c = (fdgmres.deformed_problem(p, n, 0.1, prec=prec) if op == "csr"
+                 else fdgmres.mapped_problem(p, n, 0.1, prec=prec))
+            csetup = time.perf_counter() - t
+            dtc, infoc, splitc = timed_solves(c, b, x, 5, rtol=1e-8, restart=30)
+            key = f"{name}_preconditioner" if op == "csr" else f"matrix_free_{name}"
+            out[key] = {"solves_per_s": 1.0 / dtc, "ms_per_solve": dtc * 1e3, "iterations": infoc["iterations"],
+                        "rel_res_true": infoc["rel_res_true"], "err_vs_oracle": err_vs(x, ref),
+                        "err_vs_tight_oracle": err_vs(x, tight), "speedup_vs_csr_fp64": dt_csr / dtc,
+                        "setup_s": csetup, "kernel_ms_per_solve": splitc}
+            if op == "matrix_free" and name == "fp64":
+                mvm = splitc["matvec"]
+                mf_bytes = c.operator_bytes() + 2 * N * 8  # 9 coefficient fields, x and y
+                mv_s = mvm["ms_per_solve"] / 1e3 / max(mvm["launches_per_solve"], 1)
+                out[key]["matvec"] = {"avg_us": mv_s * 1e6, "algorithmic_bytes": mf_bytes,
+                                      "gbps": mf_bytes / mv_s / 1e9, "frac_hbm": mf_bytes / mv_s / 8e12}
+            c.close()
+    # equal accuracy: k* against the tight oracle solve, and the time of k* iterations
+    if tight is not None:
+        eq = {"reference": "oracle FGMRES(30) to rtol 1e-12; k* = fewest fixed iterations within 1e-8 of it"}
+        base_ms = None
+        for op in ("csr", "matrix_free"):
+            for name, prec in (("fp64", fdgmres.PREC_FP64), ("fp32", fdgmres.PREC_FP32),
+                               ("bf16", fdgmres.PREC_BF16)):
+                c = (fdgmres.deformed_problem(p, n, 0.1, prec=prec) if op == "csr"
+                     else fdgmres.mapped_problem(p, n, 0.1, prec=prec))
+                k, err = k_star_search(c, b, x, tight, 30, 30, 70)
+                e = {"k_star": k, "err_vs_tight_oracle": err}
+                if k is not None:
+                    dtk, _, _ = timed_solves(c, b, x, 5, rtol=0.0, restart=30, maxit=k,
+                                             flags=fdgmres.SOLVE_FIXED_ITERS)
+                    e["ms_per_solve"] = dtk * 1e3
+                    if base_ms is None:
+                        base_ms = dtk * 1e3
+                    e["speedup_vs_csr_fp64"] = base_ms / (dtk * 1e3)
+                eq[f"{op}_{name}"] = e
+                c.close()
+        out["equal_accuracy"] = eq
     return out
 
 
@@ -348,33 +398,42 @@ def complex_pairs_apply_128(reps=20):
     return out
 
 
-def precision_sweep_192():
+def precision_sweep_192(refs):
     """Unit cube, p = 6, n = 192, FGMRES(50): P^-1 in FP64, FP32 and BF16 (FP32 accumulate).
-    k* = the fixed iteration count at which the solution is within 1e-8 of the FP64 solve
-    (itself checked against the oracle by the test suite); timed solves use k*."""
+    k* = the fixed iteration count at which the solution is within 1e-8 of the oracle's
+    FP64 solution (of the GPU FP64 solve when the oracle leg is off); timed solves use k*.
+    The one-apply contraction |b - A P~^{-1} b| / |b| (A = P here) shows what each
+    precision's preconditioner leaves for FGMRES to do."""
+    import numpy as np
     import torch
     from paper_1705_04384_amd import fdgmres, inputs
     d, p, n = 3, 6, 192
     N = n ** d
     b = torch.from_numpy(inputs.rhs_normal(inputs.SEED_SWEEP_192, N)).cuda()
     x = torch.empty_like(b)
-    out = {"workload": f"unit cube, p={p}, n={n} (N={N}), N(0,1) RHS, FGMRES(50), outer FP64"}
+    ref = refs.get("sweep_192")
+    out = {"workload": f"unit cube, p={p}, n={n} (N={N}), N(0,1) RHS, FGMRES(50), outer FP64",
+           "k_star_reference": "oracle FP64 FGMRES(50) to rtol 1e-8" if ref is not None else "GPU FP64 solve"}
     ctx = fdgmres.unit_problem(d, p, n)
     dt, info, split = timed_solves(ctx, b, x, 5, rtol=1e-8, restart=50)
-    x64 = x.clone()
+    if ref is None:
+        ref = x.cpu().numpy()
     out["fp64"] = {"ms_per_solve": dt * 1e3, "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
-                   "kernel_ms_per_solve": split}
+                   "err_vs_oracle": err_vs(x, refs.get("sweep_192")), "kernel_ms_per_solve": split}
     ctx.close()
-    for name, prec in (("fp32", fdgmres.PREC_FP32), ("bf16", fdgmres.PREC_BF16)):
+    s = torch.empty_like(b)
+    y = torch.empty_like(b)
+    for name, prec in (("fp64", fdgmres.PREC_FP64), ("fp32", fdgmres.PREC_FP32), ("bf16", fdgmres.PREC_BF16)):
         ctx = fdgmres.unit_problem(d, p, n, prec=prec)
-        k_star, err = None, None
-        for k in range(1, 13):
-            ctx.solve(b, x, rtol=0.0, restart=50, maxit=k, flags=fdgmres.SOLVE_FIXED_ITERS)
-            err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-            if err <= 1e-8:
-                k_star = k
-                break
-        entry = {"k_star": k_star, "err_vs_fp64": err}
+        ctx.apply_prec(b, s)
+        ctx.matvec(s, y)
+        contraction = float(torch.linalg.norm(b - y) / torch.linalg.norm(b))
+        if name == "fp64":
+            out["fp64"]["one_apply_contraction"] = contraction
+            ctx.close()
+            continue
+        k_star, err = k_star_search(ctx, b, x, ref, 50, 1, 12)
+        entry = {"k_star": k_star, "err_vs_oracle": err, "one_apply_contraction": contraction}
         if k_star is not None:
             dt, info, split = timed_solves(ctx, b, x, 5, rtol=0.0, restart=50, maxit=k_star,
                                            flags=fdgmres.SOLVE_FIXED_ITERS)
@@ -387,7 +446,10 @@ def precision_sweep_192():
 
 
 def cpu_baseline(p, n, f, noise, count):
-    """The oracle (FP64, numpy/scipy) solving the same problem; setup excluded."""
+    """The CPU-baseline leg: the oracle (FP64, numpy/scipy) timed on a bounded sample of the
+    headline problem (setup excluded), then on every configuration at one BLAS thread and
+    at all cores.  Returns the baseline entry and the oracle's solutions, against which
+    every GPU solve of this run reports its error."""
     import numpy as np
     from oracle import colloc, fd, fgmres
     M, K, _, _ = colloc.colloc_factors(p, n)
@@ -395,11 +457,13 @@ def cpu_baseline(p, n, f, noise, count):
     mv = lambda v: colloc.unit_matvec([M] * 3, [K] * 3, v)
     pr = lambda v: fd.fd_apply([U] * 3, [V] * 3, [lam] * 3, v)
     rhs = [f, noise]
+    refs = {}
     t0 = time.perf_counter()
     its = []
     for k in range(count):
-        _, info = fgmres.fgmres(mv, pr, rhs[k % 2], rtol=1e-8, restart=30)
+        x, info = fgmres.fgmres(mv, pr, rhs[k % 2], rtol=1e-8, restart=30)
         its.append(info["iterations"])
+        refs[f"headline_{k % 2}"] = x
     dt = time.perf_counter() - t0
     threads = None
     try:
@@ -407,14 +471,19 @@ def cpu_baseline(p, n, f, noise, count):
         threads = max((d.get("num_threads") or 0) for d in threadpool_info()) or None
     except Exception:
         pass
-    return dict(value=count / dt, unit="solves/s", cores=threads or os.cpu_count(), kind="oracle",
+    base = dict(value=count / dt, unit="solves/s", cores=threads or os.cpu_count(), kind="oracle",
                 sample=f"{count} oracle FGMRES(30) solves of the same 128^3 p=4 problem "
                        f"(alternating the two right-hand sides), {dt:.1f} s, iterations {its}")
+    timing, xs = oracle_timing(threads)
+    base["per_config"] = timing
+    refs.update(xs)
+    return base, refs
 
 
-def oracle_timing():
-    """CPU-baseline leg, extended: the oracle on every configuration (one solve each, setup
-    excluded), at one BLAS thread and at all cores, with the host CPU named."""
+def oracle_timing(threads=None):
+    """The oracle on every configuration (one solve each, setup excluded), at one BLAS
+    thread and at all cores, with the host CPU named; returns the timings and the oracle's
+    solutions (plus a tight FGMRES solve of the deformed cube to rtol 1e-12)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import colloc, fd, fgmres
@@ -427,7 +496,8 @@ def oracle_timing():
                 break
     except OSError:
         pass
-    out = {"cpu": cpu, "cpu_count": os.cpu_count(), "configs": {}}
+    out = {"cpu": cpu, "cpu_count": os.cpu_count(), "all_cores_threads": threads, "configs": {}}
+    xs = {}
 
     def unit(d, p, n):
         M, K, _, _ = colloc.colloc_factors(p, n)
@@ -438,36 +508,43 @@ def oracle_timing():
 
     cases = []
     mv, pr = unit(2, 3, 33)
-    cases.append(("2D p=3 n=33 FGMRES(30)", mv, pr, colloc.manufactured_rhs(3, 33, 2), 30))
+    cases.append(("2D p=3 n=33 FGMRES(30)", "c2d", mv, pr, colloc.manufactured_rhs(3, 33, 2), 30))
     mv, pr = unit(3, 4, 128)
-    cases.append(("3D p=4 n=128 FGMRES(30)", mv, pr, inputs.rhs_normal(inputs.SEED_NOISE_128, 128 ** 3), 30))
+    cases.append(("3D p=4 n=128 FGMRES(30)", None, mv, pr, inputs.rhs_normal(inputs.SEED_NOISE_128, 128 ** 3), 30))
     t0 = time.perf_counter()
     A = colloc.deformed_operator(3, 96, 0.1)
     asm = time.perf_counter() - t0
     M, K, _, _ = colloc.colloc_factors(3, 96)
     U, V, lam = fd.factor_pencil(K, M)
-    cases.append(("3D deformed p=3 n=96 FGMRES(30)", lambda v: A @ v,
-                  lambda v: fd.fd_apply([U] * 3, [V] * 3, [lam] * 3, v),
-                  inputs.rhs_uniform(inputs.SEED_DEFORMED_96, 96 ** 3), 30))
+    dmv = lambda v: A @ v
+    dpr = lambda v: fd.fd_apply([U] * 3, [V] * 3, [lam] * 3, v)
+    bdef = inputs.rhs_uniform(inputs.SEED_DEFORMED_96, 96 ** 3)
+    cases.append(("3D deformed p=3 n=96 FGMRES(30)", "deformed_96", dmv, dpr, bdef, 30))
     mv, pr = unit(3, 6, 192)
-    cases.append(("3D p=6 n=192 FGMRES(50)", mv, pr, inputs.rhs_normal(inputs.SEED_SWEEP_192, 192 ** 3), 50))
-    for name, mv, pr, b, m in cases:
+    cases.append(("3D p=6 n=192 FGMRES(50)", "sweep_192", mv, pr, inputs.rhs_normal(inputs.SEED_SWEEP_192, 192 ** 3),
+                  50))
+    for name, key, mv, pr, b, m in cases:
         row = {}
         for label, limit in (("all_cores", None), ("one_thread", 1)):
             with threadpool_limits(limits=limit):
                 t0 = time.perf_counter()
-                _, info = fgmres.fgmres(mv, pr, b, rtol=1e-8, restart=m)
+                x, info = fgmres.fgmres(mv, pr, b, rtol=1e-8, restart=m)
                 row[label + "_s"] = time.perf_counter() - t0
             row["iterations"] = info["iterations"]
         out["configs"][name] = row
+        if key:
+            xs[key] = x
     out["configs"]["3D deformed p=3 n=96 FGMRES(30)"]["assembly_s"] = asm
-    return out
+    xt, info = fgmres.fgmres(dmv, dpr, bdef, rtol=1e-12, restart=30)
+    xs["deformed_96_tight"] = xt
+    out["configs"]["3D deformed p=3 n=96 FGMRES(30)"]["tight_reference_iterations"] = info["iterations"]
+    return out, xs
 
 
 def main():
     args = parse()
     if args.oracle_timing:
-        print(json.dumps(oracle_timing()), flush=True)
+        print(json.dumps(oracle_timing()[0]), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
@@ -575,16 +652,18 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+    refs = {}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], refs = cpu_baseline(p, n, f, noise, args.cpu_solves)
+        out["err_vs_oracle"] = [err_vs(X[k], refs.get(f"headline_{k}")) for k in range(2)]
     if not args.no_extra:
-        out["deformed_96"] = deformed_96()
-        out["precision_sweep_192"] = precision_sweep_192()
+        out["deformed_96"] = deformed_96(refs)
+        out["precision_sweep_192"] = precision_sweep_192(refs)
         out["batched_2d_p3_n33"] = batched_2d(1000)
         out["galerkin_convection_p3_n48"] = galerkin_convection_48()
         out["complex_pairs_apply_128"] = complex_pairs_apply_128()
     if not args.no_serve:
         out["serving"] = serving(args.serve_requests)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, n, f, noise, args.cpu_solves)
     print(json.dumps(out), flush=True)
 
 
