@@ -136,7 +136,8 @@ def timed_solves(ctx, b, x, reps, **kw):
 def _timed(fn, ctx, b, x, reps, **kw):
     import torch
     from paper_1705_04384_amd import fdgmres
-    classes = (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE, fdgmres.TIMER_MATVEC, fdgmres.TIMER_KRYLOV)
+    classes = (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE, fdgmres.TIMER_MATVEC, fdgmres.TIMER_KRYLOV,
+               fdgmres.TIMER_RESIDUAL)
     info = fn(b, x, **kw)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -151,7 +152,7 @@ def _timed(fn, ctx, b, x, reps, **kw):
         fn(b, x, **kw)
     torch.cuda.synchronize()
     split = {}
-    for c, name in zip(classes, ("fd_slab", "fd_fibre", "matvec", "krylov")):
+    for c, name in zip(classes, ("fd_slab", "fd_fibre", "matvec", "krylov", "residual_matvec")):
         ctx.timer_enable(c, False)
         cnt, ms = ctx.timer_read(c)
         split[name] = {"launches_per_solve": cnt / reps, "ms_per_solve": ms / reps}
@@ -445,6 +446,25 @@ def precision_sweep_192(refs):
     return out
 
 
+def matvec_roofline(N, mv_launches, mv_kms, rs_launches, rs_kms, timed_every):
+    """Roofline entry of the unit-cube matvec (eq. 2.9, streaming one-pass form): algorithmic
+    bytes per launch (read x, write y: 2 N doubles; the residual form also reads b: 3 N) over
+    the average launch duration, from HIP events around its launches in every
+    timed_every-th step of the timed region."""
+    out = {"kernel": "k_kron3_stream (unit-cube matvec, eq. 2.9)", "bound": "hbm", "peak": 8000.0,
+           "unit": "GB/s", "timing": f"HIP events around every launch in every {timed_every}th step of the "
+                                     f"timed region"}
+    if mv_launches:
+        s = mv_kms / 1e3 / mv_launches
+        out.update({"launches": mv_launches, "avg_launch_us": s * 1e6, "bytes_per_launch": 2 * N * 8,
+                    "achieved": 2 * N * 8 / s / 1e9, "frac": 2 * N * 8 / s / 1e9 / 8000.0})
+    if rs_launches:
+        s = rs_kms / 1e3 / rs_launches
+        out["residual_form"] = {"launches": rs_launches, "avg_launch_us": s * 1e6, "bytes_per_launch": 3 * N * 8,
+                                "achieved": 3 * N * 8 / s / 1e9, "frac": 3 * N * 8 / s / 1e9 / 8000.0}
+    return out
+
+
 def cpu_baseline(p, n, f, noise, count):
     """The CPU-baseline leg: the oracle (FP64, numpy/scipy) timed on a bounded sample of the
     headline problem (setup excluded), then on every configuration at one BLAS thread and
@@ -571,7 +591,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    for t in (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE):
+    timed_classes = (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE, fdgmres.TIMER_MATVEC, fdgmres.TIMER_RESIDUAL)
+    for t in timed_classes:
         ctx.timer_read(t)
     # FD kernel timing (HIP events recorded by the kernels' dispatches) during every
     # TIMED_EVERY-th step of the timed region: a timed dispatch leaves a few microseconds
@@ -583,16 +604,18 @@ def main():
     for k in range(args.steps):
         on = k % timed_every == 0
         if on:
-            for t in (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE):
+            for t in timed_classes:
                 ctx.timer_enable(t, True)
         infos = step()
         if on:
-            for t in (fdgmres.TIMER_APPLY, fdgmres.TIMER_FIBRE):
+            for t in timed_classes:
                 ctx.timer_enable(t, False)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     launches, kms = ctx.timer_read(fdgmres.TIMER_APPLY)
     f_launches, f_kms = ctx.timer_read(fdgmres.TIMER_FIBRE)
+    mv_launches, mv_kms = ctx.timer_read(fdgmres.TIMER_MATVEC)
+    rs_launches, rs_kms = ctx.timer_read(fdgmres.TIMER_RESIDUAL)
     for info in infos:
         assert info["converged"] and info["rel_res_true"] <= 1e-8, info
 
@@ -644,6 +667,7 @@ def main():
         "fibre_pass": {"kernel": "k_fibre (FD mode 3 + divide + mode 3, FP64 MFMA)", "launches": f_launches,
                        "avg_launch_us": f_avg_s * 1e6,
                        "tflops": pass_flops / f_avg_s / 1e12 if f_launches else None},
+        "roofline_matvec": matvec_roofline(N, mv_launches, mv_kms, rs_launches, rs_kms, timed_every),
     }
     ctx.close()
     if args.copy_calibration:

@@ -279,8 +279,10 @@ size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart);
  * other classes: events around the launch).  kernel: 0 = FD slab passes (modes 1 and 2 of
  * eq. 4.9, or the whole 2D solve in two passes; for n > 256 every unfused mode product),
  * 1 = operator matvec, 2 = Krylov vector kernels, 3 = FD fibre pass (mode 3 with V_3^T,
- * the eigenvalue divide and mode 3 with U_3).  fdg_timer_read returns the number of timed
- * launches and their summed duration in milliseconds, and resets the timer. */
+ * the eigenvalue divide and mode 3 with U_3), 4 = the residual form of the unit-domain
+ * matvec (r = b - A x with its squared-norm partials, used for true residuals).
+ * fdg_timer_read returns the number of timed launches and their summed duration in
+ * milliseconds, and resets the timer. */
 int fdg_timer_enable(fdg_ctx *ctx, int kernel, int enable);
 int fdg_timer_read(fdg_ctx *ctx, int kernel, int64_t *launches, double *total_ms);
 

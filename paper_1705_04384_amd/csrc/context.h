@@ -10,7 +10,7 @@
 #include "common.h"
 
 namespace fdg {
-constexpr int kTimerClasses = 4;
+constexpr int kTimerClasses = 5;
 
 struct TimerState {
   bool on = false;

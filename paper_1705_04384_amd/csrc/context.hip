@@ -309,7 +309,7 @@ int residual_partials(const fdg_ctx *c) {
 }
 
 int residual_entries(fdg_ctx *c, const Exec &ex, CBatch x, CBatch b, MBatch r, int64_t nent, MBatch part) {
-  TimedLaunch tl(c, 1, ex.stream, ex.timed);
+  TimedLaunch tl(c, 4, ex.stream, ex.timed);
   if (c->op_kind != 1 || !launch_kron_residual_f64(ex.stream, x, b, r, c->d, c->n, nent, ctx_bands(c), part))
     return set_error(FDG_EINVAL, "residual: the fused form does not apply to this operator");
   return hip_check(hipGetLastError(), "residual launch");

@@ -6,6 +6,10 @@
 //     a(j3) = sum_j2 M2 sM,      c(j3) = sum_j2 (K2 sM + M2 sK),
 // and the output y(i3) = sum_j3 K3 a(j3) + M3 c(j3) over the direction-3 band.
 // Forms, in order of preference:
+//   k_kron3_stream  one pass streaming the planes of a chunk through a register ring
+//                   (one band width W in 2..8 in all directions, band starts growing by at
+//                   most 1 per row, at least 128 workgroups per entry); no scratch,
+//                   gathered batches;
 //   k_kron3_wpp     one pass, one wave per plane (bands up to 8 wide whose starts grow by
 //                   at most 1 per row in directions 1 and 2); no scratch, gathered batches;
 //   k_kron3_planes  two passes through per-plane intermediates a, c (scratch);
@@ -631,6 +635,275 @@ __global__ __launch_bounds__(512) void k_kron3_wpp(CBatch x, MBatch y, int n, in
   }
 }
 
+
+// Workgroup barrier that orders LDS accesses only: __syncthreads() also orders global
+// memory, which makes every wave wait for all of its outstanding loads (the prefetched
+// planes) at each barrier.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The same between the lanes of one wave.
+__device__ inline void lds_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// One-pass 3D form streaming direction 3 through registers.  A workgroup of 8 waves owns
+// a tile of 64 columns i1 x T2 rows i2 and a chunk of outputs i3 in [s3, e3).  Waves
+// 0..6 load and compute, wave 7 only stores (and, for the residual, loads b): a wave
+// keeps its prefetched planes in flight only while it issues no global stores and no
+// loads that may or may not execute, and its barriers order LDS only (lds_barrier).
+// The tile's windows are at most 64 + w1 - 1 staged columns j1 (lanes, plus w1 - 1 halo
+// lanes) and 7 RPW staged rows j2 (T2 = 7 RPW - w2 + 1 with band starts growing by at
+// most 1 per row); compute wave w stages rows j2 = R0 + w + 7 k, k < RPW.  The chunk's
+// input planes j3 are visited in order, loaded D planes ahead into registers (every load
+// is issued, at a clamped address where it lies outside the tensor, and masked when
+// used).  Per plane, each compute wave passes its rows through a wave-private LDS row
+// buffer and forms the direction-1 band sums sM = M1 x and sK = K1 x, which enter a
+// register ring holding the last WMAX planes.  When the ring holds the direction-3 band
+// of an output plane i3, each compute wave forms
+//     f = K3 sM + M3 sK,   g = M3 sM          (band sums over the ring)
+// for its rows and stores them to LDS; after one workgroup barrier it forms the outputs
+// of its rows i2 = i2a + w + 7 k,  y = M2 f + K2 g  (band sums over staged rows), into an
+// LDS output tile that the store wave writes out after the next barrier.  Coefficients
+// are staged in LDS once.
+// RES: the store wave writes r = b - A x (b loaded one output ahead) and the workgroup
+// writes one partial sum of |r|^2.
+template <int W, int RPW, int D, int C3MAX, bool RES>
+__global__ __launch_bounds__(512) void k_kron3_stream(CBatch x, MBatch y, int n, int ntx, int nty, int nchunk,
+                                                      int c3len, int64_t ntiles, KronBands bd, CBatch rhs,
+                                                      MBatch part) {
+  constexpr int NWC = 7;               // compute waves; wave 7 stores
+  constexpr int NR = NWC * RPW;        // staged rows j2
+  constexpr int NPLMAX = C3MAX + W - 1;  // planes j3 of a chunk (band starts growing by <= 1)
+  constexpr int KO = (NR + NWC - 1) / NWC;  // output rows i2 per compute wave (T2 <= NR)
+  __shared__ double xrow[NWC][RPW][64 + 8];
+  __shared__ double zf[2][NR][64], zg[2][NR][64], ob[2][NR][64];
+  // Band coefficients of directions 2 and 3 and the direction-3 band starts are uniform
+  // per wave: they are read through the constant address space (scalar loads, scalar
+  // registers, their own completion counter), so reading them never makes a wave wait
+  // for its prefetched planes.
+  typedef const __attribute__((address_space(4))) double cdbl;
+  typedef const __attribute__((address_space(4))) int32_t cint;
+  cdbl *M2c = (cdbl *)bd.M[1], *K2c = (cdbl *)bd.K[1], *M3c = (cdbl *)bd.M[2], *K3c = (cdbl *)bd.K[2];
+  cint *lo2c = (cint *)bd.lo[1], *lo3c = (cint *)bd.lo[2];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // XCD-aware order: consecutive linear tiles (neighbours in i1, then i2, then i3) share
+  // an XCD, so their halos meet in one L2; the grid is padded to a multiple of 8
+  const int64_t nb = (int64_t)gridDim.x;
+  const int64_t bid = blockIdx.x;
+  const int64_t lin = (bid & 7) * (nb >> 3) + (bid >> 3);
+  if (lin >= ntiles) return;
+  const int tx = (int)(lin % ntx);
+  int64_t rest = lin / ntx;
+  const int ty = (int)(rest % nty);
+  rest /= nty;
+  const int64_t ent = rest / nchunk;
+  const int64_t tile_in_ent = lin - ent * (int64_t)ntx * nty * nchunk;
+  const int s3 = (int)(rest - ent * nchunk) * c3len;
+  const int e3 = s3 + c3len < n ? s3 + c3len : n;
+  const int nq = e3 - s3;
+  const int64_t n2 = (int64_t)n * n;
+  constexpr int w1 = W, w2 = W, w3 = W;  // the launcher checks that every band is W wide
+  const int T2 = NR - w2 + 1;
+  const int i1a = tx * 64, i2a = ty * T2;
+  const int i1 = i1a + lane;
+  const bool act1 = i1 < n;
+  const int i1c = act1 ? i1 : n - 1;
+  const int L0 = bd.lo[0][i1a];
+  const int R0 = bd.lo[1][i2a];
+  const int P0 = bd.lo[2][s3];
+  const int NPL = bd.lo[2][e3 - 1] + w3 - P0;
+  auto plane_of = [&](int q) { return lo3c[s3 + q] + w3 - 1 - P0; };  // plane completing output q
+  double rr = 0.0;  // RES: this thread's part of |b - A x|^2
+  if (wave == NWC) {
+    // the store wave: output q - 1 after the barrier of output q, the last one after the
+    // final barrier
+    gptr<double> __restrict__ yb = y.gat(ent);
+    gptr<const double> __restrict__ bbase = RES ? rhs.gat(ent) : nullptr;
+    int offo[NR];  // this lane's output offsets within a plane (clamped; masked on store)
+    bool oko[NR];
+#pragma unroll
+    for (int u2 = 0; u2 < NR; ++u2) {
+      const int i2 = i2a + u2;
+      oko[u2] = act1 && u2 < T2 && i2 < n;
+      offo[u2] = oko[u2] ? i2 * n + i1 : 0;
+    }
+    double bn[NR];
+    if (RES) {
+#pragma unroll
+      for (int u2 = 0; u2 < NR; ++u2) bn[u2] = bbase[(int64_t)s3 * n2 + offo[u2]];
+    }
+    for (int q = 0; q <= nq; ++q) {
+      lds_barrier();
+      if (q == 0) continue;
+      const int i3 = s3 + q - 1, buf = (q - 1) & 1;
+      gptr<double> yp = yb + (int64_t)i3 * n2;
+      // every row of the output tile is read before any store is issued, so the LDS reads
+      // are in flight together
+      double v[NR];
+#pragma unroll
+      for (int u2 = 0; u2 < NR; ++u2) v[u2] = ob[buf][u2][lane];
+      // keep the reads here (the compiler would otherwise sink each into its store's branch
+      // and wait for them one at a time)
+#pragma unroll
+      for (int u2 = 0; u2 < NR; ++u2) asm volatile("" ::"v"(v[u2]));
+      if (RES) {
+        double bc[NR];
+#pragma unroll
+        for (int u2 = 0; u2 < NR; ++u2) bc[u2] = bn[u2];
+        const int inext = q < nq ? s3 + q : i3;
+#pragma unroll
+        for (int u2 = 0; u2 < NR; ++u2) bn[u2] = bbase[(int64_t)inext * n2 + offo[u2]];
+#pragma unroll
+        for (int u2 = 0; u2 < NR; ++u2) {
+          const double r = bc[u2] - v[u2];
+          v[u2] = r;
+          if (oko[u2]) rr = fma(r, r, rr);
+        }
+      }
+#pragma unroll
+      for (int u2 = 0; u2 < NR; ++u2)
+        if (oko[u2]) yp[offo[u2]] = v[u2];
+    }
+  } else {
+    gptr<const double> __restrict__ xb = x.gat(ent);
+    const int off1 = bd.lo[0][i1c] - L0;  // in [0, 63]
+    double m1[W], k1[W];  // direction-1 coefficients of this lane's column
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      m1[t] = bd.M[0][(size_t)i1c * w1 + t];
+      k1[t] = bd.K[0][(size_t)i1c * w1 + t];
+    }
+    // window offsets of this wave's output rows (their coefficients are read per output)
+    int b2[KO];
+#pragma unroll
+    for (int kk = 0; kk < KO; ++kk) {
+      const int u2 = wave + NWC * kk, i2 = i2a + u2;
+      b2[kk] = (u2 < T2 && i2 < n) ? lo2c[i2] - R0 : 0;
+    }
+    // this lane's elements of a plane: row R0 + wave + 7 k, column L0 + lane (and the halo
+    // column L0 + 64 + lane for lane < w1 - 1), as offsets within a plane; outside the
+    // tensor the offset is clamped to 0: such values only reach outputs beyond the tensor,
+    // which are never stored, and every load is issued on every path
+    int offm[RPW], offh[RPW];  // n^2 <= 2^20
+#pragma unroll
+    for (int k = 0; k < RPW; ++k) {
+      const int r = R0 + wave + NWC * k;
+      const bool rok = r < n;
+      offm[k] = (rok && L0 + lane < n) ? r * n + L0 + lane : 0;
+      offh[k] = (rok && lane < w1 - 1 && L0 + 64 + lane < n) ? r * n + L0 + 64 + lane : 0;
+    }
+    double pm[D][RPW], ph[D][RPW];  // prefetched planes (ring of D)
+    auto issue = [&](int u, int pl) {
+      gptr<const double> xp = xb + (int64_t)(P0 + (pl < NPL ? pl : NPL - 1)) * n2;
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) {
+        pm[u][k] = xp[offm[k]];
+        ph[u][k] = xp[offh[k]];
+      }
+    };
+#pragma unroll
+    for (int u = 0; u < D; ++u) issue(u, u);
+    double rm[RPW][W], rk[RPW][W];  // ring: sM, sK of plane pl in slot pl % W
+#pragma unroll
+    for (int k = 0; k < RPW; ++k)
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        rm[k][t] = 0.0;
+        rk[k][t] = 0.0;
+      }
+    int q = 0;      // next output of the chunk
+    // every plane step is unrolled: the prefetch ring is indexed statically and every load
+    // is issued on every path, so each use waits for exactly the loads it needs
+#pragma clang loop unroll(full)
+    for (int pl = 0; pl < NPLMAX; ++pl) {
+      const int u = pl % D;
+      double vm[RPW], vh[RPW];
+#pragma unroll
+      for (int k = 0; k < RPW; ++k) {
+        vm[k] = pm[u][k];
+        vh[k] = ph[u][k];
+      }
+      if (pl + D < NPLMAX) issue(u, pl + D);
+      if (pl < NPL) {
+        // direction 1 on the wave's rows of plane pl
+#pragma unroll
+        for (int k = 0; k < RPW; ++k) {
+          xrow[wave][k][lane] = vm[k];
+          if (lane < 8) xrow[wave][k][64 + lane] = vh[k];
+        }
+        lds_wave_sync();
+#pragma unroll
+        for (int k = 0; k < RPW; ++k) {
+          double sm = 0.0, sk = 0.0;
+#pragma unroll
+          for (int t = 0; t < W; ++t) {
+            const double v = xrow[wave][k][off1 + t];
+            sm = fma(m1[t], v, sm);
+            sk = fma(k1[t], v, sk);
+          }
+          rm[k][pl % W] = sm;
+          rk[k][pl % W] = sk;
+        }
+        lds_wave_sync();
+        // outputs whose direction-3 band ends at this plane
+        while (q < nq && plane_of(q) == pl) {
+          const int buf = q & 1;
+          double k3[W], m3[W];
+#pragma unroll
+          for (int t = 0; t < W; ++t) {
+            k3[t] = K3c[(size_t)(s3 + q) * W + t];
+            m3[t] = M3c[(size_t)(s3 + q) * W + t];
+          }
+#pragma unroll
+          for (int k = 0; k < RPW; ++k) {
+            double f = 0.0, g = 0.0;
+#pragma unroll
+            for (int t = 0; t < W; ++t) {
+              const int sl = (pl + 1 + t) % W;  // plane pl - W + 1 + t
+              f = fma(k3[t], rm[k][sl], f);
+              f = fma(m3[t], rk[k][sl], f);
+              g = fma(m3[t], rm[k][sl], g);
+            }
+            zf[buf][wave + NWC * k][lane] = f;
+            zg[buf][wave + NWC * k][lane] = g;
+          }
+          lds_barrier();
+#pragma unroll
+          for (int k = 0; k < KO; ++k) {
+            const int u2 = wave + NWC * k;
+            const int i2 = i2a + u2;
+            if (u2 < T2 && i2 < n) {
+              double acc = 0.0;
+#pragma unroll
+              for (int t = 0; t < W; ++t) {
+                acc = fma(M2c[(size_t)i2 * W + t], zf[buf][b2[k] + t][lane], acc);
+                acc = fma(K2c[(size_t)i2 * W + t], zg[buf][b2[k] + t][lane], acc);
+              }
+              ob[buf][u2][lane] = acc;
+            }
+          }
+          ++q;
+        }
+      }
+    }
+    lds_barrier();  // the last output tile is complete
+  }
+  if (RES) {  // one partial per workgroup: the store wave's lanes in a fixed order
+    if (wave == NWC) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) rr += __shfl_xor(rr, off, 64);
+      if (lane == 0) part.gat(ent)[tile_in_ent] = rr;
+    }
+  }
+}
+
 }  // namespace
 
 int kron_window_max() { return 16; }
@@ -641,7 +914,8 @@ bool kron_fused_ok(int n, int64_t nbatch, const KronBands &bd) {
 #endif
   int w = 0;
   for (int l = 0; l < 3; ++l) w = bd.w[l] > w ? bd.w[l] : w;
-  return w <= 8 && bd.step[0] <= 1 && bd.step[1] <= 1 && (int64_t)n * n * nbatch < ((int64_t)1 << 31);
+  return w <= 8 && bd.step[0] <= 1 && bd.step[1] <= 1 && bd.step[2] <= 1 &&
+         (int64_t)n * n * nbatch < ((int64_t)1 << 31);
 }
 
 bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bd) {
@@ -653,15 +927,74 @@ bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bd) {
 
 namespace {
 
+// Shape of the streaming one-pass form: RPW staged rows j2 per compute wave, D planes
+// loaded ahead (2: the measured best at n = 128 and 192; deeper rings cost occupancy),
+// and chunks of 8 outputs i3.
+#ifndef FDG_MV_RPW
+#define FDG_MV_RPW 2
+#endif
+#ifndef FDG_MV_D
+#define FDG_MV_D 2
+#endif
+constexpr int kStreamRPW = FDG_MV_RPW, kStreamD = FDG_MV_D;
+
+struct StreamShape {
+  int ntx, nty, nchunk, c3len;
+  int64_t tiles() const { return (int64_t)ntx * nty * nchunk; }
+};
+
+StreamShape stream_shape(int n, const KronBands &bd) {
+  StreamShape sh;
+  const int T2 = 7 * kStreamRPW - bd.w[1] + 1;
+  sh.ntx = (int)cdiv(n, 64);
+  sh.nty = (int)cdiv(n, T2);
+  sh.c3len = 8;
+  sh.nchunk = (int)cdiv(n, sh.c3len);
+  return sh;
+}
+
+// The streaming form needs one band width W in [2, 8] for all three directions, and it
+// is taken when it has at least 128 workgroups per entry: each of its workgroups walks
+// its planes one after the other, so on small grids the one-wave-per-plane form, which
+// spreads the planes over more waves, finishes first (measured on MI355X: 64^3 p = 2
+// 8.1 against 10.4 us, 48^3 p = 3 7.9 against 10.2; from 80^3 p = 4 on the streaming form
+// is faster).  The choice depends on n and the bands only.
+bool stream_ok(int n, const KronBands &bd) {
+  return bd.w[0] == bd.w[1] && bd.w[1] == bd.w[2] && bd.w[0] >= 2 && bd.w[0] <= 8 &&
+         stream_shape(n, bd).tiles() >= 128;
+}
+
 constexpr int kWppT2 = FDG_MV_T2, kWppC3 = FDG_MV_C3;
 
-int64_t wpp_tiles(int n) { return (int64_t)cdiv(n, 64) * cdiv(n, kWppT2) * cdiv(n, kWppC3); }
+int64_t wpp_tiles(int n, const KronBands &bd) {
+  if (stream_ok(n, bd)) return stream_shape(n, bd).tiles();
+  return (int64_t)cdiv(n, 64) * cdiv(n, kWppT2) * cdiv(n, kWppC3);
+}
 
 template <bool RES>
 void launch_wpp(hipStream_t s, CBatch x, MBatch y, int n, int64_t nbatch, const KronBands &bd, CBatch rhs,
                 MBatch part) {
   int w = 0;
   for (int l = 0; l < 3; ++l) w = bd.w[l] > w ? bd.w[l] : w;
+  if (stream_ok(n, bd)) {
+    const StreamShape sh = stream_shape(n, bd);
+    const int64_t ntiles = sh.tiles() * nbatch;
+    const dim3 grid((unsigned)((ntiles + 7) / 8 * 8));
+#define FDG_STREAM(WW, C3)                                                                                   \
+  hipLaunchKernelGGL((k_kron3_stream<WW, kStreamRPW, kStreamD, C3, RES>), grid, dim3(512), 0, s, x, y, n, sh.ntx, \
+                     sh.nty, sh.nchunk, sh.c3len, ntiles, bd, rhs, part)
+    switch (w) {
+      case 2: FDG_STREAM(2, 8); break;
+      case 3: FDG_STREAM(3, 8); break;
+      case 4: FDG_STREAM(4, 8); break;
+      case 5: FDG_STREAM(5, 8); break;
+      case 6: FDG_STREAM(6, 8); break;
+      case 7: FDG_STREAM(7, 8); break;
+      default: FDG_STREAM(8, 8); break;
+    }
+#undef FDG_STREAM
+    return;
+  }
   const int ntx = (int)cdiv(n, 64), nty = (int)cdiv(n, kWppT2), nchunk = (int)cdiv(n, kWppC3);
   const dim3 grid((unsigned)((int64_t)ntx * nty * nchunk * nbatch));
   if (w <= 4)
@@ -679,7 +1012,7 @@ void launch_wpp(hipStream_t s, CBatch x, MBatch y, int n, int64_t nbatch, const 
 
 int kron_residual_partials(int d, int n, const KronBands &bd) {
   if (d != 3 || !kron_fused_ok(n, 1, bd)) return 0;
-  return (int)wpp_tiles(n);
+  return (int)wpp_tiles(n, bd);
 }
 
 bool launch_kron_residual_f64(hipStream_t s, CBatch x, CBatch rhs, MBatch r, int d, int n, int64_t nbatch,

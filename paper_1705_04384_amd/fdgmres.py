@@ -20,7 +20,7 @@ PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 SOLVE_USE_X0 = 1
 SOLVE_FIXED_ITERS = 2
 SOLVE_NO_AHEAD = 4
-TIMER_APPLY, TIMER_MATVEC, TIMER_KRYLOV, TIMER_FIBRE = 0, 1, 2, 3
+TIMER_APPLY, TIMER_MATVEC, TIMER_KRYLOV, TIMER_FIBRE, TIMER_RESIDUAL = 0, 1, 2, 3, 4
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i32p = ctypes.POINTER(ctypes.c_int32)

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import colloc, fd, fgmres
 from paper_1705_04384_amd import inputs
-from tests.gpu_helpers import oracle_unit, relerr, to_dev, torch_cuda
+from tests.gpu_helpers import maxrel, oracle_unit, relerr, to_dev, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -81,6 +81,43 @@ def test_kron_matvec_tiles_and_tails(p, n, batch):
         assert relerr(got[k * N:(k + 1) * N], ref) <= 1e-13, (p, n, k)
     ctx.close()
 
+
+
+@pytest.mark.parametrize("p,n,batch", [(4, 80, 2), (3, 96, 1), (6, 100, 1), (2, 130, 1), (5, 97, 1), (4, 128, 1)])
+def test_kron_matvec_streaming_form(p, n, batch):
+    """Shapes with at least 128 workgroups per entry take the streaming one-pass form (band
+    widths 3 to 7, ragged tails in every direction: 80, 100, 130 and 97 are not multiples
+    of the 64-column tile, of the T2 = 15 - w row tile or of the 8-plane chunk); against
+    the oracle's product element by element, and its residual form (r = b - A x with the
+    |r|^2 partials) through the true residual a solve reports."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.unit_problem(3, p, n, batch=batch)
+    N = n ** 3
+    x = np.concatenate([inputs.rhs_normal(400 + k, N) for k in range(batch)])
+    y = torch.full((batch * N,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.matvec(to_dev(x), y)
+    torch.cuda.synchronize()
+    M, K, _, _ = colloc.colloc_factors(p, n)
+    got = y.cpu().numpy()
+    for k in range(batch):
+        ref = colloc.unit_matvec([M] * 3, [K] * 3, x[k * N:(k + 1) * N])
+        assert relerr(got[k * N:(k + 1) * N], ref) <= 1e-13, (p, n, k)
+        assert maxrel(got[k * N:(k + 1) * N], ref) <= 1e-13, (p, n, k)
+    ctx.close()
+    if batch == 1:
+        # residual form: a solve from a start guess x0 reports ||b - A x|| / ||b|| of its
+        # iterate, computed by the fused residual kernel; recompute it with the oracle
+        ctx = fdg.unit_problem(3, p, n)
+        b = inputs.rhs_normal(410, N)
+        xd = to_dev(inputs.rhs_normal(411, N) * 1e-3)
+        info = ctx.solve(to_dev(b), xd, rtol=0.0, restart=30, maxit=1,
+                         flags=fdg.SOLVE_USE_X0 | fdg.SOLVE_FIXED_ITERS)
+        xr = xd.cpu().numpy()
+        r = b - colloc.unit_matvec([M] * 3, [K] * 3, xr)
+        assert abs(info["rel_res_true"] - np.linalg.norm(r) / np.linalg.norm(b)) <= 1e-12 * max(
+            1.0, info["rel_res_true"]), (info["rel_res_true"], np.linalg.norm(r) / np.linalg.norm(b))
+        ctx.close()
 
 
 @pytest.mark.parametrize("p,n,band", [(3, 12, False), (4, 9, False), (3, 8, True)])
