@@ -53,7 +53,10 @@ typedef enum {
 enum {
   FDG_SOLVE_USE_X0 = 1,       /* start from the x passed in instead of 0                     */
   FDG_SOLVE_FIXED_ITERS = 2,  /* run exactly maxit inner iterations, ignore rtol in a cycle  */
-  FDG_SOLVE_NO_AHEAD = 4      /* fdg_solve: do not queue Arnoldi steps ahead (same results)  */
+  FDG_SOLVE_NO_AHEAD = 4,     /* fdg_solve: do not queue Arnoldi steps ahead (same results)  */
+  FDG_SOLVE_TIME_SPLIT = 8    /* fdg_solve: fill the device time split in the info, from the kernel
+                                 timers (it reads and resets them; each timed launch leaves the
+                                 queue idle for a few microseconds, so the solve is slower) */
 };
 
 typedef struct {
@@ -67,6 +70,12 @@ typedef struct {
   int half_steps;        /* BiCGStab: half steps done (the paper's count is half_steps / 2,
                             "k + 0.5" when the last iteration stopped after its BiCG half);
                             0 for flexible GMRES                                           */
+  double t_apply_ms;     /* fdg_solve with FDG_SOLVE_TIME_SPLIT: device time of the P^{-1}
+                            applies (HIP events around their kernels); 0 otherwise         */
+  double t_matvec_ms;    /* the same for the operator matvecs (true residuals included)    */
+  double t_orth_ms;      /* the same for the Gram-Schmidt and other vector kernels         */
+  double t_host_ms;      /* fdg_solve: host time spent on the Givens least-squares update,
+                            the choice of the next phase and its launches (always set)    */
 } fdg_info;
 
 /* ------------------------------------------------------------------------------------

@@ -187,6 +187,9 @@ int ctx_ready_prec(fdg_ctx *c);
 // Device address of the no-allocation apply's scratch array on device dev (current),
 // looked up once per device; called when a context is created.
 int scratch_setup(int dev);
+// Number and summed duration (ms) of the timed launches of kernel timer class k since the
+// last read, after the context stream has drained; resets the class.
+int timer_collect(fdg_ctx *c, int k, int64_t *launches, double *total_ms);
 // Some direction's pencil has complex eigenvalue pairs (block-diagonal D).
 bool ctx_has_pairs(const fdg_ctx *c);
 // Apply/matvec scratch t1, t2 (and t32a, t32b for a reduced-precision context).

@@ -875,6 +875,30 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   rb.hh = c->hpin;
   rb.hh_dev = c->hpin_dev;
   if (!c->phase_ev) HIPCHK(hipEventCreateWithFlags(&c->phase_ev, hipEventDisableTiming));
+  // device time split: every kernel timer class on for this solve (after clearing what
+  // earlier launches left in them), the previous on/off states restored at the end
+  const bool split = (flags & FDG_SOLVE_TIME_SPLIT) != 0;
+  struct TimerRestore {  // puts the timer on/off states back on every way out
+    fdg_ctx *c = nullptr;
+    bool on[kTimerClasses] = {};
+    ~TimerRestore() {
+      if (c)
+        for (int k = 0; k < kTimerClasses; ++k) c->timers[k].on = on[k];
+    }
+  } restore;
+  if (split) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < kTimerClasses; ++k) restore.on[k] = c->timers[k].on;
+    restore.c = c;
+    for (int k = 0; k < kTimerClasses; ++k) {
+      int64_t cnt;
+      double ms;
+      if ((st = timer_collect(c, k, &cnt, &ms)) != FDG_OK) return st;
+      c->timers[k].on = true;
+    }
+  }
+  double host_ms = 0.0;  // Givens updates, phase choice and launches
+  auto host_clock = [] { return std::chrono::steady_clock::now(); };
   SolveRun run;
   run.init(c, rb, restart, b, x, rtol, maxit, flags);
   if (!(flags & FDG_SOLVE_NO_AHEAD)) run.bank_stride = (size_t)host_doubles(restart);
@@ -885,6 +909,7 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
   Phase spec;
   bool spec_queued = false;
   while (!run.finished()) {
+    auto h0 = host_clock();
     if (!queued) {
       // the previous phase's last kernel may still be retiring (its results were read);
       // the slots armed here are ones it has already written, so it cannot overwrite them
@@ -902,6 +927,7 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       if (st != FDG_OK) return st;
       spec_queued = true;
     }
+    host_ms += std::chrono::duration<double, std::milli>(host_clock() - h0).count();
     HIPCHK(hipEventRecord(c->phase_ev, c->stream));
     stream_idle = false;
     // the host needs the phase's scalars, not the end of its last kernel: poll the armed
@@ -923,7 +949,9 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
       stream_idle = true;
     }
     const int consumed_bank = run.phase().bank;
+    auto h1 = host_clock();
     run.consume();
+    host_ms += std::chrono::duration<double, std::milli>(host_clock() - h1).count();
     // the next phase: the queued speculation when consume() chose the same step, else a
     // new phase in the bank just read (a discarded speculation still writes the other)
     Phase next = run.phase();
@@ -939,7 +967,20 @@ extern "C" int fdg_solve(fdg_ctx *c, const double *b, double *x, double rtol, in
     (void)hipGetLastError();
     HIPCHK(e);
   }
-  if (info) *info = run.info();
+  fdg_info out = run.info();
+  out.t_host_ms = host_ms;
+  if (split) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double ms[kTimerClasses];
+    for (int k = 0; k < kTimerClasses; ++k) {
+      int64_t cnt;
+      if ((st = timer_collect(c, k, &cnt, &ms[k])) != FDG_OK) return st;
+    }
+    out.t_apply_ms = ms[0] + ms[3];   // slab passes (or mode products) and fibre passes
+    out.t_matvec_ms = ms[1] + ms[4];  // matvecs and fused residual matvecs
+    out.t_orth_ms = ms[2];            // Gram-Schmidt and the other vector kernels
+  }
+  if (info) *info = out;
   return run.status();
 }
 
@@ -975,12 +1016,12 @@ extern "C" int fdg_timer_enable(fdg_ctx *c, int kernel, int enable) {
   return FDG_OK;
 }
 
-extern "C" int fdg_timer_read(fdg_ctx *c, int kernel, int64_t *launches, double *total_ms) {
-  clear_error();
-  if (!c || kernel < 0 || kernel >= kTimerClasses || !launches || !total_ms)
-    return set_error(FDG_EINVAL, "timer_read: bad argument");
-  HIPCHK(hipStreamSynchronize(c->stream));
-  TimerState &t = c->timers[kernel];
+namespace fdg {
+
+// Number and summed duration (ms) of the timed launches of class k since the last read;
+// the stream must have drained.  Resets the class.
+int timer_collect(fdg_ctx *c, int k, int64_t *launches, double *total_ms) {
+  TimerState &t = c->timers[k];
   double sum = 0.0;
   int64_t cnt = 0;
   for (size_t i = 0; i + 1 < t.pending.size(); i += 2) {
@@ -994,4 +1035,14 @@ extern "C" int fdg_timer_read(fdg_ctx *c, int kernel, int64_t *launches, double 
   *launches = cnt;
   *total_ms = sum;
   return FDG_OK;
+}
+
+}  // namespace fdg
+
+extern "C" int fdg_timer_read(fdg_ctx *c, int kernel, int64_t *launches, double *total_ms) {
+  clear_error();
+  if (!c || kernel < 0 || kernel >= kTimerClasses || !launches || !total_ms)
+    return set_error(FDG_EINVAL, "timer_read: bad argument");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return timer_collect(c, kernel, launches, total_ms);
 }

@@ -20,6 +20,7 @@ PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 SOLVE_USE_X0 = 1
 SOLVE_FIXED_ITERS = 2
 SOLVE_NO_AHEAD = 4
+SOLVE_TIME_SPLIT = 8
 TIMER_APPLY, TIMER_MATVEC, TIMER_KRYLOV, TIMER_FIBRE, TIMER_RESIDUAL = 0, 1, 2, 3, 4
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -36,7 +37,9 @@ class FdgError(RuntimeError):
 class fdg_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("breakdown", ctypes.c_int), ("rel_res_est", ctypes.c_double),
-                ("rel_res_true", ctypes.c_double), ("ms_total", ctypes.c_double), ("half_steps", ctypes.c_int)]
+                ("rel_res_true", ctypes.c_double), ("ms_total", ctypes.c_double), ("half_steps", ctypes.c_int),
+                ("t_apply_ms", ctypes.c_double), ("t_matvec_ms", ctypes.c_double), ("t_orth_ms", ctypes.c_double),
+                ("t_host_ms", ctypes.c_double)]
 
 
 class fdg_done(ctypes.Structure):
@@ -341,7 +344,8 @@ class Context:
             _check(st)
         return {"iterations": info.iterations, "restarts": info.restarts, "converged": info.converged,
                 "breakdown": info.breakdown, "rel_res_est": info.rel_res_est, "rel_res_true": info.rel_res_true,
-                "ms_total": info.ms_total}
+                "ms_total": info.ms_total, "t_apply_ms": info.t_apply_ms, "t_matvec_ms": info.t_matvec_ms,
+                "t_orth_ms": info.t_orth_ms, "t_host_ms": info.t_host_ms}
 
     def operator_bytes(self):
         """Bytes of operator data one matvec reads (x and y excluded)."""

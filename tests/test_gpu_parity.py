@@ -434,3 +434,28 @@ def test_csr_operator_general_and_tensor_patterns(d, n):
         torch.cuda.synchronize()
         assert relerr(y.cpu().numpy(), S @ x) <= 1e-14
         ctx.close()
+
+
+def test_solve_time_split():
+    """FDG_SOLVE_TIME_SPLIT fills the device time of the applies, matvecs and vector
+    kernels (kernel timers), and the host time is always set; the iterate is the same bits
+    as without the split, and the caller's timer states are restored."""
+    fdg = _fdg()
+    torch = torch_cuda()
+    p, n = 3, 12
+    ctx = fdg.deformed_problem(p, n, 0.1)
+    b = to_dev(inputs.rhs_uniform(inputs.SEED_DEFORMED_96, n ** 3))
+    x1 = torch.empty_like(b)
+    x2 = torch.empty_like(b)
+    i1 = ctx.solve(b, x1, rtol=1e-8, restart=30)
+    i2 = ctx.solve(b, x2, rtol=1e-8, restart=30, flags=fdg.SOLVE_TIME_SPLIT)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2) and i1["iterations"] == i2["iterations"]
+    assert i1["t_apply_ms"] == 0.0 and i1["t_matvec_ms"] == 0.0 and i1["t_orth_ms"] == 0.0
+    assert i1["t_host_ms"] > 0.0 and i2["t_host_ms"] > 0.0
+    assert i2["t_apply_ms"] > 0.0 and i2["t_matvec_ms"] > 0.0 and i2["t_orth_ms"] > 0.0
+    assert i2["t_apply_ms"] + i2["t_matvec_ms"] + i2["t_orth_ms"] < i2["ms_total"]
+    # timers were off before, so nothing is recorded by a later solve
+    ctx.solve(b, x1, rtol=1e-8, restart=30)
+    assert ctx.timer_read(fdg.TIMER_APPLY) == (0, 0.0)
+    ctx.close()
