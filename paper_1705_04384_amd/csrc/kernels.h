@@ -124,7 +124,7 @@ void launch_norm_reduce(hipStream_t s, CBatch Pn, int G, int64_t nbatch, MBatch 
 // x = (overwrite ? 0 : x) + sum_q Z_q y_q, q < k.at(e) <= 256; coefficients from ytab[e*256 + q]
 // when ytab is given, else y (shared by every entry).
 void launch_lincomb(hipStream_t s, MBatch x, CBatch Z, int64_t ldz, IBatch k, const Coeffs &y,
-                    const double *ytab, int64_t N, int64_t nbatch, IBatch overwrite);
+                    const double *ytab, int64_t N, int64_t nbatch, IBatch overwrite, bool aligned16_all);
 // r = b - Ax and the partials P.at(e)[g] of |r|^2 (2-wide accesses, and so a different
 // summation order, when every pointer is 16-byte aligned and N is even).
 void launch_residual(hipStream_t s, CBatch b, CBatch Ax, MBatch r, int64_t N, int64_t nbatch, int G,

@@ -449,8 +449,11 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
   }
   // 2-wide accesses of b; the Krylov buffers are 256-byte aligned with an even or odd N
   // handled inside the launchers
-  bool b16 = true;
-  for (int e = 0; e < nrun; ++e) b16 = b16 && al(runs[e]->b, 16);
+  bool b16 = true, x16 = true;
+  for (int e = 0; e < nrun; ++e) {
+    b16 = b16 && al(runs[e]->b, 16);
+    x16 = x16 && al(runs[e]->x, 16);
+  }
   bool a32 = true;  // 32-byte alignment of every V_j / Z_j (load width of the FD passes)
   if (steps & kStepIter)
     for (int e = 0; e < nrun; ++e) {
@@ -475,7 +478,7 @@ int enqueue_phase(const Exec &ex, SolveRun *const *runs, int nrun, TableArena *t
   }
   if (steps & kStepLincomb) {
     TimedLaunch tl(c, 2, s, timed);
-    launch_lincomb(s, X, Zb, N, K, r0.coeffs(), ytab, N, nrun, OW);
+    launch_lincomb(s, X, Zb, N, K, r0.coeffs(), ytab, N, nrun, OW, x16);
   }
   if (steps & kStepRes) {
     if (r0.res_parts > 0) {  // r = b - A x fused into the matvec
