@@ -53,16 +53,17 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_slab_fd_unit128_p4_traffic.md")
-FD_SOURCE = os.path.join(ROOT, "paper_1705_04384_amd", "csrc", "fd_apply.hip")
+CSRC = os.path.join(ROOT, "paper_1705_04384_amd", "csrc")
 
 
-def measured_traffic():
-    """HBM bytes per k_slab launch from the committed counter summary, or None when the
-    summary is missing or was taken on a different version of the FD kernel source."""
+def measured_traffic(key="traffic_bytes_per_launch", source="fd_apply.hip"):
+    """HBM bytes per launch of a kernel (key) from the committed counter summary, or None
+    when the summary is missing or was taken on a different version of the kernel's
+    source file (source, locked by its sha256 in the summary)."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
-        src = hashlib.sha256(open(FD_SOURCE, "rb").read()).hexdigest()
+        src = hashlib.sha256(open(os.path.join(CSRC, source), "rb").read()).hexdigest()
     except OSError:
         return None
     vals = {}
@@ -71,10 +72,10 @@ def measured_traffic():
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("fd_apply.hip sha256") != src:
+    if vals.get(f"{source} sha256") != src:
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -457,11 +458,13 @@ def matvec_roofline(N, mv_launches, mv_kms, rs_launches, rs_kms, timed_every):
     if mv_launches:
         s = mv_kms / 1e3 / mv_launches
         out.update({"launches": mv_launches, "avg_launch_us": s * 1e6, "bytes_per_launch": 2 * N * 8,
-                    "achieved": 2 * N * 8 / s / 1e9, "frac": 2 * N * 8 / s / 1e9 / 8000.0})
+                    "achieved": 2 * N * 8 / s / 1e9, "frac": 2 * N * 8 / s / 1e9 / 8000.0,
+                    "traffic": measured_traffic("matvec_traffic_bytes_per_launch", "operator.hip")})
     if rs_launches:
         s = rs_kms / 1e3 / rs_launches
         out["residual_form"] = {"launches": rs_launches, "avg_launch_us": s * 1e6, "bytes_per_launch": 3 * N * 8,
-                                "achieved": 3 * N * 8 / s / 1e9, "frac": 3 * N * 8 / s / 1e9 / 8000.0}
+                                "achieved": 3 * N * 8 / s / 1e9, "frac": 3 * N * 8 / s / 1e9 / 8000.0,
+                                "traffic": measured_traffic("residual_traffic_bytes_per_launch", "operator.hip")}
     return out
 
 

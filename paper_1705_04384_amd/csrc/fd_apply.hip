@@ -118,6 +118,31 @@ __device__ inline void gemm_preloaded_a(int kpad, const double (&xa)[MT][KB][4],
   }
 }
 
+// The same, loading after the MFMAs of each k-block kb the A fragment kb of the next
+// contraction (load_next(kb)): its loads overlap this contraction, and its registers take
+// the place of the fragment just consumed.
+template <int MT, int NT, int KB, typename LoadB, typename LoadNext>
+__device__ inline void gemm_preloaded_a_next(int kpad, const double (&xa)[MT][KB][4], LoadB load_b,
+                                             dbl4 (&acc)[MT][NT], LoadNext load_next) {
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (kb * 16 >= kpad) break;
+    double bv[NT][4];
+    load_b(kb * 16, bv);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b) acc[a][b] = mfma(xa[a][kb][t], bv[b][t], acc[a][b]);
+    load_next(kb);
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // Pass A / C.  Workgroup = (slab s, column block cb) with WAVES waves; wave w owns rows
 // [w*MT*16, (w+1)*MT*16) of both contractions and all kNB columns.
@@ -162,9 +187,11 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
   const int kpad = (n + 15) & ~15;
 
   // with PRE, the wave's whole strip of X (its MT*16 rows, all columns) is loaded into
-  // registers first, so its HBM latency overlaps the W1 staging below
+  // registers first, together with the W1 staging below, and GEMM1 loads the W2 rows of
+  // GEMM2 as it consumes the strip: the pass waits for memory about twice instead of
+  // once per k-block
   constexpr int KB = PRE ? MPAD / 16 : 1;
-  double xa[MT][KB][4];
+  double xa[MT][KB][4], w2a[MT][KB][4];
   if (PRE) {
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
@@ -176,26 +203,45 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
       }
     }
   }
-  // stage W1[c0 .. c0+kNB)[0 .. kpad) (zero-padded rows and columns beyond n)
-  for (int e = threadIdx.x; e < kNB * (kpad / 2); e += NTHR) {
-    const int c = e / (kpad / 2), j = 2 * (e % (kpad / 2));
-    const double2 v = *reinterpret_cast<const double2 *>(W1 + (size_t)(c0 + c) * ldw + j);
-    buf[c * LDP + j] = v.x;
-    buf[c * LDP + j + 1] = v.y;
+  // stage W1[c0 .. c0+kNB)[0 .. kpad) (zero-padded rows and columns beyond n); every
+  // thread's loads are issued before the first LDS store (addresses clamped to the tile)
+  {
+    constexpr int SIT = (kNB * (MPAD / 2) + NTHR - 1) / NTHR;
+    const int half = kpad / 2, stot = kNB * half;
+    double2 sv[SIT];
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int e0 = (int)threadIdx.x + it * NTHR, e = e0 < stot ? e0 : stot - 1;
+      const int c = e / half, j = 2 * (e % half);
+      sv[it] = *reinterpret_cast<const double2 *>(W1 + (size_t)(c0 + c) * ldw + j);
+    }
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int e = (int)threadIdx.x + it * NTHR;
+      if (e < stot) {
+        const int c = e / half, j = 2 * (e % half);
+        buf[c * LDP + j] = sv[it].x;
+        buf[c * LDP + j + 1] = sv[it].y;
+      }
+    }
   }
   __syncthreads();
 
   // ---- GEMM1 ----
   dbl4 acc[MT][NT];
   if (PRE) {
-    gemm_preloaded_a<MT, NT, KB>(kpad, xa, [&](int j0, double (&bv)[NT][4]) {
+    gemm_preloaded_a_next<MT, NT, KB>(kpad, xa, [&](int j0, double (&bv)[NT][4]) {
       const int j = j0 + 4 * lg;
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
         const double *p = buf + (16 * b + li) * LDP + j;
         bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
       }
-    }, acc);
+    }, acc, [&](int kb) {
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+        load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + kb * 16 + 4 * lg, w2a[a][kb]);
+    });
   } else {
     gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
       const int j = j0 + 4 * lg;
@@ -221,16 +267,27 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
   __syncthreads();
 
   // ---- GEMM2 ----
-  gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
-    const int j = j0 + 4 * lg;
+  if (PRE) {
+    gemm_preloaded_a<MT, NT, KB>(kpad, w2a, [&](int j0, double (&bv)[NT][4]) {
+      const int j = j0 + 4 * lg;
 #pragma unroll
-    for (int a = 0; a < MT; ++a) load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + j, f.a[a]);
+      for (int b = 0; b < NT; ++b) {
+        const double *p = buf + (16 * b + li) * LDP + j;
+        bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
+      }
+    }, acc);
+  } else {
+    gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
+      const int j = j0 + 4 * lg;
 #pragma unroll
-    for (int b = 0; b < NT; ++b) {
-      const double *p = buf + (16 * b + li) * LDP + j;
-      f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
-    }
-  }, acc);
+      for (int a = 0; a < MT; ++a) load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + j, f.a[a]);
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        const double *p = buf + (16 * b + li) * LDP + j;
+        f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
+      }
+    }, acc);
+  }
 #pragma unroll
   for (int b = 0; b < NT; ++b) {
     const int c = c0 + 16 * b + li;
@@ -255,7 +312,7 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
 //   GEMM1: T[k3][c] = sum_i3 Wa[k3][i3] X[i3][c];   T /= lam3[k3] + lam2[i2] + lam1[i1]
 //   GEMM2: S[k3][c] = sum_k Wb[k3][k] T[k][c]        (T back in LDS, transposed)
 // ------------------------------------------------------------------------------------
-template <int WAVES, int MT, int NT, bool VEC>
+template <int WAVES, int MT, int NT, bool VEC, bool PRE>
 __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
                                                       const double *__restrict__ Wa, const double *__restrict__ Wb,
                                                       int ldw, int n, int ncb, const double *__restrict__ lam1,
@@ -276,17 +333,42 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
+  // with PRE, the wave's rows of Wa and Wb (the A operands of both contractions) are
+  // loaded into registers together with the staging loads below
+  constexpr int KB = PRE ? MPAD / 16 : 1;
+  double wa[MT][KB][4], wb[MT][KB][4];
+  if (PRE) {  // Wa now; Wb while GEMM1 consumes Wa
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+        load4_pad(Wa + (size_t)(m0 + 16 * a + li) * ldw + kb * 16 + 4 * lg, wa[a][kb]);
+  }
   // stage X[i3][c0 .. c0+kNB) -> xt[c][i3], zero beyond n or n^2 (VEC: n^2 % 4 == 0 and
-  // 32-byte aligned entries, four columns per load)
+  // 32-byte aligned entries, four columns per load; every thread's loads are issued at
+  // clamped addresses before the first LDS store)
   if (VEC) {
     constexpr int Q = kNB / 4;
-    for (int e = threadIdx.x; e < kpad * Q; e += NTHR) {
+    constexpr int SIT = (MPAD * Q + NTHR - 1) / NTHR;
+    dbl4 sv[SIT];
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int e = (int)threadIdx.x + it * NTHR;
       const int i3 = e / Q, q = e - i3 * Q;
       const int64_t cg = c0 + 4 * q;
-      dbl4 v = dbl4{0.0, 0.0, 0.0, 0.0};
-      if (i3 < n && cg < n2) v = *(gptr<const dbl4>)(Xb + (int64_t)i3 * n2 + cg);
+      const int i3c = i3 < n ? i3 : n - 1;
+      const int64_t cgc = cg < n2 ? cg : n2 - 4;
+      sv[it] = *(gptr<const dbl4>)(Xb + (int64_t)i3c * n2 + cgc);
+    }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = v[t];
+    for (int it = 0; it < SIT; ++it) {
+      const int e = (int)threadIdx.x + it * NTHR;
+      if (e < kpad * Q) {
+        const int i3 = e / Q, q = e - i3 * Q;
+        const bool ok = i3 < n && c0 + 4 * q < n2;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = ok ? sv[it][t] : 0.0;
+      }
     }
   } else {
     for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
@@ -297,6 +379,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   }
   __syncthreads();
   dbl4 acc[MT][NT];
+  auto lds_b = [&](int j0, double (&bv)[NT][4]) {
+    const int j = j0 + 4 * lg;
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      const double *p = xt + (16 * b + li) * LDP + j;
+      bv[b][0] = p[0]; bv[b][1] = p[1]; bv[b][2] = p[2]; bv[b][3] = p[3];
+    }
+  };
   auto lds_gemm = [&](const double *W) {
     gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
       const int j = j0 + 4 * lg;
@@ -309,7 +399,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
       }
     }, acc);
   };
-  lds_gemm(Wa);
+  if (PRE)
+    gemm_preloaded_a_next<MT, NT, KB>(kpad, wa, lds_b, acc, [&](int kb) {
+#pragma unroll
+      for (int a = 0; a < MT; ++a)
+        load4_pad(Wb + (size_t)(m0 + 16 * a + li) * ldw + kb * 16 + 4 * lg, wb[a][kb]);
+    });
+  else
+    lds_gemm(Wa);
   __syncthreads();  // every wave has finished reading xt
 #pragma unroll
   for (int b = 0; b < NT; ++b) {
@@ -327,7 +424,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
       }
   }
   __syncthreads();
-  lds_gemm(Wb);
+  if (PRE)
+    gemm_preloaded_a<MT, NT, KB>(kpad, wb, lds_b, acc);
+  else
+    lds_gemm(Wb);
 #pragma unroll
   for (int b = 0; b < NT; ++b) {
     const int64_t cg = c0 + 16 * b + li;
@@ -351,6 +451,21 @@ void launch_timed(K kernel, dim3 grid, dim3 blk, hipStream_t s, hipEvent_t ev0, 
     hipLaunchKernelGGL(kernel, grid, blk, 0, s, args...);
 }
 
+// The preloading forms (the A operands of a pass in registers, about two waits for memory
+// per pass instead of one per k-block) for the 16-column workgroups of n <= 64.  Measured
+// on MI355X (FP64 apply, us, pipelined -> preloading): 3D n = 32: 12.3 -> 11.4, 48: 14.6
+// -> 13.0, 64: 18.0 -> 16.1; n = 80: 31.8 -> 32.8 and 96: 55.5 -> 59.5 (there every
+// wave of a pass reaches its MFMAs at the same time, and the waits the preloading removes
+// were already overlapped by other workgroups).
+#ifndef FDG_FD_PRE_MAXN
+#define FDG_FD_PRE_MAXN 64
+#endif
+#ifndef FDG_FD_PRE_FIBRE_MAXN
+#define FDG_FD_PRE_FIBRE_MAXN 64
+#endif
+inline bool pre_ok(int n) { return n <= FDG_FD_PRE_MAXN; }
+inline bool pre_fibre_ok(int n) { return n <= FDG_FD_PRE_FIBRE_MAXN; }
+
 template <int WAVES, int MT, int NT>
 void slab_launch(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
                  int64_t nslab, int spe, bool div, const double *lam1, const double *lam2, bool aligned32,
@@ -361,21 +476,39 @@ void slab_launch(hipStream_t s, CBatch X, MBatch Y, const double *W1, const doub
   const int remap = (nslab % 8 == 0) ? 1 : 0;
   const bool vec = (n % 4 == 0) && aligned32;
   const dim3 grid((unsigned)nwg), blk(64 * WAVES);
-  constexpr bool PRE = false;  // preloading the X strip measured slower at n = 128
+  if (NT == 1 && pre_ok(n)) {
+    constexpr bool P = NT == 1 && WAVES * MT * 16 <= 96;
+    if (div) {
+      if (vec)
+        launch_timed(k_slab<WAVES, MT, NT, true, true, P>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+                     ncb, remap, lam1, lam2);
+      else
+        launch_timed(k_slab<WAVES, MT, NT, false, true, P>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+                     ncb, remap, lam1, lam2);
+    } else {
+      if (vec)
+        launch_timed(k_slab<WAVES, MT, NT, true, false, P>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+                     ncb, remap, lam1, lam2);
+      else
+        launch_timed(k_slab<WAVES, MT, NT, false, false, P>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+                     ncb, remap, lam1, lam2);
+    }
+    return;
+  }
   if (div) {
     if (vec)
-      launch_timed(k_slab<WAVES, MT, NT, true, true, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe, ncb,
-                   remap, lam1, lam2);
+      launch_timed(k_slab<WAVES, MT, NT, true, true, false>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+                   ncb, remap, lam1, lam2);
     else
-      launch_timed(k_slab<WAVES, MT, NT, false, true, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+      launch_timed(k_slab<WAVES, MT, NT, false, true, false>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
                    ncb, remap, lam1, lam2);
   } else {
     if (vec)
-      launch_timed(k_slab<WAVES, MT, NT, true, false, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
+      launch_timed(k_slab<WAVES, MT, NT, true, false, false>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
                    ncb, remap, lam1, lam2);
     else
-      launch_timed(k_slab<WAVES, MT, NT, false, false, PRE>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab, spe,
-                   ncb, remap, lam1, lam2);
+      launch_timed(k_slab<WAVES, MT, NT, false, false, false>, grid, blk, s, ev0, ev1, X, Y, W1, W2, ldw, n, nslab,
+                   spe, ncb, remap, lam1, lam2);
   }
 }
 
@@ -390,10 +523,22 @@ void fibre_launch(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const dou
   // 4-wide staging loads: every entry and every i3 row 32-byte aligned
   const bool vec = n2 % 4 == 0 && !X.ptrs && (reinterpret_cast<uintptr_t>(X.base) & 31) == 0 &&
                    (batch == 1 || X.stride % 4 == 0);
+  if (NT == 1 && pre_fibre_ok(n)) {
+    constexpr bool P = NT == 1 && WAVES * MT * 16 <= 96;
+    if (vec)
+      launch_timed(k_fibre<WAVES, MT, NT, true, P>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2,
+                   lam3);
+    else
+      launch_timed(k_fibre<WAVES, MT, NT, false, P>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2,
+                   lam3);
+    return;
+  }
   if (vec)
-    launch_timed(k_fibre<WAVES, MT, NT, true>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
+    launch_timed(k_fibre<WAVES, MT, NT, true, false>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2,
+                 lam3);
   else
-    launch_timed(k_fibre<WAVES, MT, NT, false>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2, lam3);
+    launch_timed(k_fibre<WAVES, MT, NT, false, false>, grid, blk, s, ev0, ev1, X, Y, Wa, Wb, ldw, n, ncb, lam1, lam2,
+                 lam3);
 }
 
 }  // namespace
@@ -411,10 +556,10 @@ struct Shape {
 };
 
 static Shape pick_shape(int n, bool small_grid) {
-#if defined(FDG_FD_FORCE_W) && defined(FDG_FD_FORCE_MT)
+#if defined(FDG_FD_FORCE_W) && defined(FDG_FD_FORCE_MT) && defined(FDG_FD_FORCE_NT)
   if (16 * FDG_FD_FORCE_W * FDG_FD_FORCE_MT >= ((n + 15) & ~15) &&
       16 * FDG_FD_FORCE_W * FDG_FD_FORCE_MT <= ((n + 63) / 64) * 64)
-    return {FDG_FD_FORCE_W, FDG_FD_FORCE_MT, 2};
+    return {FDG_FD_FORCE_W, FDG_FD_FORCE_MT, FDG_FD_FORCE_NT};
 #endif
   const int nt = (small_grid || n <= 96) ? 1 : 2;
   const int k = (n + 15) / 16;  // 16-row tiles needed
@@ -425,7 +570,7 @@ static Shape pick_shape(int n, bool small_grid) {
 }
 
 #define FDG_SHAPES(X)                                                                             \
-  X(4, 1, 1) X(5, 1, 1) X(6, 1, 1) X(7, 1, 1) X(8, 1, 1) X(8, 2, 1) X(12, 1, 1)                 \
+  X(4, 1, 1) X(5, 1, 1) X(6, 1, 1) X(7, 1, 1) X(8, 1, 1) X(8, 2, 1) X(12, 1, 1) \
   X(4, 1, 2) X(5, 1, 2) X(6, 1, 2) X(7, 1, 2) X(8, 1, 2) X(4, 2, 2) X(6, 2, 2) X(8, 2, 2) X(4, 3, 2) X(12, 1, 2)
 
 void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
