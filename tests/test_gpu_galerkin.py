@@ -237,6 +237,9 @@ def test_complex_pencil_fd_apply_matches_oracle(d, p, n, winds):
     torch = torch_cuda()
     ctx, Ms, KHs, npairs, cond = _blocks_context(fdg, d, p, n, winds)
     assert npairs > 0
+    # cond(U) of these cases is 66 .. 1.33e4 (host factorization, deterministic): bounded
+    # here so that the tolerance cannot grow loose unnoticed (tol <= 2.1e-9)
+    assert cond <= 2e4, cond
     tol = 1e-13 * cond + 1e-10
     b = inputs.rhs_normal(31, n ** d)
     s = torch.empty(n ** d, dtype=torch.float64, device="cuda")

@@ -167,3 +167,22 @@ def test_gpu_tolerances_catch_planted_mistakes(d, p, n):
             assert nm > 1.8 * GPU_TOL["bf16"][1], (mx, nm)
         finally:
             reduced.u_order = orig_order
+
+
+@pytest.mark.parametrize("d,p,n", [(3, 6, 24), (2, 6, 96)])
+def test_column_balancing_leaves_the_bf16_error(d, p, n):
+    """The FD is invariant under U_l -> U_l S^-1, V_l -> V_l S for diagonal S, so the
+    columns of U and V could be balanced before the BF16 rounding.  BF16 keeps FP32's
+    exponent range and rounds each value relative to its own magnitude, so balancing does
+    not lower the BF16 error of the apply (it moves it by -10% to +30% here, while the
+    columns of V span a factor of about 10 in 2-norm): it cannot cut the BF16 iteration
+    count."""
+    Us, Vs, lams, b = _real_problem(d, p, n)
+    U, V, lam = Us[0], Vs[0], lams[0]
+    s64 = fd.fd_apply(Us, Vs, lams, b)
+    e0 = np.linalg.norm(reduced.fd_apply_reduced(Us, Vs, lams, b, "bf16") - s64) / np.linalg.norm(s64)
+    for sc in (1.0 / np.linalg.norm(V, axis=0), np.sqrt(np.linalg.norm(U, axis=0) / np.linalg.norm(V, axis=0))):
+        Ub, Vb = U / sc, V * sc
+        assert np.linalg.norm(fd.fd_apply([Ub] * d, [Vb] * d, lams, b) - s64) <= 1e-13 * np.linalg.norm(s64)
+        e = np.linalg.norm(reduced.fd_apply_reduced([Ub] * d, [Vb] * d, lams, b, "bf16") - s64) / np.linalg.norm(s64)
+        assert 0.9 * e0 <= e <= 1.5 * e0, (e, e0)
