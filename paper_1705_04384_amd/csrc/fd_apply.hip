@@ -74,24 +74,29 @@ __device__ inline void mma_block(const Frag<MT, NT> &f, dbl4 (&acc)[MT][NT]) {
       for (int b = 0; b < NT; ++b) acc[a][b] = mfma(f.a[a][t], f.b[b][t], acc[a][b]);
 }
 
-// acc = sum over k-blocks j0 = 0, 16, .., kpad-16 of load(j0); the next block's operands are
-// loaded before the current block's MFMAs are issued (two register buffers).
-template <int MT, int NT, typename Load>
+// acc = sum over k-blocks j0 = 0, 16, .., kpad-16 of load(j0), for kpad <= 16 KB; the
+// operands of block kb + PD are loaded before block kb's MFMAs are issued (PD + 1 register
+// buffers).  The loop is unrolled over the KB blocks the workgroup shape allows and every
+// load is issued unconditionally (load must stay in bounds for every j0 < 16 KB), so the
+// compiler waits for exactly the loads a block needs; a rolled loop with conditional
+// loads made it wait for all outstanding loads before every block.
+#ifndef FDG_FD_PD
+#define FDG_FD_PD 1
+#endif
+template <int MT, int NT, int KB, typename Load>
 __device__ inline void gemm_pipelined(int kpad, Load load, dbl4 (&acc)[MT][NT]) {
+  constexpr int PD = FDG_FD_PD < KB ? FDG_FD_PD : KB;
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-  Frag<MT, NT> f0, f1;
-  load(0, f0);
-  for (int j0 = 0; j0 < kpad; j0 += 32) {
-    const bool has1 = j0 + 16 < kpad;
-    if (has1) load(j0 + 16, f1);
-    mma_block<MT, NT>(f0, acc);
-    if (has1) {
-      if (j0 + 32 < kpad) load(j0 + 32, f0);
-      mma_block<MT, NT>(f1, acc);
-    }
+  Frag<MT, NT> f[PD + 1];
+#pragma unroll
+  for (int p = 0; p < PD; ++p) load(16 * p, f[p]);
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (kb + PD < KB) load(16 * (kb + PD), f[(kb + PD) % (PD + 1)]);
+    if (16 * kb < kpad) mma_block<MT, NT>(f[kb % (PD + 1)], acc);
   }
 }
 
@@ -243,12 +248,21 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
         load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + kb * 16 + 4 * lg, w2a[a][kb]);
     });
   } else {
-    gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
+    gemm_pipelined<MT, NT, MPAD / 16>(kpad, [&](int j0, Frag<MT, NT> &f) {
       const int j = j0 + 4 * lg;
 #pragma unroll
       for (int a = 0; a < MT; ++a) {
         const int row = m0 + 16 * a + li;
-        load4<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
+        if (VEC) {
+          // 4-wide at clamped addresses, no branch: an element beyond the slab's n columns
+          // meets a zero of the zero-padded W1 tile, and a padding row of Y1 a zero column
+          // of W2 in GEMM2, so clamped values never reach the result
+          const int rowc = row < n ? row : n - 1, jc = j < n ? j : n - 4;
+          const dbl4 x = *(gptr<const dbl4>)(Xs + (int64_t)rowc * n + jc);
+          f.a[a][0] = x[0]; f.a[a][1] = x[1]; f.a[a][2] = x[2]; f.a[a][3] = x[3];
+        } else {
+          load4<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
+        }
       }
 #pragma unroll
       for (int b = 0; b < NT; ++b) {
@@ -277,7 +291,7 @@ __global__ __launch_bounds__(64 * WAVES, PRE ? 2 : 1) void k_slab(CBatch X, MBat
       }
     }, acc);
   } else {
-    gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
+    gemm_pipelined<MT, NT, MPAD / 16>(kpad, [&](int j0, Frag<MT, NT> &f) {
       const int j = j0 + 4 * lg;
 #pragma unroll
       for (int a = 0; a < MT; ++a) load4_pad(W2 + (size_t)(m0 + 16 * a + li) * ldw + j, f.a[a]);
@@ -333,6 +347,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
+  // the eigenvalues of the divide, loaded with the first loads of the pass (a load used
+  // right after it is issued would be waited for on its own)
+  double lv3[MT][4], lv2[NT], lv1[NT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lv3[a][r] = lam3[m0 + 16 * a + lg + 4 * r];
+#pragma unroll
+  for (int b = 0; b < NT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    const bool cok = cg < n2;
+    lv2[b] = lam2[cok ? (int)(cg / n) : 0];
+    lv1[b] = lam1[cok ? (int)(cg % n) : 0];
+  }
   // with PRE, the wave's rows of Wa and Wb (the A operands of both contractions) are
   // loaded into registers together with the staging loads below
   constexpr int KB = PRE ? MPAD / 16 : 1;
@@ -388,7 +416,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
     }
   };
   auto lds_gemm = [&](const double *W) {
-    gemm_pipelined<MT, NT>(kpad, [&](int j0, Frag<MT, NT> &f) {
+    gemm_pipelined<MT, NT, MPAD / 16>(kpad, [&](int j0, Frag<MT, NT> &f) {
       const int j = j0 + 4 * lg;
 #pragma unroll
       for (int a = 0; a < MT; ++a) load4_pad(W + (size_t)(m0 + 16 * a + li) * ldw + j, f.a[a]);
@@ -410,17 +438,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre(CBatch X, MBatch Y,
   __syncthreads();  // every wave has finished reading xt
 #pragma unroll
   for (int b = 0; b < NT; ++b) {
-    const int64_t cg = c0 + 16 * b + li;
-    const bool cok = cg < n2;
-    const int i2 = cok ? (int)(cg / n) : 0, i1 = cok ? (int)(cg % n) : 0;
-    const double l12 = lam2[i2] + lam1[i1];
+    const double l12 = lv2[b] + lv1[b];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int k3 = m0 + 16 * a + lg + 4 * r;
         // rows k3 >= n are zero (zero-padded Wa); lam3 is padded with 1
-        xt[(16 * b + li) * LDP + k3] = acc[a][b][r] / (lam3[k3] + l12);
+        xt[(16 * b + li) * LDP + k3] = acc[a][b][r] / (lv3[a][r] + l12);
       }
   }
   __syncthreads();

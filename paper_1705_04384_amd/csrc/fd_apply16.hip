@@ -86,24 +86,23 @@ __device__ inline void mma_block16(const Frag16<MT, NT> &f, flt4 (&acc)[MT][NT])
     for (int b = 0; b < NT; ++b) acc[a][b] = mfma16(f.a[a], f.b[b], acc[a][b]);
 }
 
-// acc = sum over the 32-wide k-blocks j0 = 0, 32, .., kpad - 32 of load(j0); the next
-// block's operands are loaded before the current block's MFMAs (two register buffers).
-template <int MT, int NT, typename Load>
+// acc = sum over the 32-wide k-blocks j0 = 0, 32, .., kpad - 32 (kpad <= 32 KB) of
+// load(j0); block kb + 1's operands are loaded before block kb's MFMAs, in a loop unrolled
+// over the KB blocks with unconditional loads (load stays in bounds for every j0 < 32 KB),
+// so that the compiler waits for exactly the loads a block needs (a rolled loop with
+// conditional loads waited for all of them).
+template <int MT, int NT, int KB, typename Load>
 __device__ inline void gemm16(int kpad, Load load, flt4 (&acc)[MT][NT]) {
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
-  Frag16<MT, NT> f0, f1;
-  load(0, f0);
-  for (int j0 = 0; j0 < kpad; j0 += 64) {
-    const bool has1 = j0 + 32 < kpad;
-    if (has1) load(j0 + 32, f1);
-    mma_block16<MT, NT>(f0, acc);
-    if (has1) {
-      if (j0 + 64 < kpad) load(j0 + 64, f0);
-      mma_block16<MT, NT>(f1, acc);
-    }
+  Frag16<MT, NT> f[2];
+  load(0, f[0]);
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (kb + 1 < KB) load(32 * (kb + 1), f[(kb + 1) & 1]);
+    if (32 * kb < kpad) mma_block16<MT, NT>(f[kb & 1], acc);
   }
 }
 
@@ -191,7 +190,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab16(const TI *__restrict__ X,
 #pragma unroll
       for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + 4 * lg + r] = to_bf16_once(acc[a][b][r]);
   __syncthreads();
-  gemm16<MT, NT>(kpad, [&](int j0, Frag16<MT, NT> &f) {
+  gemm16<MT, NT, MPAD / 32>(kpad, [&](int j0, Frag16<MT, NT> &f) {
     const int j = j0 + 8 * lg;
 #pragma unroll
     for (int a = 0; a < MT; ++a) f.a[a] = load8_bf(W2 + (size_t)(m0 + 16 * a + li) * ldw + j);
@@ -239,15 +238,43 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 31) & ~31;
-  if (VEC) {  // n^2 % 4 == 0 and a 16-byte aligned X: four columns per load
+  // the eigenvalues of the divide, loaded with the first loads of the pass (a load used
+  // right after it is issued would be waited for on its own)
+  float lv3[MT][4], lv2[NT], lv1[NT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lv3[a][r] = lam3[m0 + 16 * a + 4 * lg + r];
+#pragma unroll
+  for (int b = 0; b < NT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    const bool cok = cg < n2;
+    lv2[b] = lam2[cok ? (int)(cg / n) : 0];
+    lv1[b] = lam1[cok ? (int)(cg % n) : 0];
+  }
+  if (VEC) {  // n^2 % 4 == 0 and a 16-byte aligned X: four columns per load, every load of
+             // the thread issued (at clamped addresses) before the first LDS store
     constexpr int Q = kNB / 4;
-    for (int e = threadIdx.x; e < kpad * Q; e += NTHR) {
+    constexpr int SIT = (MPAD * Q + NTHR - 1) / NTHR;
+    flt4 sv[SIT];
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int e = (int)threadIdx.x + it * NTHR;
       const int i3 = e / Q, q = e - i3 * Q;
       const int64_t cg = c0 + 4 * q;
-      flt4 v = flt4{0.f, 0.f, 0.f, 0.f};
-      if (i3 < n && cg < n2) v = *reinterpret_cast<const flt4 *>(Xb + (int64_t)i3 * n2 + cg);
+      const int i3c = i3 < n ? i3 : n - 1;
+      const int64_t cgc = cg < n2 ? cg : n2 - 4;
+      sv[it] = *reinterpret_cast<const flt4 *>(Xb + (int64_t)i3c * n2 + cgc);
+    }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = to_bf16_once(v[t]);
+    for (int it = 0; it < SIT; ++it) {
+      const int e = (int)threadIdx.x + it * NTHR;
+      if (e < kpad * Q) {
+        const int i3 = e / Q, q = e - i3 * Q;
+        const bool ok = i3 < n && c0 + 4 * q < n2;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = to_bf16_once(ok ? sv[it][t] : 0.0f);
+      }
     }
   } else {
     for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
@@ -259,7 +286,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
   __syncthreads();
   flt4 acc[MT][NT];
   auto lds_gemm = [&](const __bf16 *W) {
-    gemm16<MT, NT>(kpad, [&](int j0, Frag16<MT, NT> &f) {
+    gemm16<MT, NT, MPAD / 32>(kpad, [&](int j0, Frag16<MT, NT> &f) {
       const int j = j0 + 8 * lg;
 #pragma unroll
       for (int a = 0; a < MT; ++a) f.a[a] = load8_bf(W + (size_t)(m0 + 16 * a + li) * ldw + j);
@@ -271,19 +298,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
   __syncthreads();  // every wave is done with the staged block
 #pragma unroll
   for (int b = 0; b < NT; ++b) {
-    const int64_t cg = c0 + 16 * b + li;
-    const bool cok = cg < n2;
-    const int i2 = cok ? (int)(cg / n) : 0, i1 = cok ? (int)(cg % n) : 0;
-    const float l12 = lam2[i2] + lam1[i1];
+    const float l12 = lv2[b] + lv1[b];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int k3 = m0 + 16 * a + 4 * lg + r;
         // rows k3 >= n are zero (zero-padded Wa); lam3 is padded with 1
-        xt[(16 * b + li) * LDP + k3] = to_bf16_once(acc[a][b][r] / (lam3[k3] + l12));
+        xt[(16 * b + li) * LDP + k3] = to_bf16_once(acc[a][b][r] / (lv3[a][r] + l12));
       }
   }
+
   __syncthreads();
   lds_gemm(Wb);
 #pragma unroll

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fd_apply.h"
 
@@ -56,38 +57,41 @@ __device__ inline void load4v(const T *p, int j, int jmax, bool ok, float (&v)[4
   load4f(p, j, jmax, ok, v);
 }
 
-template <int MT, int NT>
+// Operands of one 16-wide k-block: A as loaded (TA: float, or the FP64 input of the first
+// pass, rounded to FP32 where the MFMA takes it, so that the next k-block's loads are
+// issued before this one's values are used), B from LDS.
+template <int MT, int NT, typename TA = float>
 struct Frag32 {
-  float a[MT][4];
+  TA a[MT][4];
   float b[NT][4];
 };
 
-template <int MT, int NT>
-__device__ inline void mma_block32(const Frag32<MT, NT> &f, flt4 (&acc)[MT][NT]) {
+template <int MT, int NT, typename TA>
+__device__ inline void mma_block32(const Frag32<MT, NT, TA> &f, flt4 (&acc)[MT][NT]) {
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
-      for (int b = 0; b < NT; ++b) acc[a][b] = mfma32(f.a[a][t], f.b[b][t], acc[a][b]);
+      for (int b = 0; b < NT; ++b) acc[a][b] = mfma32((float)f.a[a][t], f.b[b][t], acc[a][b]);
 }
 
-template <int MT, int NT, typename Load>
+// acc = sum over the 16-wide k-blocks below kpad <= 16 KB; block kb + 1's operands are
+// loaded before block kb's MFMAs, in a loop unrolled over the KB blocks with unconditional
+// loads (load stays in bounds for every j0 < 16 KB), so that the compiler waits for exactly
+// the loads a block needs (a rolled loop with conditional loads waited for all of them).
+template <int MT, int NT, int KB, typename TA = float, typename Load>
 __device__ inline void gemm32(int kpad, Load load, flt4 (&acc)[MT][NT]) {
 #pragma unroll
   for (int a = 0; a < MT; ++a)
 #pragma unroll
     for (int b = 0; b < NT; ++b) acc[a][b] = flt4{0.f, 0.f, 0.f, 0.f};
-  Frag32<MT, NT> f0, f1;
-  load(0, f0);
-  for (int j0 = 0; j0 < kpad; j0 += 32) {
-    const bool has1 = j0 + 16 < kpad;
-    if (has1) load(j0 + 16, f1);
-    mma_block32<MT, NT>(f0, acc);
-    if (has1) {
-      if (j0 + 32 < kpad) load(j0 + 32, f0);
-      mma_block32<MT, NT>(f1, acc);
-    }
+  Frag32<MT, NT, TA> f[2];
+  load(0, f[0]);
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    if (kb + 1 < KB) load(16 * (kb + 1), f[(kb + 1) & 1]);
+    if (16 * kb < kpad) mma_block32<MT, NT>(f[kb & 1], acc);
   }
 }
 
@@ -128,25 +132,64 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
   const int c0 = cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
-  for (int e = threadIdx.x; e < kNB * kpad; e += NTHR) {
-    const int c = e / kpad, j = e - c * kpad;
-    buf[c * LDP + j] = W1[(size_t)(c0 + c) * ldw + j];
+  {  // W1 column tile, 4-wide: every load of the thread issued before the first LDS store
+    constexpr int SIT = (kNB * (MPAD / 4) + NTHR - 1) / NTHR;
+    const int q4 = kpad / 4, stot = kNB * q4;
+    flt4 sv[SIT];
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int e0 = (int)threadIdx.x + it * NTHR, e = e0 < stot ? e0 : stot - 1;
+      const int c = e / q4, j = 4 * (e - c * q4);
+      sv[it] = *reinterpret_cast<const flt4 *>(W1 + (size_t)(c0 + c) * ldw + j);
+    }
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int e = (int)threadIdx.x + it * NTHR;
+      if (e < stot) {
+        const int c = e / q4, j = 4 * (e - c * q4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) buf[c * LDP + j + t] = sv[it][t];
+      }
+    }
   }
   __syncthreads();
   flt4 acc[MT][NT];
-  gemm32<MT, NT>(kpad, [&](int j0, Frag32<MT, NT> &f) {
-    const int j = j0 + 4 * lg;
+  if constexpr (VEC) {
+    // A loaded 4-wide at clamped addresses with no branch (its values are rounded to FP32
+    // only where the MFMA takes them): an element beyond the slab's n columns or rows
+    // meets a zero of the zero-padded W1 tile in GEMM1, and a padding row of Y1 a zero
+    // column of W2 in GEMM2, so the clamped values never reach the result
+    gemm32<MT, NT, MPAD / 16, TI>(kpad, [&](int j0, Frag32<MT, NT, TI> &f) {
+      const int j = j0 + 4 * lg, jc = j < n ? j : n - 4;
 #pragma unroll
-    for (int a = 0; a < MT; ++a) {
-      const int row = m0 + 16 * a + li;
-      load4v<VEC>(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
-    }
+      for (int a = 0; a < MT; ++a) {
+        const int row = m0 + 16 * a + li, rowc = row < n ? row : n - 1;
+        typedef typename std::conditional<sizeof(TI) == 8, dbl4, flt4>::type V4;
+        const V4 x = *reinterpret_cast<const V4 *>(Xs + (int64_t)rowc * n + jc);
 #pragma unroll
-    for (int b = 0; b < NT; ++b) {
-      const float *p = buf + (16 * b + li) * LDP + j;
-      f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
-    }
-  }, acc);
+        for (int t = 0; t < 4; ++t) f.a[a][t] = x[t];
+      }
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        const float *p = buf + (16 * b + li) * LDP + j;
+        f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
+      }
+    }, acc);
+  } else {
+    gemm32<MT, NT, MPAD / 16>(kpad, [&](int j0, Frag32<MT, NT> &f) {
+      const int j = j0 + 4 * lg;
+#pragma unroll
+      for (int a = 0; a < MT; ++a) {
+        const int row = m0 + 16 * a + li;
+        load4f(Xs + (int64_t)row * n + j, j, n, row < n, f.a[a]);
+      }
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        const float *p = buf + (16 * b + li) * LDP + j;
+        f.b[b][0] = p[0]; f.b[b][1] = p[1]; f.b[b][2] = p[2]; f.b[b][3] = p[3];
+      }
+    }, acc);
+  }
   __syncthreads();
 #pragma unroll
   for (int a = 0; a < MT; ++a)
@@ -155,7 +198,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab32(const TI *__restrict__ X,
 #pragma unroll
       for (int r = 0; r < 4; ++r) buf[(16 * b + li) * LDP + m0 + 16 * a + 4 * lg + r] = acc[a][b][r];
   __syncthreads();
-  gemm32<MT, NT>(kpad, [&](int j0, Frag32<MT, NT> &f) {
+  gemm32<MT, NT, MPAD / 16>(kpad, [&](int j0, Frag32<MT, NT> &f) {
     const int j = j0 + 4 * lg;
 #pragma unroll
     for (int a = 0; a < MT; ++a) {
@@ -208,15 +251,43 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 15) & ~15;
-  if (VEC) {  // n^2 % 4 == 0 and a 16-byte aligned X: four columns per load
+  // the eigenvalues of the divide, loaded with the first loads of the pass (a load used
+  // right after it is issued would be waited for on its own)
+  float lv3[MT][4], lv2[NT], lv1[NT];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) lv3[a][r] = lam3[m0 + 16 * a + 4 * lg + r];
+#pragma unroll
+  for (int b = 0; b < NT; ++b) {
+    const int64_t cg = c0 + 16 * b + li;
+    const bool cok = cg < n2;
+    lv2[b] = lam2[cok ? (int)(cg / n) : 0];
+    lv1[b] = lam1[cok ? (int)(cg % n) : 0];
+  }
+  if (VEC) {  // n^2 % 4 == 0 and a 16-byte aligned X: four columns per load, every load of
+             // the thread issued (at clamped addresses) before the first LDS store
     constexpr int Q = kNB / 4;
-    for (int e = threadIdx.x; e < kpad * Q; e += NTHR) {
+    constexpr int SIT = (MPAD * Q + NTHR - 1) / NTHR;
+    flt4 sv[SIT];
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int e = (int)threadIdx.x + it * NTHR;
       const int i3 = e / Q, q = e - i3 * Q;
       const int64_t cg = c0 + 4 * q;
-      flt4 v = flt4{0.f, 0.f, 0.f, 0.f};
-      if (i3 < n && cg < n2) v = *reinterpret_cast<const flt4 *>(Xb + (int64_t)i3 * n2 + cg);
+      const int i3c = i3 < n ? i3 : n - 1;
+      const int64_t cgc = cg < n2 ? cg : n2 - 4;
+      sv[it] = *reinterpret_cast<const flt4 *>(Xb + (int64_t)i3c * n2 + cgc);
+    }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = v[t];
+    for (int it = 0; it < SIT; ++it) {
+      const int e = (int)threadIdx.x + it * NTHR;
+      if (e < kpad * Q) {
+        const int i3 = e / Q, q = e - i3 * Q;
+        const bool ok = i3 < n && c0 + 4 * q < n2;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = ok ? sv[it][t] : 0.0f;
+      }
     }
   } else {
     for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
@@ -228,7 +299,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
   __syncthreads();
   flt4 acc[MT][NT];
   auto lds_gemm = [&](const float *W) {
-    gemm32<MT, NT>(kpad, [&](int j0, Frag32<MT, NT> &f) {
+    gemm32<MT, NT, MPAD / 16>(kpad, [&](int j0, Frag32<MT, NT> &f) {
       const int j = j0 + 4 * lg;
 #pragma unroll
       for (int a = 0; a < MT; ++a) {
@@ -246,18 +317,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre32(const float *__restrict_
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NT; ++b) {
-    const int64_t cg = c0 + 16 * b + li;
-    const bool cok = cg < n2;
-    const int i2 = cok ? (int)(cg / n) : 0, i1 = cok ? (int)(cg % n) : 0;
-    const float l12 = lam2[i2] + lam1[i1];
+    const float l12 = lv2[b] + lv1[b];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int k3 = m0 + 16 * a + 4 * lg + r;
-        xt[(16 * b + li) * LDP + k3] = acc[a][b][r] / (lam3[k3] + l12);  // lam3 padded with 1
+        xt[(16 * b + li) * LDP + k3] = acc[a][b][r] / (lv3[a][r] + l12);  // lam3 padded with 1
       }
   }
+
   __syncthreads();
   lds_gemm(Wb);
 #pragma unroll
