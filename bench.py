@@ -120,6 +120,9 @@ def _serving(count):
         out[f"open_loop_{frac}"] = {"rate_per_s": rate, "served": serve.summarize(r_s, m_s),
                                     "one_by_one": serve.summarize(r_o, m_o)}
     out["server"]["stats"] = srv.stats()
+    out["context_memory"] = {"held_gib": cache.held_bytes() / 2**30,
+                             "shared_workspace_gib": cache.ws_buf.numel() / 2**30,
+                             "workspace_grows": cache.ws_grows}
     cache.close()
     cold = serve.FactorCache(threads=16)
     rate = 0.8 * sat["solves_per_s"]

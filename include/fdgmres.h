@@ -283,6 +283,38 @@ size_t fdg_operator_bytes(const fdg_ctx *ctx);
  * (factors, operator excluded for CSR, Krylov bases, scratch). */
 size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart);
 
+/* Device memory the context owns now, as allocated: *held = everything (factors in
+ * three precisions, operator data, solve and apply workspace); *workspace = the part
+ * fdg_release_workspace would return (apply buffers, Krylov bases V and Z, reduction
+ * partials, BiCGStab vectors; 0 while a caller's buffer is attached).  Either pointer may be NULL.  FDG_EINVAL for a NULL
+ * context, FDG_EHIP if the runtime cannot size an allocation. */
+int fdg_ctx_bytes(const fdg_ctx *ctx, size_t *held, size_t *workspace);
+
+/* Waits for the context's stream, then frees its solve and apply workspace (device
+ * buffers and the host-mapped scalar slots); factors and operator stay.  The next apply,
+ * matvec or solve allocates them again, so a cache of many contexts can bound the memory
+ * its idle ones hold.  Requests of the context already admitted to a server are not
+ * affected (they use the server's arena).  FDG_EINVAL for a NULL context. */
+int fdg_release_workspace(fdg_ctx *ctx);
+
+/* Bytes of a buffer that fdg_attach_workspace accepts for contexts of this shape and
+ * solves with restart <= the given one (apply buffers in FP64 and FP32, the flexible
+ * GMRES bases V and Z sharing one region with the BiCGStab vectors, reduction partials),
+ * 0 for an invalid shape. */
+size_t fdg_workspace_bytes(int d, int n, int batch, int restart);
+
+/* Makes the context carve its solve and apply workspace from a caller's device buffer of
+ * `bytes` bytes (256-byte aligned, at least fdg_workspace_bytes(d, n, batch, restart))
+ * instead of allocating its own, after waiting for its stream and freeing what it owned;
+ * dev = NULL detaches (own allocations again on next use).  The buffer stays the
+ * caller's: it must outlive the attachment and must not be written by anything else while
+ * a call of the context runs.  Several contexts may share one buffer provided their calls
+ * never overlap in time (fdg_solve and fdg_bicgstab return with the stream drained;
+ * fdg_apply_prec and fdg_matvec do not, so order them on one stream or synchronize).
+ * A solve with a restart above the attached one fails with FDG_EINVAL.  FDG_EINVAL for a
+ * NULL context, a misaligned or too small buffer, or restart outside [1, 10000]. */
+int fdg_attach_workspace(fdg_ctx *ctx, void *dev, size_t bytes, int restart);
+
 /* Per-kernel timing with HIP events on the context stream for every launch of the named
  * kernel class while enabled (FD passes: events recorded by the kernel dispatch itself;
  * other classes: events around the launch).  kernel: 0 = FD slab passes (modes 1 and 2 of

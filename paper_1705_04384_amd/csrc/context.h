@@ -70,6 +70,10 @@ struct fdg_ctx {
   double *bicg = nullptr;          // BiCGStab vectors and partials (allocated on first use)
   double *bicg_host = nullptr;     // BiCGStab host-mapped scalars and its device address
   double *bicg_host_dev = nullptr;
+  // workspace carved from a caller's buffer (fdg_attach_workspace) instead of owned:
+  // the device pointers above then point into it and are never freed here
+  char *ext_ws = nullptr;
+  int ext_restart = 0;
   fdg::TimerState timers[fdg::kTimerClasses];
 };
 

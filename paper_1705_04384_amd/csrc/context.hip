@@ -16,6 +16,7 @@
 #include "mapped.h"
 #include "kernels.h"
 #include "modeprod.h"
+#include "reduce.h"
 #include "solve_run.h"
 
 using namespace fdg;
@@ -360,6 +361,17 @@ int ctx_matvec(fdg_ctx *c, const double *x, double *y) {
 namespace {
 
 int ensure_krylov(fdg_ctx *c, int m) {
+  if (c->ext_ws) {  // bases carved at attach for restarts up to ext_restart; slots owned
+    if (m > c->ext_restart)
+      return set_error(FDG_EINVAL, "solve: restart %d exceeds the %d of the attached workspace", m,
+                       c->ext_restart);
+    if (c->hpin) return FDG_OK;
+    HIPCHK(hipHostMalloc((void **)&c->hpin, sizeof(double) * 2 * (size_t)host_doubles(c->ext_restart) * c->batch,
+                         hipHostMallocMapped));
+    HIPCHK(hipHostGetDevicePointer((void **)&c->hpin_dev, c->hpin, 0));
+    c->restart_alloc = c->ext_restart;
+    return FDG_OK;
+  }
   if (c->restart_alloc >= m) return FDG_OK;
   dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol);
   dfree(c->hbuf); dfree(c->scal);
@@ -421,6 +433,152 @@ extern "C" int fdg_create(fdg_ctx **out, int d, const int32_t *n, int batch, voi
   return FDG_OK;
 }
 
+namespace {
+
+// Apply buffers, Krylov bases, partials, BiCGStab vectors and the host-mapped slots; each
+// is allocated again on its next use (dalloc skips only non-null pointers).  Carved
+// pointers into an attached buffer are dropped, not freed.
+void free_workspace(fdg_ctx *c) {
+  if (c->ext_ws) {
+    c->t1 = c->t2 = c->Vb = c->Zb = c->P1 = c->P2 = c->P3 = c->Hcol = c->hbuf = c->scal = c->bicg = nullptr;
+    c->t32a = c->t32b = nullptr;
+    c->ext_ws = nullptr;
+    c->ext_restart = 0;
+  } else {
+    dfree(c->t1); dfree(c->t2);
+    if (c->t32a) (void)hipFree(c->t32a);
+    if (c->t32b) (void)hipFree(c->t32b);
+    c->t32a = c->t32b = nullptr;
+    dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol);
+    dfree(c->hbuf); dfree(c->scal);
+    dfree(c->bicg);
+  }
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  c->hpin = c->hpin_dev = nullptr;
+  c->restart_alloc = 0;
+  if (c->bicg_host) (void)hipHostFree(c->bicg_host);
+  c->bicg_host = c->bicg_host_dev = nullptr;
+}
+
+// Adds the size of the device allocation at p (0 for NULL) to *sum.
+int add_size(const void *p, size_t *sum) {
+  if (!p) return FDG_OK;
+  size_t sz = 0;
+  int st = hip_check(hipMemPtrGetInfo(const_cast<void *>(p), &sz), "hipMemPtrGetInfo");
+  if (st == FDG_OK) *sum += sz;
+  return st;
+}
+
+// Byte offsets of the workspace regions in an attached buffer, each with the same 256
+// bytes of slack as an owned allocation and 256-byte aligned.  The FGMRES bases (V, Z)
+// and the BiCGStab vectors share one region: a context runs one call at a time and each
+// call writes these vectors before reading them.
+struct WsLayout {
+  size_t t1, t2, t32a, t32b, krylov, zoff, P1, P2, P3, Hcol, hbuf, scal, total;
+};
+
+WsLayout ws_layout(int64_t N, int batch, int m) {
+  WsLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 256 + 255) / 256 * 256;
+    return at;
+  };
+  const size_t NB = (size_t)N * batch;
+  const size_t G = (size_t)reduction_blocks(N);
+  L.t1 = take(NB * 8);
+  L.t2 = take(NB * 8);
+  L.t32a = take(NB * 4);
+  L.t32b = take(NB * 4);
+  L.zoff = (NB * (m + 1) * 8 + 256 + 255) / 256 * 256;  // Z as aligned as an owned allocation
+  L.krylov = take(std::max(L.zoff + NB * m * 8, (8 * (size_t)N + 8 * (size_t)kMaxG + 64) * 8));
+  L.P1 = take(G * (m + 1) * batch * 8);
+  L.P2 = take(G * (m + 1) * batch * 8);
+  L.P3 = take(G * batch * 8);
+  L.Hcol = take((size_t)(m + 2) * batch * 8);
+  L.hbuf = take((size_t)2 * (m + 2) * batch * 8);
+  L.scal = take((size_t)4 * batch * 8);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" int fdg_ctx_bytes(const fdg_ctx *c, size_t *held, size_t *workspace) {
+  clear_error();
+  if (!c) return set_error(FDG_EINVAL, "ctx_bytes: NULL context");
+  size_t ws = 0, fixed = 0;
+  int st = FDG_OK;
+  if (!c->ext_ws)
+    for (const void *p : {(const void *)c->t1, (const void *)c->t2, (const void *)c->t32a, (const void *)c->t32b,
+                          (const void *)c->Vb, (const void *)c->Zb, (const void *)c->P1, (const void *)c->P2,
+                          (const void *)c->P3, (const void *)c->Hcol, (const void *)c->hbuf,
+                          (const void *)c->scal, (const void *)c->bicg})
+      if (st == FDG_OK) st = add_size(p, &ws);
+  for (int l = 0; l < 3 && st == FDG_OK; ++l)
+    for (const void *p : {(const void *)c->Wv[l], (const void *)c->Wu[l], (const void *)c->lam[l],
+                          (const void *)c->Wv32[l], (const void *)c->Wu32[l], (const void *)c->Wv16[l],
+                          (const void *)c->Wu16[l], (const void *)c->lam32[l], (const void *)c->bandM[l],
+                          (const void *)c->bandK[l], (const void *)c->bandD[l], (const void *)c->bandlo[l],
+                          (const void *)c->mu[l], (const void *)c->role[l], (const void *)c->bstart[l]})
+      if (st == FDG_OK) st = add_size(p, &fixed);
+  for (const void *p : {(const void *)c->fields, (const void *)c->ell_col, (const void *)c->ell_val,
+                        (const void *)c->ell_lo})
+    if (st == FDG_OK) st = add_size(p, &fixed);
+  if (st != FDG_OK) return st;
+  if (held) *held = fixed + ws;
+  if (workspace) *workspace = ws;
+  return FDG_OK;
+}
+
+extern "C" int fdg_release_workspace(fdg_ctx *c) {
+  clear_error();
+  if (!c) return set_error(FDG_EINVAL, "release_workspace: NULL context");
+  int st = hip_check(hipStreamSynchronize(c->stream), "release_workspace: hipStreamSynchronize");
+  if (st != FDG_OK) return st;
+  free_workspace(c);
+  return FDG_OK;
+}
+
+extern "C" size_t fdg_workspace_bytes(int d, int n, int batch, int restart) {
+  if ((d != 2 && d != 3) || n < 1 || n > 1024 || batch < 1 || restart < 1 || restart > 10000) return 0;
+  return ws_layout(ipow(n, d), batch, restart).total;
+}
+
+extern "C" int fdg_attach_workspace(fdg_ctx *c, void *dev, size_t bytes, int restart) {
+  clear_error();
+  if (!c) return set_error(FDG_EINVAL, "attach_workspace: NULL context");
+  if (dev && (restart < 1 || restart > 10000))
+    return set_error(FDG_EINVAL, "attach_workspace: restart must be in [1, 10000] (got %d)", restart);
+  if (dev && reinterpret_cast<uintptr_t>(dev) % 256 != 0)
+    return set_error(FDG_EINVAL, "attach_workspace: buffer must be 256-byte aligned");
+  const WsLayout L = ws_layout(c->N, c->batch, dev ? restart : 1);
+  if (dev && bytes < L.total)
+    return set_error(FDG_EINVAL, "attach_workspace: %zu bytes given, %zu needed", bytes, L.total);
+  int st = hip_check(hipStreamSynchronize(c->stream), "attach_workspace: hipStreamSynchronize");
+  if (st != FDG_OK) return st;
+  free_workspace(c);
+  if (!dev) return FDG_OK;  // detached: owned workspace again, allocated on next use
+  char *w = static_cast<char *>(dev);
+  c->t1 = reinterpret_cast<double *>(w + L.t1);
+  c->t2 = reinterpret_cast<double *>(w + L.t2);
+  c->t32a = w + L.t32a;
+  c->t32b = w + L.t32b;
+  c->Vb = reinterpret_cast<double *>(w + L.krylov);
+  c->Zb = reinterpret_cast<double *>(w + L.krylov + L.zoff);
+  c->bicg = c->Vb;
+  c->P1 = reinterpret_cast<double *>(w + L.P1);
+  c->P2 = reinterpret_cast<double *>(w + L.P2);
+  c->P3 = reinterpret_cast<double *>(w + L.P3);
+  c->Hcol = reinterpret_cast<double *>(w + L.Hcol);
+  c->hbuf = reinterpret_cast<double *>(w + L.hbuf);
+  c->scal = reinterpret_cast<double *>(w + L.scal);
+  c->ext_ws = w;
+  c->ext_restart = restart;
+  return FDG_OK;
+}
+
 extern "C" int fdg_destroy(fdg_ctx *c) {
   clear_error();
   if (!c) return FDG_OK;
@@ -433,14 +591,7 @@ extern "C" int fdg_destroy(fdg_ctx *c) {
   }
   dfree(c->fields);
   dfree(c->ell_col); dfree(c->ell_val); dfree(c->ell_lo);
-  dfree(c->t1); dfree(c->t2);
-  if (c->t32a) (void)hipFree(c->t32a);
-  if (c->t32b) (void)hipFree(c->t32b);
-  dfree(c->Vb); dfree(c->Zb); dfree(c->P1); dfree(c->P2); dfree(c->P3); dfree(c->Hcol);
-  dfree(c->hbuf); dfree(c->scal);
-  if (c->hpin) (void)hipHostFree(c->hpin);
-  dfree(c->bicg);
-  if (c->bicg_host) (void)hipHostFree(c->bicg_host);
+  free_workspace(c);
   if (c->phase_ev) (void)hipEventDestroy(c->phase_ev);
   for (auto &t : c->timers) {
     for (auto e : t.pool) (void)hipEventDestroy(e);

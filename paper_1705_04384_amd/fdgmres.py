@@ -57,7 +57,8 @@ EXPORTS = [
     "fdg_server_pending", "fdg_server_stats", "fdg_set_operator_mapped", "fdg_set_operator_fields",
     "fdg_deformed_coefficients", "fdg_factor_pencil_sym", "fdg_galerkin_factors", "fdg_galerkin_csr",
     "fdg_set_prec_factors_sym", "fdg_bicgstab", "fdg_operator_bytes", "fdg_factor_pencil_blocks",
-    "fdg_set_prec_factors_blocks", "fdg_apply_prec_noalloc",
+    "fdg_set_prec_factors_blocks", "fdg_apply_prec_noalloc", "fdg_ctx_bytes", "fdg_release_workspace",
+    "fdg_workspace_bytes", "fdg_attach_workspace",
 ]
 
 
@@ -112,6 +113,11 @@ def lib():
     L.fdg_set_prec_factors_sym.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     L.fdg_operator_bytes.argtypes = [ctypes.c_void_p]
     L.fdg_operator_bytes.restype = ctypes.c_size_t
+    L.fdg_ctx_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    L.fdg_release_workspace.argtypes = [ctypes.c_void_p]
+    L.fdg_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.fdg_workspace_bytes.restype = ctypes.c_size_t
+    L.fdg_attach_workspace.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
     L.fdg_bicgstab.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                                ctypes.c_int, ctypes.POINTER(fdg_info)]
     L.fdg_status_str.argtypes = [ctypes.c_int]
@@ -236,6 +242,11 @@ def footprint_bytes(d, n, batch=1, prec=PREC_FP64, restart=30):
 _torch = None
 
 
+def workspace_bytes(d, n, batch=1, restart=30):
+    """Bytes of a buffer Context.attach_workspace accepts for this shape and restart."""
+    return int(lib().fdg_workspace_bytes(d, n, batch, restart))
+
+
 def _dev_ptr(t, numel, device):
     """Device address of t after checking that it is a contiguous float64 tensor of exactly
     numel elements on CUDA device index `device` (the C ABI takes bare pointers, so an
@@ -272,11 +283,13 @@ class Context:
         dims = (ctypes.c_int32 * 3)(n, n, n)
         _check(lib().fdg_create(ctypes.byref(h), d, dims, batch, ctypes.c_void_p(stream.cuda_stream)))
         self._h = h
+        self._ws = None  # an attached workspace buffer, kept alive while attached
 
     def close(self):
         if self._h:
             lib().fdg_destroy(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -350,6 +363,36 @@ class Context:
     def operator_bytes(self):
         """Bytes of operator data one matvec reads (x and y excluded)."""
         return int(lib().fdg_operator_bytes(self._h))
+
+    def device_bytes(self):
+        """(held, workspace): device bytes the context holds, and the releasable part."""
+        held, ws = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().fdg_ctx_bytes(self._h, ctypes.byref(held), ctypes.byref(ws)))
+        return int(held.value), int(ws.value)
+
+    def release_workspace(self):
+        """Frees the solve/apply workspace after the stream drains; allocated again on use."""
+        _check(lib().fdg_release_workspace(self._h))
+        self._ws = None
+
+    def attach_workspace(self, buf, restart=30):
+        """Carves the solve/apply workspace from `buf` (a contiguous uint8 device tensor of at
+        least workspace_bytes(d, n, batch, restart) bytes, kept referenced while attached;
+        contexts sharing it must not run calls that overlap in time); None detaches."""
+        if buf is None:
+            _check(lib().fdg_attach_workspace(self._h, None, 0, 0))
+            self._ws = None
+            return
+        import torch
+        if not isinstance(buf, torch.Tensor) or buf.dtype != torch.uint8 or not buf.is_contiguous():
+            raise ValueError("expected a contiguous uint8 tensor")
+        if not buf.is_cuda or buf.device.index != self.device:
+            raise ValueError(f"workspace must be on cuda:{self.device}")
+        need = workspace_bytes(self.d, self.n, self.batch, restart)
+        if buf.numel() < need:
+            raise ValueError(f"workspace of {buf.numel()} bytes, {need} needed")
+        _check(lib().fdg_attach_workspace(self._h, ctypes.c_void_p(buf.data_ptr()), buf.numel(), restart))
+        self._ws = buf
 
     def bicgstab(self, b, x, rtol=1e-8, maxit=1000, flags=0):
         """Preconditioned BiCGStab; "iterations" is the paper's count (k or k + 0.5)."""

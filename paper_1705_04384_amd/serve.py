@@ -7,7 +7,7 @@ module only decides *when* a request enters the server:
 - Host setup of a request's 1D factors (collocation matrices, generalized eigenproblem
   of eq. 4.6) depends on (p, n) only; it runs in a thread pool (the library releases
   the GIL) the first time a (p, n) arrives, and its device context (d, p, n) is created
-  once and kept.
+  once and kept; the contexts share one blocking-solve workspace.
 - Requests are admitted first come, first served among those whose context is ready;
   a request enters when the server has a free slot and arena space for its Krylov
   bases (its footprint), otherwise it and everything behind it wait.
@@ -30,16 +30,40 @@ def _factors(p, n):
 
 
 class FactorCache:
-    """(p, n) -> host factors (thread pool); (d, p, n) -> device context."""
+    """(p, n) -> host factors (thread pool); (d, p, n) -> device context.
 
-    def __init__(self, threads=8):
+    The contexts carve their blocking-solve workspace ((2m + 3) N doubles and partials) from
+    one shared device buffer sized for the largest of them: the blocking solves run one
+    at a time and each returns with its stream drained, so the cache holds one workspace
+    instead of one per shape.  Served requests do not use it: their bases live in the
+    server's arena, which admission by footprint bounds."""
+
+    def __init__(self, threads=8, restart=30, device="cuda"):
         self.pool = ThreadPoolExecutor(max_workers=threads)
         self.futs = {}
         self.ctxs = {}
+        self.restart = restart
+        self.device = device
+        self.ws_buf = None
+        self.ws_grows = 0
 
     def request(self, p, n):
         if (p, n) not in self.futs:
             self.futs[(p, n)] = self.pool.submit(_factors, p, n)
+
+    def attach(self, key, ctx):
+        """Adds a context, attached to the shared workspace (grown, and every context
+        re-attached, when this one needs more)."""
+        need = fdgmres.workspace_bytes(ctx.d, ctx.n, ctx.batch, self.restart)
+        if self.ws_buf is None or self.ws_buf.numel() < need:
+            import torch
+            buf = torch.empty(need, dtype=torch.uint8, device=self.device)
+            for c in self.ctxs.values():
+                c.attach_workspace(buf, self.restart)
+            self.ws_buf = buf
+            self.ws_grows += 1
+        ctx.attach_workspace(self.ws_buf, self.restart)
+        self.ctxs[key] = ctx
 
     def context(self, d, p, n):
         """The device context, or None while its factors are still being computed."""
@@ -54,8 +78,14 @@ class FactorCache:
             return None
         M, K, U, V, lam = f.result()
         c = fdgmres.unit_context(d, n, M, K, U, V, lam)
-        self.ctxs[(d, p, n)] = c
+        self.attach((d, p, n), c)
         return c
+
+    def held_bytes(self):
+        """Device bytes of the cache: what the contexts own (factors, operator bands) and
+        the shared workspace."""
+        own = sum(c.device_bytes()[0] for c in self.ctxs.values())
+        return own + (0 if self.ws_buf is None else self.ws_buf.numel())
 
     def warm(self, reqs):
         for r in reqs:
@@ -69,6 +99,7 @@ class FactorCache:
         for c in self.ctxs.values():
             c.close()
         self.ctxs.clear()
+        self.ws_buf = None
 
 
 def stage(reqs, device="cuda"):
@@ -121,9 +152,11 @@ def run_served(server, cache, reqs, bufs, rtol=1e-8, maxit=1000, time_scale=1.0)
     return out, time.perf_counter() - t0
 
 
-def run_one_by_one(cache, reqs, bufs, rtol=1e-8, restart=30, maxit=1000, time_scale=1.0):
+def run_one_by_one(cache, reqs, bufs, rtol=1e-8, restart=None, maxit=1000, time_scale=1.0):
     """The same arrival stream solved one request at a time with the blocking fdg_solve
-    (a request starts when it has arrived and the previous one has finished)."""
+    (a request starts when it has arrived and the previous one has finished); restart
+    defaults to the one the cache's shared workspace is sized for."""
+    restart = cache.restart if restart is None else restart
     order = sorted(reqs, key=lambda r: r["t"])
     out = {}
     t0 = time.perf_counter()

@@ -5,6 +5,8 @@ context and right-hand side, whatever it is mixed with (same-context requests ar
 grouped into shared launches at different Arnoldi indices; different shapes run on
 other lanes), and the solve must match the FP64 oracle as the single solve does.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -160,3 +162,107 @@ def test_served_low_precision_and_zero_rhs():
     srv.close()
     ctx32.close()
     ctx64.close()
+
+
+def test_release_workspace_keeps_results_and_returns_memory():
+    fdg = _fdg()
+    torch = torch_cuda()
+    ctx = fdg.deformed_problem(3, 12, 0.1)
+    b = to_dev(inputs.rhs_normal(850, ctx.N))
+    held0, ws0 = ctx.device_bytes()
+    assert ws0 == 0 and held0 > 0                      # factors and operator only
+    x1, i1 = _solo(ctx, b, restart=6)
+    held1, ws1 = ctx.device_bytes()
+    assert ws1 >= (2 * 6 + 1) * ctx.N * 8              # bases V (m + 1) and Z (m) at least
+    assert held1 == held0 + ws1
+    ctx.release_workspace()
+    assert ctx.device_bytes() == (held0, 0)
+    x2, i2 = _solo(ctx, b, restart=6)                  # allocated again: same bits
+    assert i2["iterations"] == i1["iterations"] and np.array_equal(x1, x2)
+    ctx.release_workspace()
+    y = torch.empty_like(b)
+    ctx.apply_prec(b, y)
+    ctx.release_workspace()
+    y2 = torch.empty_like(b)
+    ctx.apply_prec(b, y2)
+    assert torch.equal(y, y2)
+    xb = torch.empty_like(b)
+    ib = ctx.bicgstab(b, xb, rtol=1e-8)
+    assert ib["converged"] and ctx.device_bytes()[1] > 0
+    ctx.release_workspace()
+    xb2 = torch.empty_like(b)
+    ctx.bicgstab(b, xb2, rtol=1e-8)
+    assert torch.equal(xb, xb2)
+    ctx.close()
+
+
+def test_shared_workspace_gives_the_same_bits():
+    fdg = _fdg()
+    torch = torch_cuda()
+    own = [fdg.deformed_problem(3, 12, 0.1), fdg.unit_problem(2, 3, 40), fdg.unit_problem(3, 4, 18)]
+    shr = [fdg.deformed_problem(3, 12, 0.1), fdg.unit_problem(2, 3, 40), fdg.unit_problem(3, 4, 18)]
+    m = 6
+    need = max(fdg.workspace_bytes(c.d, c.n, c.batch, m) for c in shr)
+    buf = torch.full((need,), 0xFF, dtype=torch.uint8, device="cuda")  # NaN bytes: nothing may read before writing
+    held = [c.device_bytes()[0] for c in shr]
+    for c in shr:
+        c.attach_workspace(buf, m)
+    for k, (co, cs) in enumerate(zip(own, shr)):
+        assert cs.device_bytes() == (held[k], 0)
+        b = to_dev(inputs.rhs_normal(880 + k, co.N))
+        xo, io = _solo(co, b, restart=m)
+        xs, is_ = _solo(cs, b, restart=m)
+        assert is_["iterations"] == io["iterations"] and io["converged"]
+        assert np.array_equal(xo, xs)
+        yo, ys = torch.empty_like(b), torch.empty_like(b)
+        co.apply_prec(b, yo)
+        cs.apply_prec(b, ys)
+        torch.cuda.synchronize()
+        assert torch.equal(yo, ys)
+        bo, bs = torch.empty_like(b), torch.empty_like(b)
+        co.bicgstab(b, bo, rtol=1e-8)
+        cs.bicgstab(b, bs, rtol=1e-8)
+        assert torch.equal(bo, bs)
+        assert cs.device_bytes()[1] == 0                  # nothing allocated beside the buffer
+    with pytest.raises(fdg.FdgError):                     # restart above the attached one
+        shr[0].solve(to_dev(inputs.rhs_normal(890, shr[0].N)), torch.empty(shr[0].N, dtype=torch.float64,
+                                                                           device="cuda"), restart=m + 1)
+    with pytest.raises(ValueError):                       # too small (checked before the C call)
+        shr[0].attach_workspace(buf[: need // 4], m)
+    L = fdg.lib()
+    assert L.fdg_attach_workspace(shr[0]._h, ctypes.c_void_p(buf.data_ptr()), 1024, m) == -1
+    assert L.fdg_attach_workspace(shr[0]._h, ctypes.c_void_p(buf.data_ptr() + 8), need - 8, m) == -1
+    shr[0].attach_workspace(None)                         # detached: owned workspace again
+    b = to_dev(inputs.rhs_normal(880, shr[0].N))
+    x0, _ = _solo(shr[0], b, restart=m)
+    x1, _ = _solo(own[0], b, restart=m)
+    assert np.array_equal(x0, x1) and shr[0].device_bytes()[1] > 0
+    for c in own + shr:
+        c.close()
+
+
+def test_factor_cache_shares_one_workspace():
+    from paper_1705_04384_amd import serve
+    _fdg()
+    shapes = [(2, 3, 40), (3, 3, 20), (3, 4, 22), (2, 4, 30)]
+    reqs = [{"id": k, "d": d, "p": p, "n": n, "t": 0.0, "seed": 870 + k}
+            for k, (d, p, n) in enumerate(shapes * 2)]
+    cache = serve.FactorCache(threads=2, restart=30)
+    cache.warm(reqs)
+    assert cache.ws_buf.numel() == fdgmres_ws(3, 22)
+    bufs = serve.stage(reqs)
+    res, _ = serve.run_one_by_one(cache, reqs, bufs)
+    assert all(v[1] == 0 for v in res.values())
+    for r in reqs[:4]:                                    # the same bits from an unshared context
+        ctx = serve.fdgmres.unit_problem(r["d"], r["p"], r["n"])
+        b, x = bufs[r["id"]]
+        x2 = torch_cuda().empty_like(b)
+        ctx.solve(b, x2, rtol=1e-8, restart=30)
+        assert torch_cuda().equal(x, x2)
+        ctx.close()
+    cache.close()
+
+
+def fdgmres_ws(d, n):
+    from paper_1705_04384_amd import fdgmres
+    return fdgmres.workspace_bytes(d, n, 1, 30)

@@ -269,3 +269,62 @@ def test_device_vector_checks_reject_wrong_tensors():
         fdg._dev_ptr(np.zeros(12), 12, 0)
     with pytest.raises(ValueError, match="CUDA"):
         fdg._dev_ptr(ok, 12, 0)
+
+
+def test_context_memory_calls_reject_null():
+    L = _lib()
+    assert L.fdg_release_workspace(None) == -1
+    import ctypes
+    held = ctypes.c_size_t(7)
+    assert L.fdg_ctx_bytes(None, ctypes.byref(held), None) == -1
+    assert held.value == 7
+
+
+def test_workspace_bytes_cover_the_solve_buffers():
+    _lib()
+    for d, n, m in [(2, 33, 8), (3, 20, 30), (3, 128, 30)]:
+        N = n ** d
+        w = fdg.workspace_bytes(d, n, restart=m)
+        assert w >= (2 * m + 1) * N * 8 + 2 * N * 8 + 2 * N * 4      # V, Z, FP64 and FP32 apply buffers
+        assert w >= (8 * N + 2) * 8 + 2 * N * 8                       # BiCGStab vectors share the bases
+        bases = max((2 * m + 1) * N, 8 * N + 8 * 256 + 64) * 8
+        partials = (2 * (m + 1) + 1) * 256 * 8 + (3 * (m + 2) + 4) * 8  # at most 256 blocks
+        assert w <= 2 * N * 8 + 2 * N * 4 + bases + partials + 11 * 512
+        assert fdg.workspace_bytes(d, n, restart=m + 1) > w
+        assert fdg.workspace_bytes(d, n, batch=2, restart=m) > w
+    w1 = fdg.workspace_bytes(3, 10, restart=1)
+    assert w1 >= (8 * 1000 + 8 * 256 + 64) * 8                          # restart 1: BiCGStab sets the size
+    for bad in [(1, 10, 1, 30), (3, 0, 1, 30), (3, 10, 0, 30), (3, 10, 1, 0), (3, 2000, 1, 30)]:
+        assert fdg.lib().fdg_workspace_bytes(*bad) == 0
+
+
+def test_shared_workspace_cache_grows_and_reattaches():
+    """Host logic of the context cache's shared workspace (fake contexts, host buffer)."""
+    from paper_1705_04384_amd import serve
+
+    class Fake:
+        def __init__(self, d, n):
+            self.d, self.n, self.batch, self.buf, self.attaches = d, n, 1, None, 0
+
+        def attach_workspace(self, buf, restart):
+            assert buf.numel() >= fdg.workspace_bytes(self.d, self.n, self.batch, restart)
+            self.buf, self.attaches = buf, self.attaches + 1
+
+        def device_bytes(self):
+            return 1000, 0
+
+        def close(self):
+            pass
+
+    cache = serve.FactorCache(threads=1, restart=8, device="cpu")
+    a, b, c = Fake(2, 20), Fake(3, 12), Fake(2, 30)
+    cache.attach((2, 3, 20), a)
+    assert cache.ws_buf.numel() == fdg.workspace_bytes(2, 20, 1, 8) and a.buf is cache.ws_buf
+    cache.attach((3, 3, 12), b)                      # larger: new buffer, a re-attached to it
+    assert cache.ws_buf.numel() == fdg.workspace_bytes(3, 12, 1, 8)
+    assert a.buf is cache.ws_buf and b.buf is cache.ws_buf and a.attaches == 2
+    cache.attach((2, 3, 30), c)                      # fits: no new buffer
+    assert cache.ws_grows == 2 and c.buf is cache.ws_buf and a.attaches == 2
+    assert cache.held_bytes() == 3 * 1000 + cache.ws_buf.numel()
+    cache.close()
+    assert cache.ws_buf is None and not cache.ctxs
