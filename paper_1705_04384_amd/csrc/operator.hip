@@ -927,16 +927,20 @@ bool kron_two_pass_ok(int d, int n, int64_t nbatch, const KronBands &bd) {
 
 namespace {
 
-// Shape of the streaming one-pass form: RPW staged rows j2 per compute wave, D planes
-// loaded ahead (2: the measured best at n = 128 and 192; deeper rings cost occupancy),
-// and chunks of 8 outputs i3.
-#ifndef FDG_MV_RPW
-#define FDG_MV_RPW 2
-#endif
+// Shape of the streaming one-pass form: D = 2 planes loaded ahead (the measured best at
+// n = 128 and 192; deeper rings cost occupancy), and per band width w the staged rows j2
+// per compute wave (RPW) and the outputs i3 per chunk.  Measured on MI355X (us per
+// product, RPW in {2, 3, 4} x chunk in {4, 6, 8}): wide bands want tall tiles, whose
+// halo share 1 - T2 / (7 RPW) is smaller (p = 6, w = 7: 192^3 92.8 -> 74.2 with RPW 4,
+// 128^3 28.7 -> 26.9); narrow bands want more, shorter chunks (w <= 4: 96^3 p = 3
+// 11.3 -> 9.9, 128^3 p = 2 16.1 -> 14.5 with chunks of 6); w = 5, 6 keep RPW 2 and
+// chunks of 8 (128^3 p = 4: 19.2, every other shape 19.1-33.9).
 #ifndef FDG_MV_D
 #define FDG_MV_D 2
 #endif
-constexpr int kStreamRPW = FDG_MV_RPW, kStreamD = FDG_MV_D;
+constexpr int kStreamD = FDG_MV_D;
+constexpr int stream_rpw(int w) { return w >= 7 ? 4 : 2; }
+constexpr int stream_chunk(int w) { return w <= 4 ? 6 : 8; }
 
 struct StreamShape {
   int ntx, nty, nchunk, c3len;
@@ -945,10 +949,11 @@ struct StreamShape {
 
 StreamShape stream_shape(int n, const KronBands &bd) {
   StreamShape sh;
-  const int T2 = 7 * kStreamRPW - bd.w[1] + 1;
+  const int w = bd.w[1];
+  const int T2 = 7 * stream_rpw(w) - w + 1;
   sh.ntx = (int)cdiv(n, 64);
   sh.nty = (int)cdiv(n, T2);
-  sh.c3len = 8;
+  sh.c3len = stream_chunk(w);
   sh.nchunk = (int)cdiv(n, sh.c3len);
   return sh;
 }
@@ -981,7 +986,7 @@ void launch_wpp(hipStream_t s, CBatch x, MBatch y, int n, int64_t nbatch, const 
     const int64_t ntiles = sh.tiles() * nbatch;
     const dim3 grid((unsigned)((ntiles + 7) / 8 * 8));
 #define FDG_STREAM(WW, C3)                                                                                   \
-  hipLaunchKernelGGL((k_kron3_stream<WW, kStreamRPW, kStreamD, C3, RES>), grid, dim3(512), 0, s, x, y, n, sh.ntx, \
+  hipLaunchKernelGGL((k_kron3_stream<WW, stream_rpw(WW), kStreamD, C3, RES>), grid, dim3(512), 0, s, x, y, n, sh.ntx, \
                      sh.nty, sh.nchunk, sh.c3len, ntiles, bd, rhs, part)
     switch (w) {
       case 2: FDG_STREAM(2, 8); break;

@@ -83,11 +83,13 @@ def test_kron_matvec_tiles_and_tails(p, n, batch):
 
 
 
-@pytest.mark.parametrize("p,n,batch", [(4, 80, 2), (3, 96, 1), (6, 100, 1), (2, 130, 1), (5, 97, 1), (4, 128, 1)])
+@pytest.mark.parametrize("p,n,batch", [(4, 80, 2), (3, 96, 1), (6, 100, 1), (2, 130, 1), (5, 97, 1), (4, 128, 1),
+                                       (6, 133, 1), (7, 110, 1)])
 def test_kron_matvec_streaming_form(p, n, batch):
     """Shapes with at least 128 workgroups per entry take the streaming one-pass form (band
-    widths 3 to 7, ragged tails in every direction: 80, 100, 130 and 97 are not multiples
-    of the 64-column tile, of the T2 = 15 - w row tile or of the 8-plane chunk); against
+    widths w = 3 to 8; 14 staged rows for w <= 6, 28 for w >= 7; chunks of 6 planes for
+    w <= 4, else 8; ragged tails in every direction: 80, 100, 130, 97, 133 and 110 are not
+    multiples of the 64-column tile, of the T2 = 7 RPW - w + 1 row tile or of the chunk); against
     the oracle's product element by element, and its residual form (r = b - A x with the
     |r|^2 partials) through the true residual a solve reports."""
     fdg = _fdg()
