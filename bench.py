@@ -377,6 +377,53 @@ def batched_2d(count):
     return out
 
 
+def served_headline(p, n, f, noise, X, plain_rate):
+    """The headline problem's right-hand sides submitted together to the request server,
+    which launches the same phase of all of them as one kernel per step: K = 2 (the two
+    headline right-hand sides) and K = 8 (those and six more N(0,1) ones).  Each served
+    solve is the fdg_solve result bit for bit (checked against the plain solves' x)."""
+    import torch
+    from paper_1705_04384_amd import fdgmres, inputs
+    d = 3
+    N = n ** d
+    ctx = fdgmres.unit_problem(d, p, n)
+    out = {"workload": "the headline problem; K right-hand sides admitted together to fdg_server (1 lane), "
+                       "grouped launches; throughput over repeated batches, RHS resident in HBM"}
+    srv = fdgmres.Server(max_slots=8, restart=30, lanes=1,
+                         arena_bytes=8 * fdgmres.server_run_bytes(ctx, 30) + (64 << 20))
+    for K in (2, 8):
+        rhs = [f, noise] + [inputs.rhs_normal(inputs.SEED_NOISE_128 + 100 + k, N) for k in range(K - 2)]
+        B = [torch.from_numpy(r).cuda() for r in rhs]
+        Y = [torch.empty_like(b) for b in B]
+        infos = {}
+
+        def batch():
+            for k in range(K):
+                assert srv.admit(ctx, B[k], Y[k], rtol=1e-8, tag=k)
+            while len(infos) < K:
+                for tag, st, info in srv.step(wait_us=0):
+                    infos[tag] = info
+        for _ in range(5):
+            infos.clear()
+            batch()
+        torch.cuda.synchronize()
+        reps = 400 // K
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            infos.clear()
+            batch()
+        torch.cuda.synchronize()
+        rate = K * reps / (time.perf_counter() - t0)
+        assert all(i["converged"] and i["rel_res_true"] <= 1e-8 for i in infos.values())
+        out[f"K{K}"] = {"solves_per_s": rate, "vs_plain": rate / plain_rate,
+                        "same_bits_as_plain": bool(torch.equal(Y[0], X[0]) and torch.equal(Y[1], X[1])),
+                        "iterations": sorted({i["iterations"] for i in infos.values()})}
+    out["server_stats"] = srv.stats()
+    srv.close()
+    ctx.close()
+    return out
+
+
 def complex_pairs_apply_128(reps=20):
     """P^{-1} at n = 128 (3D) with real eigenvalues (three fused passes) against the same
     shape with complex eigenvalue pairs in every direction (2 x 2 blocks of D: fused
@@ -700,6 +747,7 @@ def main():
         out["cpu_baseline"], refs = cpu_baseline(p, n, f, noise, args.cpu_solves)
         out["err_vs_oracle"] = [err_vs(X[k], refs.get(f"headline_{k}")) for k in range(2)]
     if not args.no_extra:
+        out["served_headline"] = served_headline(p, n, f, noise, X, out["value"])
         out["deformed_96"] = deformed_96(refs)
         out["precision_sweep_192"] = precision_sweep_192(refs)
         out["batched_2d_p3_n33"] = batched_2d(1000)

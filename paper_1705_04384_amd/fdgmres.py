@@ -242,6 +242,11 @@ def footprint_bytes(d, n, batch=1, prec=PREC_FP64, restart=30):
 _torch = None
 
 
+def server_run_bytes(ctx, restart=30):
+    """Arena bytes one request of this context takes in a server of the given restart."""
+    return int(lib().fdg_server_run_bytes(ctx._h, restart))
+
+
 def workspace_bytes(d, n, batch=1, restart=30):
     """Bytes of a buffer Context.attach_workspace accepts for this shape and restart."""
     return int(lib().fdg_workspace_bytes(d, n, batch, restart))
