@@ -187,38 +187,30 @@ __device__ inline double block_sum(double v, double *red) {
 }
 
 // The update w -= V hs followed by the dots V^T w of the updated w over the block's
-// chunk, reading each basis value from memory once when nv <= kStageNV (the two-step form
-// reads the basis twice, and the second read misses the cache at large N).  The updated
-// w is bitwise that of chunk_update (the same fma order per element); the summation order
-// of the dots depends on nv only.
+// chunk, reading each basis value from memory once when nv <= kGroupNV (the two-step form
+// reads the basis twice, and the second read misses the cache at large N).  The summation
+// order of the dots depends on nv only.
 //
 // nv <= kRegNV: thread-strided elements, all nv basis values of an element in registers,
-// per-thread running dots, then butterflies and the waves in index order (store_partials).
-// kRegNV < nv <= kStageNV: sub-chunks of S elements (S depends on nv); thread e loads
-// element e of kStageBatch basis vectors at a time, updates w there and leaves the basis
-// values and w in LDS; then wave k reduces components q = k, k + 16, ... over the
-// sub-chunk (a strided sum and a butterfly) into a running sum per q in LDS.
+// per-thread running dots, then butterflies and the waves in index order (store_partials);
+// the updated w is bitwise that of chunk_update (the same fma order per element).
+// kRegNV < nv <= kGroupNV: 2 (nv <= 16) or 4 lanes per element, 8 basis vectors per lane
+// (group_update_dots): every thread of the block loads.  Measured on MI355X at N = 96^3
+// (deformed cube, FGMRES(30), 35 calls per solve): 968 -> 739 us per solve against the
+// previous form, which staged sub-chunks of the basis in LDS with only the threads of a
+// sub-chunk loading (at nv = 30: 55.3 -> 37.6 us per call, 4.1 -> 6.0 TB/s).
 // Larger nv: the update and the dots each stream the basis.
-// Measured on MI355X at N = 96^3 (FGMRES(30)): 39.6 -> 28.3 us per call on average.
 #ifndef FDG_REG_NV
 #define FDG_REG_NV 8  // 10 measures the same; 12 and more spill registers
-#endif
-#ifndef FDG_STAGE_NV
-#define FDG_STAGE_NV 32
 #endif
 constexpr int kRegNV = FDG_REG_NV;
 #ifndef FDG_REG2_UNROLL
 #define FDG_REG2_UNROLL 4
 #endif
-constexpr int kStageNV = FDG_STAGE_NV;
-constexpr int kStage = 12288;   // doubles of staged basis values (96 KB)
-constexpr int kStageBatch = 8;  // basis loads in flight per thread in the staged form
+constexpr int kGroupNV = 4 * kQB;
 
 struct PassLds {
   double red[kRedWaves][kQB];
-  double vs[kStage];
-  double ws[kRed];
-  double accq[kStageNV > 0 ? kStageNV : 1];
 };
 
 template <int NVM, int UNR>
@@ -252,42 +244,100 @@ __device__ inline void reg_update_dots(gptr<const double> __restrict__ Vb, int64
   }
 }
 
-__device__ inline void staged_update_dots(gptr<const double> __restrict__ Vb, int64_t ldv, int nv, const double *hs,
-                                          gptr<double> __restrict__ wb, int64_t beg, int64_t end, gptr<double> Pg,
-                                          PassLds &L) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int S = kStage / nv;
-  S = (S < kRed ? S : kRed) / 64 * 64;
-  if (tid < kStageNV) L.accq[tid] = 0.0;
-  for (int64_t s0 = beg; s0 < end; s0 += S) {
-    const int len = (int)(end - s0 < S ? end - s0 : S);
-    if (tid < len) {
-      gptr<const double> vcol = Vb + s0 + tid;
-      double wi = wb[s0 + tid];
-      for (int q0 = 0; q0 < nv; q0 += kStageBatch) {
-        double v[kStageBatch];
+// Lane exchange inside a quad of lanes (quad_perm DPP, both halves of a double).
+template <int CTRL>
+__device__ inline double quad_dpp(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+
+// nv <= LPE QPL: LPE lanes per element (1, 2 or 4 adjacent lanes; 2-wide elements with
+// VEC), lane k of the group holding basis vectors q = k QPL + t, t < QPL.  Each lane loads
+// its basis values of the element (every load issued, at clamped vector and element
+// indices), the group adds its partial sums of V_q h_q by xor exchanges inside the quad
+// (commutative adds: the same bits in every lane of the group), and every lane forms
+// w' = w - that sum and its dots.  The dots are summed over the lanes that hold the same
+// q by an xor butterfly, then over the waves in index order.
+template <bool VEC, int LPE, int QPL>
+__device__ inline void group_update_dots(gptr<const double> __restrict__ Vb, int64_t ldv, int nv, const double *hs,
+                                         gptr<double> __restrict__ wb, int64_t beg, int64_t end, gptr<double> Pg,
+                                         double (*red)[4 * kQB]) {
+  static_assert(LPE == 1 || LPE == 2 || LPE == 4, "lanes per element");
+  static_assert(LPE * QPL <= 4 * kQB, "partials buffer");
+  constexpr int EL = VEC ? 2 : 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, k = lane & (LPE - 1);
+  const int64_t step = (int64_t)EL * (kRed / LPE);
+  double hq[QPL];
+  gptr<const double> vq[QPL];
 #pragma unroll
-        for (int t = 0; t < kStageBatch; ++t) v[t] = q0 + t < nv ? vcol[(int64_t)(q0 + t) * ldv] : 0.0;
-#pragma unroll
-        for (int t = 0; t < kStageBatch; ++t)
-          if (q0 + t < nv) {
-            wi = fma(-v[t], hs[q0 + t], wi);
-            L.vs[(q0 + t) * S + tid] = v[t];
-          }
-      }
-      wb[s0 + tid] = wi;
-      L.ws[tid] = wi;
-    }
-    __syncthreads();
-    for (int q = wave; q < nv; q += kRedWaves) {
-      double part = 0.0;
-      for (int e = lane; e < len; e += 64) part = fma(L.vs[q * S + e], L.ws[e], part);
-      part = wave_sum(part);
-      if (lane == 0) L.accq[q] += part;
-    }
-    __syncthreads();  // staged values and w consumed before the next sub-chunk
+  for (int t = 0; t < QPL; ++t) {
+    const int q = k * QPL + t;
+    hq[t] = q < nv ? hs[q] : 0.0;  // vectors beyond nv: clamped loads, zero weight, dots unused
+    vq[t] = Vb + (int64_t)(q < nv ? q : nv - 1) * ldv;
   }
-  if (tid < nv) Pg[tid] = L.accq[tid];
+  double acc[QPL];
+#pragma unroll
+  for (int t = 0; t < QPL; ++t) acc[t] = 0.0;
+  for (int64_t i = beg + EL * (int64_t)(tid / LPE); i < end; i += step) {
+    double v[QPL][EL], w[EL];
+    const int64_t ec = i;
+    if constexpr (VEC) {
+      const dbl2 ww = ld2(wb + ec);
+      w[0] = ww.x;
+      w[1] = ww.y;
+#pragma unroll
+      for (int t = 0; t < QPL; ++t) {
+        const dbl2 vv = ld2(vq[t] + ec);
+        v[t][0] = vv.x;
+        v[t][1] = vv.y;
+      }
+    } else {
+      w[0] = wb[ec];
+#pragma unroll
+      for (int t = 0; t < QPL; ++t) v[t][0] = vq[t][ec];
+    }
+    double wn[EL];
+#pragma unroll
+    for (int el = 0; el < EL; ++el) {
+      double part = 0.0;
+#pragma unroll
+      for (int t = 0; t < QPL; ++t) part = fma(v[t][el], hq[t], part);
+      if constexpr (LPE >= 2) part += quad_dpp<kQuadXor1>(part);
+      if constexpr (LPE >= 4) part += quad_dpp<kQuadXor2>(part);
+      wn[el] = w[el] - part;
+    }
+    if (k == 0) {
+      if constexpr (VEC) {
+        dbl2 o;
+        o.x = wn[0];
+        o.y = wn[1];
+        st2(wb + ec, o);
+      } else {
+        wb[ec] = wn[0];
+      }
+    }
+#pragma unroll
+    for (int el = 0; el < EL; ++el)
+#pragma unroll
+      for (int t = 0; t < QPL; ++t) acc[t] = fma(v[t][el], wn[el], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < QPL; ++t) {
+    double a = acc[t];
+#pragma unroll
+    for (int off = LPE; off < 64; off <<= 1) a += __shfl_xor(a, off, 64);
+    if (lane < LPE) red[wave][lane * QPL + t] = a;
+  }
+  __syncthreads();
+  if (tid < nv) {
+    double sum = red[0][tid];
+    for (int wv = 1; wv < kRedWaves; ++wv) sum += red[wv][tid];
+    Pg[tid] = sum;
+  }
 }
 
 // P = partial dots V^T w.  The nb = ceil(nv / kQB) batches of kQB components are spread
@@ -374,8 +424,12 @@ __global__ __launch_bounds__(kRed) void k_update_dots(CBatch V, int64_t ldv, IBa
     reg_update_dots<kRegNV, 1>(Vb, ldv, nv, hs, wb, beg, end, Pg, L);
     return;
   }
-  if (nv <= kStageNV) {
-    staged_update_dots(Vb, ldv, nv, hs, wb, beg, end, Pg, L);
+  if (nv <= kGroupNV) {
+    __shared__ double qred[kRedWaves][4 * kQB];
+    if (nv <= 16)
+      group_update_dots<VEC, 2, kQB>(Vb, ldv, nv, hs, wb, beg, end, Pg, qred);
+    else
+      group_update_dots<VEC, 4, kQB>(Vb, ldv, nv, hs, wb, beg, end, Pg, qred);
     return;
   }
   (void)chunk_update<VEC>(Vb, ldv, nv, hs, wb, beg, end);
