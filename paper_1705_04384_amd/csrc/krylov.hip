@@ -52,10 +52,11 @@ __device__ inline void reduce_into(gptr<const double> P, int G, int ldp, int nco
 __device__ inline void store_partials(double (&acc)[kQB], double (*red)[kQB], gptr<double> Pg, int q0, int nv) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < kQB; ++t) {
-    const double v = wave_sum(acc[t]);
-    if (lane == 0) red[wave][t] = v;
-  }
+  for (int t = 0; t < kQB; ++t)
+    if (q0 + t < nv) {  // valid components only (block-uniform)
+      const double v = wave_sum(acc[t]);
+      if (lane == 0) red[wave][t] = v;
+    }
   __syncthreads();
   if (threadIdx.x < kQB && q0 + (int)threadIdx.x < nv) {
     const int t = threadIdx.x;
@@ -378,11 +379,15 @@ __global__ __launch_bounds__(kRed) void k_dots(CBatch V, int64_t ldv, IBatch nvs
 #pragma unroll
       for (int t = 0; t < kQB; ++t) acc[t] = 0.0;
     }
+    // butterflies for this wave's valid components only (a wave-uniform count): with one
+    // or two basis vectors the other six or seven would be most of the kernel's LDS work
+    const int nval = bq < nb ? (nv - bq * kQB < kQB ? nv - bq * kQB : kQB) : 0;
 #pragma unroll
-    for (int t = 0; t < kQB; ++t) {
-      const double v = wave_sum(acc[t]);
-      if (lane == 0) red[wave][t] = v;
-    }
+    for (int t = 0; t < kQB; ++t)
+      if (t < nval) {
+        const double v = wave_sum(acc[t]);
+        if (lane == 0) red[wave][t] = v;
+      }
     __syncthreads();
     if ((int)threadIdx.x < ng * kQB) {
       const int gg = threadIdx.x / kQB, t = threadIdx.x - gg * kQB;
