@@ -580,7 +580,14 @@ struct Shape {
   int waves, mt, nt;
 };
 
-static Shape pick_shape(int n, bool small_grid) {
+// With 32 columns per workgroup (3D, n > 96), two or three 16-row tiles per wave: from
+// n = 97 on 4 waves of 2 tiles in both passes, from n = 129 on 4 waves of 3 tiles in the
+// slab passes (the fibre pass keeps 12 waves of one tile).  Measured on MI355X (3D FP64
+// apply, us, one tile per wave -> these): n = 112 64.6 -> 62.3, 128 72.5 -> 70.2, 144 172
+// -> 164, 160 233 -> 221, 176 286 -> 264, 192 328 -> 308; the fibre pass with 4 x 3 at
+// n = 192: 340.
+enum ShapeRole { kRoleSlab = 1, kRoleFibre = 2 };
+static Shape pick_shape(int n, bool small_grid, int role) {
 #if defined(FDG_FD_FORCE_W) && defined(FDG_FD_FORCE_MT) && defined(FDG_FD_FORCE_NT)
   if (16 * FDG_FD_FORCE_W * FDG_FD_FORCE_MT >= ((n + 15) & ~15) &&
       16 * FDG_FD_FORCE_W * FDG_FD_FORCE_MT <= ((n + 63) / 64) * 64)
@@ -589,8 +596,10 @@ static Shape pick_shape(int n, bool small_grid) {
   const int nt = (small_grid || n <= 96) ? 1 : 2;
   const int k = (n + 15) / 16;  // 16-row tiles needed
   if (k <= 4) return {4, 1, nt};
-  if (k <= 8) return {k, 1, nt};    // 5..8 waves, one tile each
-  if (k <= 12) return {12, 1, nt};  // measured: 12 x 1 beats 6 x 2 and 4 x 3 for n in 129..192
+  if (nt == 2 && k <= 8) return {4, 2, 2};
+  if (k <= 8) return {k, 1, nt};  // 5..8 waves, one tile each
+  if (nt == 2 && k <= 12 && role == kRoleSlab) return {4, 3, 2};
+  if (k <= 12) return {12, 1, nt};
   return {8, 2, nt};
 }
 
@@ -601,7 +610,7 @@ static Shape pick_shape(int n, bool small_grid) {
 void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const double *W2, int ldw, int n,
                      int64_t nentries, int spe, bool divide, const double *lam1, const double *lam2, bool aligned32,
                      hipEvent_t ev0, hipEvent_t ev1) {
-  const Shape sh = pick_shape(n, spe == 1);
+  const Shape sh = pick_shape(n, spe == 1, kRoleSlab);
   const int64_t nslab = nentries * spe;
 #define FDG_CASE(W, M, T)                                                                  \
   if (sh.waves == W && sh.mt == M && sh.nt == T) {                                       \
@@ -615,7 +624,7 @@ void launch_slab_f64(hipStream_t s, CBatch X, MBatch Y, const double *W1, const 
 void launch_fibre_f64(hipStream_t s, CBatch X, MBatch Y, const double *Wa, const double *Wb, int ldw, int n,
                       int64_t batch, const double *lam1, const double *lam2, const double *lam3, hipEvent_t ev0,
                       hipEvent_t ev1) {
-  const Shape sh = pick_shape(n, false);
+  const Shape sh = pick_shape(n, false, kRoleFibre);
 #define FDG_CASE(W, M, T)                                                               \
   if (sh.waves == W && sh.mt == M && sh.nt == T) {                                    \
     fibre_launch<W, M, T>(s, X, Y, Wa, Wb, ldw, n, batch, lam1, lam2, lam3, ev0, ev1); \
