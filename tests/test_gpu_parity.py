@@ -181,14 +181,16 @@ def test_solve_deformed_matches_oracle(p, n, restart):
     ctx.close()
 
 
-@pytest.mark.parametrize("k", [6, 20, 44])
-def test_fixed_iterations_span_every_orthogonalization_form(k):
+@pytest.mark.parametrize("k,n", [(6, 20), (20, 20), (44, 20), (20, 21)])
+def test_fixed_iterations_span_every_orthogonalization_form(k, n):
     # one restart cycle of 44 steps at N = 20^3 (8 reduction chunks, ragged sub-chunks):
     # the Gram-Schmidt update-and-dots step takes nv = j + 1 basis vectors, so k = 6 uses
-    # the register form only, 20 adds the LDS-staged form (9..32) and 44 the two-read form
+    # the register form only, 20 adds the grouped-lane forms (2 lanes per element for
+    # nv 9..16, 4 for 17..32) and 44 the two-read form; N = 21^3 is odd, so the basis
+    # vectors are not 16-byte aligned and every form takes its one-element path
     fdg = _fdg()
     torch = torch_cuda()
-    p, n, restart = 3, 20, 44
+    p, restart = 3, 44
     ctx = fdg.deformed_problem(p, n, 0.1)
     b = inputs.rhs_uniform(inputs.SEED_DEFORMED_96, n ** 3)
     A = colloc.deformed_operator(p, n, 0.1)
