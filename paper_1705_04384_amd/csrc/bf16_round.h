@@ -45,8 +45,21 @@ __device__ inline __bf16 bf16_from_bits(uint16_t h) {
   __builtin_memcpy(&r, &h, 2);
   return r;
 }
-// A mode-product input rounded to BF16 once, from its stored precision.
+// A mode-product input rounded to BF16 once, from its stored precision.  On the device the
+// last step is the conversion instruction (gfx950 converts FP32 to BF16 rounding to
+// nearest even, which is bf16_bits_rne); an FP64 input goes through the round-to-odd FP32
+// value first, as above.
+#ifdef FDG_BF16_SOFT_RNE
 __device__ inline __bf16 to_bf16_once(float f) { return bf16_from_bits(bf16_bits_from_f32(f)); }
 __device__ inline __bf16 to_bf16_once(double x) { return bf16_from_bits(bf16_bits_from_f64(x)); }
+#else
+__device__ inline __bf16 to_bf16_once(float f) { return (__bf16)f; }
+__device__ inline __bf16 to_bf16_once(double x) {
+  const uint32_t u = fp32_bits_round_to_odd(x);
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return (__bf16)f;
+}
+#endif
 
 }  // namespace fdg
