@@ -61,5 +61,7 @@ __device__ inline __bf16 to_bf16_once(double x) {
   return (__bf16)f;
 }
 #endif
+// An input already stored in BF16 (an intermediate rounded by the pass that wrote it).
+__device__ inline __bf16 to_bf16_once(__bf16 h) { return h; }
 
 }  // namespace fdg

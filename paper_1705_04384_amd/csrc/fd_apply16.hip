@@ -1,8 +1,10 @@
 // Fused BF16 fast-diagonalization solve (eq. 4.9 / 4.7): the three passes of the FP64
 // solve (slab: modes 1 and 2; fibre: mode 3, divide, mode 3; slab: modes 1 and 2) on
 // v_mfma_f32_16x16x32_bf16.  Every mode-product input, factor and tensor, is rounded to
-// BF16 (round to nearest even) where it enters an MFMA; products accumulate in FP32; the
-// intermediates between passes are FP32, and so are the diagonal solve and the scaling.
+// BF16 (round to nearest even) where it enters an MFMA; products accumulate in FP32, and
+// the diagonal solve and the scaling are FP32.  The intermediates between passes are
+// stored already rounded to BF16: the next pass rounds each of them to BF16 where it enters
+// its first MFMA, so storing the rounded value gives the same bits with half the traffic.
 // The first pass reads the FP64 Krylov vector and the last one writes FP64.
 //
 // v_mfma_f32_16x16x32_bf16 lane layout (li = lane % 16, lg = lane / 16), per 32-wide
@@ -56,17 +58,28 @@ __device__ inline bf16x8 load8v(const T *p, int j, int jmax, bool ok) {
         v[t] = to_bf16_once(x0[t]);
         v[4 + t] = to_bf16_once(x1[t]);
       }
-    } else {
+    } else if constexpr (sizeof(T) == 4) {
       const flt4 x0 = *reinterpret_cast<const flt4 *>(p), x1 = *reinterpret_cast<const flt4 *>(p + 4);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         v[t] = to_bf16_once(x0[t]);
         v[4 + t] = to_bf16_once(x1[t]);
       }
+    } else {  // BF16 already: one 16-byte load (VEC: p is 16-byte aligned)
+      v = *reinterpret_cast<const bf16x8 *>(p);
     }
     return v;
   }
   return load8(p, j, jmax, ok);
+}
+
+// A pass output in its stored type: FP64 and FP32 as computed, BF16 rounded to nearest even.
+template <typename TO>
+__device__ inline TO store_as(float v) {
+  if constexpr (sizeof(TO) == 2)
+    return to_bf16_once(v);
+  else
+    return (TO)v;
 }
 
 // Eight consecutive BF16 (16-byte aligned, always in bounds).
@@ -209,7 +222,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab16(const TI *__restrict__ X,
         if (k2 < n) {
           float v = acc[a][b][r];
           if (DIV) v = v / (lam2[k2] + lam1[c]);
-          Ys[(int64_t)k2 * n + c] = (TO)v;
+          Ys[(int64_t)k2 * n + c] = store_as<TO>(v);
         }
       }
   }
@@ -217,8 +230,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_slab16(const TI *__restrict__ X,
 
 // Pass B: workgroup = (entry, block of kNB columns c of X[i3][c]); the block is staged
 // transposed in LDS (BF16), then T = Wa X, T /= lam3 + lam2 + lam1 (FP32), S = Wb T.
-template <int WAVES, int MT, int NT, bool VEC>
-__global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict__ X, float *__restrict__ Y,
+template <int WAVES, int MT, int NT, bool VEC, typename TI, typename TO>
+__global__ __launch_bounds__(64 * WAVES) void k_fibre16(const TI *__restrict__ X, TO *__restrict__ Y,
                                                         const __bf16 *__restrict__ Wa, const __bf16 *__restrict__ Wb,
                                                         int ldw, int n, int ncb, const float *__restrict__ lam1,
                                                         const float *__restrict__ lam2, const float *__restrict__ lam3) {
@@ -233,8 +246,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
   const int64_t bidx = blockIdx.x / ncb;
   const int cb = (int)(blockIdx.x % ncb);
   const int64_t n2 = (int64_t)n * n;
-  const float *__restrict__ Xb = X + bidx * n2 * n;
-  float *__restrict__ Yb = Y + bidx * n2 * n;
+  const TI *__restrict__ Xb = X + bidx * n2 * n;
+  TO *__restrict__ Yb = Y + bidx * n2 * n;
   const int64_t c0 = (int64_t)cb * kNB;
   const int m0 = wave * MT * 16;
   const int kpad = (n + 31) & ~31;
@@ -252,11 +265,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
     lv2[b] = lam2[cok ? (int)(cg / n) : 0];
     lv1[b] = lam1[cok ? (int)(cg % n) : 0];
   }
-  if (VEC) {  // n^2 % 4 == 0 and a 16-byte aligned X: four columns per load, every load of
-             // the thread issued (at clamped addresses) before the first LDS store
+  if (VEC) {  // n^2 % 4 == 0 and an aligned X: four columns per load, every load of the
+             // thread issued (at clamped addresses) before the first LDS store
+    typedef TI vec4 __attribute__((ext_vector_type(4)));
     constexpr int Q = kNB / 4;
     constexpr int SIT = (MPAD * Q + NTHR - 1) / NTHR;
-    flt4 sv[SIT];
+    vec4 sv[SIT];
 #pragma unroll
     for (int it = 0; it < SIT; ++it) {
       const int e = (int)threadIdx.x + it * NTHR;
@@ -264,7 +278,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
       const int64_t cg = c0 + 4 * q;
       const int i3c = i3 < n ? i3 : n - 1;
       const int64_t cgc = cg < n2 ? cg : n2 - 4;
-      sv[it] = *reinterpret_cast<const flt4 *>(Xb + (int64_t)i3c * n2 + cgc);
+      sv[it] = *reinterpret_cast<const vec4 *>(Xb + (int64_t)i3c * n2 + cgc);
     }
 #pragma unroll
     for (int it = 0; it < SIT; ++it) {
@@ -273,14 +287,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
         const int i3 = e / Q, q = e - i3 * Q;
         const bool ok = i3 < n && c0 + 4 * q < n2;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = to_bf16_once(ok ? sv[it][t] : 0.0f);
+        for (int t = 0; t < 4; ++t) xt[(4 * q + t) * LDP + i3] = to_bf16_once(ok ? sv[it][t] : TI(0));
       }
     }
   } else {
     for (int e = threadIdx.x; e < kpad * kNB; e += NTHR) {
       const int i3 = e / kNB, c = e % kNB;
       const int64_t cg = c0 + c;
-      xt[c * LDP + i3] = to_bf16_once((i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : 0.0f);
+      xt[c * LDP + i3] = to_bf16_once((i3 < n && cg < n2) ? Xb[(int64_t)i3 * n2 + cg] : TI(0));
     }
   }
   __syncthreads();
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const float *__restrict_
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int k3 = m0 + 16 * a + 4 * lg + r;
-        if (k3 < n) Yb[(int64_t)k3 * n2 + cg] = acc[a][b][r];
+        if (k3 < n) Yb[(int64_t)k3 * n2 + cg] = store_as<TO>(acc[a][b][r]);
       }
   }
 }
@@ -351,7 +365,10 @@ void slab16(hipStream_t s, const TI *X, TO *Y, const __bf16 *W1, const __bf16 *W
   const int ncb = (n + kNB - 1) / kNB;
   const int remap = (nslab % 8 == 0) ? 1 : 0;
   const dim3 grid((unsigned)(nslab * ncb)), blk(64 * W);
-  const bool vec = n % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 31) == 0;
+  // 8-element loads: two 4-wide ones for FP64 / FP32 (n % 4 == 0, 32-byte aligned X), one
+  // 16-byte one for BF16 (n % 8 == 0, 16-byte aligned X)
+  const bool vec = sizeof(TI) == 2 ? (n % 8 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0)
+                                   : (n % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 31) == 0);
 #define FDG_SLAB16(D, V)                                                                                        \
   hipLaunchKernelGGL((k_slab16<W, M, NT, TI, TO, D, V>), grid, blk, 0, s, X, Y, W1, W2, ldw, n, nslab, ncb, remap, \
                      lam1, lam2)
@@ -376,19 +393,22 @@ void slab16_dispatch(hipStream_t s, const TI *X, TO *Y, const __bf16 *W1, const 
 #undef FDG_CASE
 }
 
-void fibre16_dispatch(hipStream_t s, const float *X, float *Y, const __bf16 *Wa, const __bf16 *Wb, int ldw, int n,
+template <typename TI, typename TO>
+void fibre16_dispatch(hipStream_t s, const TI *X, TO *Y, const __bf16 *Wa, const __bf16 *Wb, int ldw, int n,
                       int64_t batch, const float *lam1, const float *lam2, const float *lam3) {
   const Shape16 sh = pick_shape16(n, false);
   const int64_t n2 = (int64_t)n * n;
-  const bool vec = n2 % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  const bool vec = n2 % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & (4 * sizeof(TI) - 1)) == 0;
 #define FDG_CASE(W, M, T)                                                                                         \
   if (sh.waves == W && sh.mt == M && sh.nt == T) {                                                               \
     const int ncb = (int)((n2 + 16 * T - 1) / (16 * T));                                                         \
     if (vec)                                                                                                     \
-      hipLaunchKernelGGL((k_fibre16<W, M, T, true>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, Wa, Wb,  \
+      hipLaunchKernelGGL((k_fibre16<W, M, T, true, TI, TO>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, \
+                         Wa, Wb,                                                                               \
                          ldw, n, ncb, lam1, lam2, lam3);                                                         \
     else                                                                                                         \
-      hipLaunchKernelGGL((k_fibre16<W, M, T, false>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, Wa, Wb, \
+      hipLaunchKernelGGL((k_fibre16<W, M, T, false, TI, TO>), dim3((unsigned)(batch * ncb)), dim3(64 * W), 0, s, X, Y, \
+                         Wa, Wb,                                                                               \
                          ldw, n, ncb, lam1, lam2, lam3);                                                         \
     return;                                                                                                      \
   }
@@ -402,14 +422,16 @@ void launch_fd_apply_bf16(hipStream_t s, int d, int n, int64_t batch, const doub
                           float *t2, const void *const *Wv, const void *const *Wu, const float *const *lam, int ldw) {
   const __bf16 *V0 = (const __bf16 *)Wv[0], *V1 = (const __bf16 *)Wv[1];
   const __bf16 *U0 = (const __bf16 *)Wu[0], *U1 = (const __bf16 *)Wu[1];
+  __bf16 *h1 = reinterpret_cast<__bf16 *>(t1), *h2 = reinterpret_cast<__bf16 *>(t2);  // BF16 intermediates
   if (d == 3) {
     const int64_t nslab = batch * n;
-    slab16_dispatch<double, float>(s, b, t1, V0, V1, ldw, n, nslab, false, false, nullptr, nullptr);
-    fibre16_dispatch(s, t1, t2, (const __bf16 *)Wv[2], (const __bf16 *)Wu[2], ldw, n, batch, lam[0], lam[1], lam[2]);
-    slab16_dispatch<float, double>(s, t2, out, U0, U1, ldw, n, nslab, false, false, nullptr, nullptr);
+    slab16_dispatch<double, __bf16>(s, b, h1, V0, V1, ldw, n, nslab, false, false, nullptr, nullptr);
+    fibre16_dispatch<__bf16, __bf16>(s, h1, h2, (const __bf16 *)Wv[2], (const __bf16 *)Wu[2], ldw, n, batch, lam[0],
+                                     lam[1], lam[2]);
+    slab16_dispatch<__bf16, double>(s, h2, out, U0, U1, ldw, n, nslab, false, false, nullptr, nullptr);
   } else {
-    slab16_dispatch<double, float>(s, b, t1, V0, V1, ldw, n, batch, true, true, lam[0], lam[1]);
-    slab16_dispatch<float, double>(s, t1, out, U0, U1, ldw, n, batch, true, false, nullptr, nullptr);
+    slab16_dispatch<double, __bf16>(s, b, h1, V0, V1, ldw, n, batch, true, true, lam[0], lam[1]);
+    slab16_dispatch<__bf16, double>(s, h1, out, U0, U1, ldw, n, batch, true, false, nullptr, nullptr);
   }
 }
 
