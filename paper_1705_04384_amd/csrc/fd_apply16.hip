@@ -340,23 +340,33 @@ __global__ __launch_bounds__(64 * WAVES) void k_fibre16(const TI *__restrict__ X
 }
 
 // Workgroup shape: waves and 16-row tiles per wave with 16 WAVES MT >= roundup(n, 32) and
-// a multiple of 32; 16 columns per workgroup for 3D n <= 96 and the 2D solve (more
-// workgroups), 32 otherwise.
+// a multiple of 32, and 16 NT columns per workgroup: 16 for the 2D solve and 3D n <= 64
+// (more workgroups), 32 for 3D n > 192, wider in between (below).
 struct Shape16 {
   int waves, mt, nt;
 };
 
-Shape16 pick_shape16(int n, bool small_grid) {
+// 3D n in 65..192: wider column blocks, 64 columns per workgroup (128 in the slab passes
+// for n > 160), so that fewer workgroups re-read and re-round the same rows of the slab
+// (each of the ceil(n / columns) workgroups of a slab reads all of it).  Measured on
+// MI355X (BF16 apply, us, 16 or 32 columns -> these): n = 96 22.7 -> 18.6, 128 30.0 ->
+// 26.1, 160 77 -> 60.3, 192 112 -> 90.0 (64 columns in the slab passes: 96.1; 128 at
+// n = 128 and 160: 30.2 and 75.6).
+enum ShapeRole16 { kRole16Slab = 1, kRole16Fibre = 2 };
+Shape16 pick_shape16(int n, bool small_grid, int role) {
   const int nt = (small_grid || n <= 96) ? 1 : 2;
   const int k = (n + 31) / 32;
   if (k <= 2) return {4, 1, nt};
+  if (!small_grid && k <= 5) return {k <= 4 ? 2 * k : 12, 1, 4};
+  if (!small_grid && k == 6) return {12, 1, role == kRole16Slab ? 8 : 2};
   if (k <= 4) return {2 * k, 1, nt};
   if (k <= 6) return {12, 1, nt};
   return {8, 2, nt};
 }
 
-#define FDG_SHAPES16(X) \
-  X(4, 1, 1) X(6, 1, 1) X(8, 1, 1) X(12, 1, 1) X(8, 2, 1) X(4, 1, 2) X(6, 1, 2) X(8, 1, 2) X(12, 1, 2) X(8, 2, 2)
+#define FDG_SHAPES16(X)                                                                                         \
+  X(4, 1, 1) X(6, 1, 1) X(8, 1, 1) X(12, 1, 1) X(8, 2, 1) X(4, 1, 2) X(6, 1, 2) X(8, 1, 2) X(12, 1, 2) X(8, 2, 2) \
+  X(6, 1, 4) X(8, 1, 4) X(12, 1, 4) X(12, 1, 8)
 
 template <int W, int M, int NT, typename TI, typename TO>
 void slab16(hipStream_t s, const TI *X, TO *Y, const __bf16 *W1, const __bf16 *W2, int ldw, int n, int64_t nslab,
@@ -383,7 +393,7 @@ void slab16(hipStream_t s, const TI *X, TO *Y, const __bf16 *W1, const __bf16 *W
 template <typename TI, typename TO>
 void slab16_dispatch(hipStream_t s, const TI *X, TO *Y, const __bf16 *W1, const __bf16 *W2, int ldw, int n,
                      int64_t nslab, bool two_d, bool div, const float *lam1, const float *lam2) {
-  const Shape16 sh = pick_shape16(n, two_d);
+  const Shape16 sh = pick_shape16(n, two_d, kRole16Slab);
 #define FDG_CASE(W, M, T)                                                        \
   if (sh.waves == W && sh.mt == M && sh.nt == T) {                              \
     slab16<W, M, T, TI, TO>(s, X, Y, W1, W2, ldw, n, nslab, div, lam1, lam2);   \
@@ -396,7 +406,7 @@ void slab16_dispatch(hipStream_t s, const TI *X, TO *Y, const __bf16 *W1, const 
 template <typename TI, typename TO>
 void fibre16_dispatch(hipStream_t s, const TI *X, TO *Y, const __bf16 *Wa, const __bf16 *Wb, int ldw, int n,
                       int64_t batch, const float *lam1, const float *lam2, const float *lam3) {
-  const Shape16 sh = pick_shape16(n, false);
+  const Shape16 sh = pick_shape16(n, false, kRole16Fibre);
   const int64_t n2 = (int64_t)n * n;
   const bool vec = n2 % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & (4 * sizeof(TI) - 1)) == 0;
 #define FDG_CASE(W, M, T)                                                                                         \
