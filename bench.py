@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the deformed-cube and precision-sweep fields")
+    ap.add_argument("--apply-sweep", action="store_true",
+                    help="only time the FD preconditioner apply at n = 96, 128, 192 in FP64, FP32 and BF16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with 3 device copies of 256 MiB (known bytes, to scale HBM counters)")
     return ap.parse_args()
@@ -424,6 +426,51 @@ def served_headline(p, n, f, noise, X, plain_rate):
     return out
 
 
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+HBM_GBPS = 8000.0
+
+
+def fd_apply_sweep(reps=40):
+    """P^-1 apply of the unit-cube problems (3D; n = 96 p = 3, 128 p = 4, 192 p = 6) in
+    FP64, FP32 and BF16: best of three timings of `reps` back-to-back applies, against the
+    MFMA peak of the precision (12 n^4 flops per apply) and the HBM roof (bytes the three
+    fused passes move: the FP64 vector in and out and two intermediates written and read
+    back, FP64 / FP32 / BF16)."""
+    import torch
+    from paper_1705_04384_amd import fdgmres, inputs
+    out = {"workload": "P^-1 apply, 3D unit cube, collocation factors, N(0,1) input, back-to-back applies"}
+    peaks = {fdgmres.PREC_FP64: PEAK_FP64_TFLOPS, fdgmres.PREC_FP32: PEAK_FP32_TFLOPS,
+             fdgmres.PREC_BF16: PEAK_BF16_TFLOPS}
+    mid_bytes = {fdgmres.PREC_FP64: 8, fdgmres.PREC_FP32: 4, fdgmres.PREC_BF16: 2}
+    names = {fdgmres.PREC_FP64: "fp64", fdgmres.PREC_FP32: "fp32", fdgmres.PREC_BF16: "bf16"}
+    for p, n in ((3, 96), (4, 128), (6, 192)):
+        N = n ** 3
+        b = torch.from_numpy(inputs.rhs_normal(3, N)).cuda()
+        z = torch.empty_like(b)
+        row = {}
+        for prec in (fdgmres.PREC_FP64, fdgmres.PREC_FP32, fdgmres.PREC_BF16):
+            ctx = fdgmres.unit_problem(3, p, n, prec=prec)
+            for _ in range(5):
+                ctx.apply_prec(b, z)
+            torch.cuda.synchronize()
+            best = float("inf")
+            for _ in range(3):
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    ctx.apply_prec(b, z)
+                torch.cuda.synchronize()
+                best = min(best, (time.perf_counter() - t0) / reps)
+            ctx.close()
+            flops = 12 * n ** 4
+            nbytes = 16 * N + 4 * mid_bytes[prec] * N
+            row[names[prec]] = {"us": best * 1e6, "tflops": flops / best / 1e12,
+                                "frac_mfma": flops / best / 1e12 / peaks[prec], "bytes": nbytes,
+                                "frac_hbm": nbytes / best / 1e9 / HBM_GBPS}
+        out[f"n{n}_p{p}"] = row
+    return out
+
+
 def complex_pairs_apply_128(reps=20):
     """P^{-1} at n = 128 (3D) with real eigenvalues (three fused passes) against the same
     shape with complex eigenvalue pairs in every direction (2 x 2 blocks of D: fused
@@ -632,6 +679,11 @@ def main():
     if args.oracle_timing:
         print(json.dumps(oracle_timing()[0]), flush=True)
         return
+    if args.apply_sweep:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(fd_apply_sweep()), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -753,6 +805,7 @@ def main():
         out["batched_2d_p3_n33"] = batched_2d(1000)
         out["galerkin_convection_p3_n48"] = galerkin_convection_48()
         out["complex_pairs_apply_128"] = complex_pairs_apply_128()
+        out["fd_apply_sweep"] = fd_apply_sweep()
     if not args.no_serve:
         out["serving"] = serving(args.serve_requests)
     print(json.dumps(out), flush=True)
