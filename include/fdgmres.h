@@ -291,9 +291,9 @@ size_t fdg_footprint_bytes(int d, int n, int batch, int prec, int restart);
 int fdg_ctx_bytes(const fdg_ctx *ctx, size_t *held, size_t *workspace);
 
 /* Waits for the context's stream, then frees its solve and apply workspace (device
- * buffers and the host-mapped scalar slots); factors and operator stay.  The next apply,
- * matvec or solve allocates them again, so a cache of many contexts can bound the memory
- * its idle ones hold.  Requests of the context already admitted to a server are not
+ * buffers and the host-mapped scalar slots; an attached buffer is detached, not freed);
+ * factors and operator stay.  The next apply, matvec or solve allocates them again, so a
+ * cache of many contexts can bound the memory its idle ones hold.  Requests of the context already admitted to a server are not
  * affected (they use the server's arena).  FDG_EINVAL for a NULL context. */
 int fdg_release_workspace(fdg_ctx *ctx);
 
