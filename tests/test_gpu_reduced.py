@@ -82,8 +82,11 @@ def test_integer_chain_bit_for_bit(d, n):
 
 
 @pytest.mark.parametrize("d,p,n", [(3, 4, 40), (3, 3, 33), (3, 6, 65), (2, 4, 130), (2, 3, 47), (3, 5, 96),
-                                   (3, 4, 129), (3, 3, 200), (2, 2, 260)])
+                                   (3, 4, 128), (3, 4, 129), (3, 5, 144), (3, 6, 168), (3, 3, 200), (2, 2, 260)])
 def test_collocation_factors_elementwise(d, p, n):
+    # 3D BF16 workgroup shapes: 64 columns for 65 <= n <= 160 (n = 65, 96, 128, 129, 144),
+    # 128-column slab passes for 160 < n <= 192 (n = 168: a ragged second column block),
+    # 32 columns beyond (n = 200); BF16 intermediates read 8 at a time when n % 8 == 0
     Us, Vs, lams, b = _real_problem(d, p, n)
     s64 = fd.fd_apply(Us, Vs, lams, b)
     got = {}
